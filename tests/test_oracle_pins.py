@@ -1,0 +1,471 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle:
+brute force, library FFT convolution, closed forms, invariants and the
+paper's printed constants.  CPU only."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2105_06055_amd import workloads as wl
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_pairs(name):
+    out = {}
+    for line in open(os.path.join(GOLD, name)):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        parts = line.split()
+        out[parts[0]] = float(parts[1])
+    return out
+
+
+# ----------------------------------------------------------------- golden
+def test_lattice_counts(orc):
+    for line in open(os.path.join(GOLD, "lattice_counts.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        dim, m, cnt = map(int, line.split())
+        shape = (8,) * dim
+        assert len(orc.stencil(orc.geom(shape, 1e-3, m * 1e-3))) == cnt
+        # anisotropic spacing with the same physical horizon also counts by |xi| <= delta
+        g = orc.geom(shape, [1e-3, 1e-3, 1e-3][:dim], m * 1e-3)
+        assert len(orc.stencil(g)) == cnt
+
+
+def test_paper_constants(orc):
+    gold = _read_pairs("paper_constants.txt")
+    a = orc.bb_alpha(2, 72e9, 3e-3)
+    assert a == pytest.approx(gold["alpha_bb2d_E72e9_delta3e-3"], rel=1e-14)
+    # W_c = G0/delta (Eq. 51) is what the workloads feed to both sides
+    assert 3.8 / 1e-3 == pytest.approx(gold["Wc_G0_3.8_delta_1e-3"])
+    assert 3.8 / 4e-4 == pytest.approx(gold["Wc_G0_3.8_delta_4e-4"])
+    assert 3.8 / 4e-3 == pytest.approx(gold["Wc_G0_3.8_delta_4e-3"])
+
+
+def test_two_node_hand_example(orc):
+    gold = _read_pairs("two_node.txt")
+    g = orc.geom((1, 2), [1.0, 1.0], 1.5)
+    u = np.array([[[0.1, 0.4]], [[0.3, -0.2]]])
+    phi = np.ones((1, 2))
+    L = orc.bb_force(g, 2.0, phi, u)
+    W = orc.bb_energy(g, 2.0, phi, u)
+    assert L[0, 0, 0] == pytest.approx(gold["L0x"], abs=1e-15)
+    assert L[1, 0, 0] == pytest.approx(gold["L0y"], abs=1e-15)
+    assert L[0, 0, 1] == pytest.approx(gold["L1x"], abs=1e-15)
+    assert L[1, 0, 1] == pytest.approx(gold["L1y"], abs=1e-15)
+    assert W[0, 0] == pytest.approx(gold["W0"], rel=1e-14)
+    assert W[0, 1] == pytest.approx(gold["W1"], rel=1e-14)
+
+
+# --------------------------------------------------- P1: brute force / FFT
+def _wrap_disp(n, a, b):
+    d = (b - a) % n
+    return np.where(d > n // 2, d - n, d)
+
+
+def _brute_bb_periodic(shape, dx, delta, alpha, phi, u):
+    """All-pairs loop over the periodic box with minimum-image bond vectors."""
+    dim = len(shape)
+    coords = np.array(np.unravel_index(np.arange(phi.size), shape)).T  # (N, dim) in (z,y,x) order
+    N = phi.size
+    L = np.zeros((dim, N))
+    pf = phi.ravel()
+    uf = u.reshape(dim, N)
+    for a in range(N):
+        if pf[a] == 0:
+            continue
+        dxyz = np.stack([_wrap_disp(shape[k], coords[a, k], coords[:, k]) for k in range(dim)], 1)
+        xi = dxyz[:, ::-1] * dx  # to (x, y[, z]) component order
+        r2 = (xi ** 2).sum(1)
+        sel = (r2 > 0) & (r2 <= delta ** 2 * (1 + 1e-10))
+        xi, r2 = xi[sel], r2[sel]
+        idx = np.nonzero(sel)[0]
+        eta = uf[:, idx].T - uf[:, a]
+        c = alpha / np.sqrt(r2) / r2 * pf[idx] * dx ** dim
+        L[:, a] = pf[a] * ((c * (xi * eta).sum(1))[:, None] * xi).sum(0)
+    return L.reshape(u.shape)
+
+
+def _fft_bb_periodic(shape, dx, delta, alpha, phi, u):
+    """Circular convolution by numpy.fft of wrap-around kernel arrays."""
+    dim = len(shape)
+    grids = np.meshgrid(*[np.fft.fftfreq(n, 1.0 / n) for n in shape], indexing="ij")
+    offs = [g.astype(float) for g in grids][::-1]  # x, y[, z] integer offsets
+    xi = [o * dx for o in offs]
+    r2 = sum(x ** 2 for x in xi)
+    inside = (r2 > 0) & (r2 <= delta ** 2 * (1 + 1e-10))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        base = np.where(inside, alpha / np.sqrt(r2) / r2 * dx ** dim, 0.0)
+    # correlation: (K * g)(x) = sum_o K(o) g(x + o) -> FFT: conj(F(K)) F(g) for real K
+    out = np.zeros_like(u)
+    for i in range(dim):
+        for j in range(dim):
+            K = base * xi[i] * xi[j]
+            Kh = np.conj(np.fft.fftn(K))
+            conv = np.real(np.fft.ifftn(Kh * np.fft.fftn(phi * u[j])))
+            P = np.real(np.fft.ifftn(Kh * np.fft.fftn(phi)))
+            out[i] += phi * (conv - P * u[j])
+    return out
+
+
+@pytest.mark.parametrize("shape", [(9, 11), (8, 7, 9)])
+def test_p1_bb_bruteforce_and_fft(orc, shape):
+    dim = len(shape)
+    dx, delta = 1e-3, 3e-3 if dim == 2 else 2.2e-3
+    rng = np.random.default_rng(11)
+    phi = rng.uniform(0.5, 1.5, size=shape) * (rng.random(shape) > 0.2)
+    u = rng.normal(size=(dim,) + shape)
+    alpha = 1e18
+    g = orc.geom(shape, dx, delta, periodic=True)
+    L = orc.bb_force(g, alpha, phi, u)
+    Lb = _brute_bb_periodic(shape, dx, delta, alpha, phi, u)
+    Lf = _fft_bb_periodic(shape, dx, delta, alpha, phi, u)
+    scale = np.abs(Lb).max()
+    assert np.abs(L - Lb).max() <= 1e-13 * scale
+    assert np.abs(L - Lf).max() <= 1e-12 * scale
+
+
+def test_p1_lps_bruteforce(orc):
+    """LPS dilatation and force against an all-pairs periodic loop."""
+    shape = (7, 8, 9)
+    dx, delta, E, nu = 1e-3, 2.2e-3, 1e11, 0.4
+    rng = np.random.default_rng(5)
+    chi = (rng.random(shape) > 0.25).astype(float)
+    u = rng.normal(size=(3,) + shape)
+    g = orc.geom(shape, dx, delta, periodic=True)
+    L, th = orc.lps_force(g, E, nu, chi, u)
+    N = chi.size
+    coords = np.array(np.unravel_index(np.arange(N), shape)).T
+    cf, uf = chi.ravel(), u.reshape(3, N)
+    bonds = []
+    for a in range(N):
+        d = np.stack([_wrap_disp(shape[k], coords[a, k], coords[:, k]) for k in range(3)], 1)
+        xi = d[:, ::-1] * dx
+        r2 = (xi ** 2).sum(1)
+        sel = np.nonzero((r2 > 0) & (r2 <= delta ** 2 * (1 + 1e-10)))[0]
+        bonds.append((sel, xi[sel], r2[sel]))
+    dV = dx ** 3
+    # full-horizon weighted volume from an explicit lattice enumeration
+    m0 = sum(np.sqrt(r2).sum() for r2 in [bonds[0][2]]) * dV  # omega r^2 = r for omega = 1/r
+    kappa, mu = E / (3 * (1 - 2 * nu)), E / (2 * (1 + nu))
+    thb = np.zeros(N)
+    for a in range(N):
+        sel, xi, r2 = bonds[a]
+        w = cf[sel] / np.sqrt(r2) * dV
+        m = cf[a] * (w * r2).sum()
+        e = (xi * (uf[:, sel].T - uf[:, a])).sum(1)
+        thb[a] = 3 * cf[a] / m * (w * e).sum() if (cf[a] and m) else 0.0
+    Lb = np.zeros((3, N))
+    for a in range(N):
+        if not cf[a]:
+            continue
+        sel, xi, r2 = bonds[a]
+        w = cf[sel] / np.sqrt(r2) * dV
+        e = (xi * (uf[:, sel].T - uf[:, a])).sum(1)
+        f = ((3 * kappa - 5 * mu) / m0 * w * (thb[a] + thb[sel]))[:, None] * xi \
+            + (30 * mu / m0 * w * e / r2)[:, None] * xi
+        Lb[:, a] = f.sum(0)
+    assert np.abs(th.ravel() - thb).max() <= 1e-13 * np.abs(thb).max()
+    assert np.abs(L.reshape(3, N) - Lb).max() <= 1e-13 * np.abs(Lb).max()
+
+
+# ----------------------------------------------------------- P2: affine
+@pytest.mark.parametrize("model", ["bb2", "bb3", "lps"])
+def test_p2_affine_interior_zero(orc, model):
+    dim = 2 if model == "bb2" else 3
+    shape = (20, 22) if dim == 2 else (14, 15, 16)
+    m = 3 if dim == 2 else 2
+    dx = 1e-3
+    delta = m * dx
+    rng = np.random.default_rng(3)
+    A = rng.normal(size=(dim, dim)) * 1e-3
+    cvec = rng.normal(size=dim) * 1e-6
+    X = np.stack(np.meshgrid(*[(np.arange(n) + 0.5) * dx for n in shape], indexing="ij")[::-1])
+    u = np.einsum("ij,j...->i...", A, X) + cvec.reshape((dim,) + (1,) * dim)
+    g = orc.geom(shape, dx, delta)
+    chi = np.ones(shape)
+    if model == "lps":
+        L, th = orc.lps_force(g, 2e11, 0.4, chi, u)
+        depth = 2 * m
+    else:
+        L = orc.bb_force(g, orc.bb_alpha(dim, 72e9, delta), chi, u)
+        depth = m
+    inner = tuple(slice(depth, n - depth) for n in shape)
+    Lmag = np.abs(L).max()
+    assert Lmag > 0  # the boundary layer does feel the deformation
+    assert np.abs(L[(slice(None),) + inner]).max() <= 1e-11 * Lmag
+    if model == "lps":
+        inner1 = tuple(slice(m, n - m) for n in shape)
+        assert np.allclose(th[inner1], np.trace(A), rtol=1e-12, atol=0)
+
+
+# -------------------------------------------------------- P3: quadratic
+def _moments(offs, dx, dim, alpha):
+    xi = offs[:, :dim] * dx
+    r2 = (xi ** 2).sum(1)
+    c = alpha / np.sqrt(r2) / r2 * dx ** dim
+    return np.einsum("s,si,sj,sk,sl->ijkl", c, xi, xi, xi, xi)
+
+
+@pytest.mark.parametrize("dim,m", [(2, 3), (3, 3)])
+def test_p3_quadratic_moments_and_navier(orc, dim, m):
+    dx = 1e-3
+    delta = m * dx
+    E = 72e9
+    shape = (24, 26) if dim == 2 else (16, 16, 17)
+    rng = np.random.default_rng(7)
+    H = rng.normal(size=(dim, dim, dim))
+    H = 0.5 * (H + H.transpose(0, 2, 1))  # u_j = 1/2 H_jkl x_k x_l
+    X = np.stack(np.meshgrid(*[(np.arange(n) + 0.5) * dx for n in shape], indexing="ij")[::-1])
+    u = 0.5 * np.einsum("jkl,k...,l...->j...", H, X, X)
+    g = orc.geom(shape, dx, delta)
+    alpha = orc.bb_alpha(dim, E, delta)
+    L = orc.bb_force(g, alpha, np.ones(shape), u)
+    inner = tuple(slice(m + 1, n - m - 1) for n in shape)
+    Li = L[(slice(None),) + inner].reshape(dim, -1)
+    M = _moments(orc.stencil(g).astype(float), dx, dim, alpha)
+    expect = 0.5 * np.einsum("ijkl,jkl->i", M, H)
+    assert np.abs(Li - expect[:, None]).max() <= 1e-9 * np.abs(expect).max()
+    # continuum Navier operator: mu lap u + (lam + mu) grad div u, lam = mu
+    lam = 3 * E / 8 if dim == 2 else 2 * E / 5
+    lap = np.einsum("jkk->j", H)
+    graddiv = np.einsum("kki->i", H)
+    navier = lam * lap + 2 * lam * graddiv
+    # discrete fourth moments differ from the continuum by quadrature error
+    # (no partial-volume correction, Sec. 4.1.1): a few percent at m = 3
+    rel = np.abs(expect - navier).max() / np.abs(navier).max()
+    assert rel < (0.07 if dim == 2 else 0.25)
+    # and the calibration converges as the grid is refined under a fixed horizon
+    if dim == 2:
+        g8 = orc.geom((40, 40), dx / 4, delta)
+        M8 = _moments(orc.stencil(g8).astype(float), dx / 4, dim, alpha)
+        rel8 = np.abs(0.5 * np.einsum("ijkl,jkl->i", M8, H) - navier).max() / np.abs(navier).max()
+        assert rel8 < rel and rel8 < 0.05
+
+
+# ----------------------------------------------- P4/P5/P6: invariants
+@pytest.mark.parametrize("model", ["bb2", "bb3", "lps"])
+def test_p4_p5_p6_symmetry_balance_energy(orc, model):
+    dim = 2 if model == "bb2" else 3
+    shape = (17, 19) if dim == 2 else (10, 11, 12)
+    dx = 1e-3
+    delta = 3 * dx if dim == 2 else 2 * dx
+    rng = np.random.default_rng(21)
+    chi = wl.random_mask(shape, 5).astype(float)
+    u = rng.normal(size=(dim,) + shape)
+    v = rng.normal(size=(dim,) + shape)
+    g = orc.geom(shape, dx, delta)
+    if model == "lps":
+        op = lambda f: orc.lps_force(g, 1e11, 0.4, chi, f)[0]
+        phi = chi
+    else:
+        phi = chi * rng.uniform(0.5, 1.5, size=shape)
+        alpha = orc.bb_alpha(dim, 72e9, delta)
+        op = lambda f: orc.bb_force(g, alpha, phi, f)
+    Lu, Lv = op(u), op(v)
+    a, b = (Lu * v).sum(), (u * Lv).sum()
+    assert abs(a - b) <= 1e-13 * np.sqrt((Lu ** 2).sum() * (v ** 2).sum())
+    # zero net force and torque (all bond forces are central and pairwise)
+    tot = Lu.reshape(dim, -1).sum(1)
+    assert np.abs(tot).max() <= 1e-12 * np.abs(Lu).sum()
+    X = np.stack(np.meshgrid(*[(np.arange(n) + 0.5) * dx for n in shape], indexing="ij")[::-1])
+    if dim == 2:
+        torque = (X[0] * Lu[1] - X[1] * Lu[0]).sum()
+    else:
+        torque = np.cross(X.reshape(3, -1).T, Lu.reshape(3, -1).T).sum(0)
+    assert np.abs(torque).max() <= 1e-12 * (np.abs(X).max() * np.abs(Lu).sum())
+    assert (u * Lu).sum() < 0
+    if model != "lps":
+        W = orc.bb_energy(g, alpha, phi, u)
+        assert W.sum() == pytest.approx(-(u * Lu).sum(), rel=1e-12)
+
+
+# ------------------------------------------------ P7: shadow energy
+def test_p7_verlet_shadow_energy(orc):
+    shape = (12, 14)
+    dx, delta = 1e-3, 3e-3
+    rng = np.random.default_rng(8)
+    chi = wl.random_mask(shape, 2)
+    g = orc.geom(shape, dx, delta)
+    alpha = orc.bb_alpha(2, 72e9, delta)
+    mdl = orc.model("bb", E=72e9, alpha=alpha, rho=2440.0)
+    u0 = rng.normal(0, 1e-6, size=(2,) + shape) * chi
+    v0 = rng.normal(0, 1e-2, size=(2,) + shape) * chi
+    out = orc.verlet(g, mdl, chi, np.stack([chi, chi]), u0, v0, dt=5e-8, nsteps=200, energy=True)
+    en = out["energy"]
+    H = en[:, 3]
+    E_plain = en[:, 0] + en[:, 1] + en[:, 2]
+    assert np.abs(H - H[0]).max() <= 1e-11 * abs(H[0])
+    assert np.abs(E_plain - E_plain[0]).max() > 1e3 * np.abs(H - H[0]).max()
+
+
+# --------------------------------------------------- P8: plane wave
+@pytest.mark.parametrize("dim", [2, 3])
+def test_p8_plane_wave_multiplier(orc, dim):
+    shape = (16, 12) if dim == 2 else (10, 8, 12)
+    dx, delta = 1e-3, 3e-3 if dim == 2 else 2e-3
+    k = np.array([3, 2, 1][:dim])  # (x, y[, z]) wavenumbers
+    e = np.array([0.3, -0.7, 0.2][:dim])
+    n_xyz = np.array(shape[::-1])
+    I = np.stack(np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")[::-1])
+    phase = 2 * np.pi * sum(k[d] * I[d] / n_xyz[d] for d in range(dim))
+    u = e.reshape((dim,) + (1,) * dim) * np.cos(phase)
+    g = orc.geom(shape, dx, delta, periodic=True)
+    alpha = 2e18
+    L = orc.bb_force(g, alpha, np.ones(shape), u)
+    # independent lattice sum of the multiplier over |o| <= delta
+    R = int(np.ceil(delta / dx))
+    Mk = np.zeros((dim, dim))
+    for o in np.ndindex(*([2 * R + 1] * dim)):
+        o = np.array(o) - R
+        xi = o * dx
+        r2 = (xi ** 2).sum()
+        if r2 == 0 or r2 > delta ** 2 * (1 + 1e-10):
+            continue
+        C = alpha / np.sqrt(r2) * np.outer(xi, xi) / r2 * dx ** dim
+        Mk += C * (1 - np.cos(2 * np.pi * (k * o / n_xyz).sum()))
+    expect = -(Mk @ e).reshape((dim,) + (1,) * dim) * np.cos(phase)
+    assert np.abs(L - expect).max() <= 1e-12 * np.abs(expect).max()
+
+
+# ------------------------------------------------------ P9: reductions
+def test_p9_lps_quarter_equals_bb(orc):
+    shape = (9, 10, 11)
+    dx, delta, E = 1e-3, 2e-3, 1e11
+    rng = np.random.default_rng(9)
+    chi = wl.random_mask(shape, 9).astype(float)
+    u = rng.normal(size=(3,) + shape)
+    g = orc.geom(shape, dx, delta)
+    L, _ = orc.lps_force(g, E, 0.25, chi, u)
+    mu = E / (2 * 1.25)
+    Lb = orc.bb_force(g, 30 * mu / orc.m0(g), chi, u)
+    assert np.abs(L - Lb).max() <= 1e-12 * np.abs(Lb).max()
+    # unit weights reproduce the plain mask
+    lam = np.ones(shape, np.uint8)
+    d, cnt = orc.damage_index(g, chi.astype(np.uint8), lam)
+    assert np.all(d == 0)
+
+
+# ------------------------------------------------------ P10: statics
+@pytest.mark.parametrize("model", ["bb", "lps"])
+def test_p10_static_cg_dense(orc, model):
+    dim = 2 if model == "bb" else 3
+    shape = (10, 12) if dim == 2 else (6, 6, 7)
+    dx = 1e-3
+    delta = 3 * dx if dim == 2 else 2 * dx
+    rng = np.random.default_rng(10)
+    chi = np.ones(shape, np.uint8)
+    chiO = np.stack([chi] * dim).copy()
+    chiO[:, :2] = 0  # clamp two layers along the slowest axis
+    b = rng.uniform(-1, 1, size=(dim,) + shape) * 1e8 * chiO
+    w = np.zeros_like(b)
+    w[:, :2] = rng.normal(size=(dim, 2) + shape[1:]) * 1e-7
+    g = orc.geom(shape, dx, delta)
+    if model == "bb":
+        mdl = orc.model("bb", E=72e9, alpha=orc.bb_alpha(2, 72e9, delta))
+        op = lambda f: orc.bb_force(g, mdl.alpha, chi.astype(float), f)
+    else:
+        mdl = orc.model("lps", E=2e11, nu=0.4)
+        op = lambda f: orc.lps_force(g, 2e11, 0.4, chi.astype(float), f)[0]
+    u, it, rr = orc.static_cg(g, mdl, chi, chiO, b, w=w, rtol=1e-12, maxit=5000)
+    assert rr <= 1e-12
+    # dense assembly of L by unit vectors, then numpy.linalg.solve
+    n = b.size
+    Lmat = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        Lmat[:, j] = op(e.reshape(b.shape)).ravel()
+    om = chiO.ravel().astype(bool)
+    A = -Lmat[np.ix_(om, om)]
+    rhs = (b.ravel() + Lmat[:, ~om] @ w.ravel()[~om])[om]
+    y = np.linalg.solve(A, rhs)
+    ud = w.ravel().copy()
+    ud[om] = y
+    assert np.abs(u.ravel() - ud).max() <= 1e-9 * np.abs(ud).max()
+
+
+# ----------------------------------------------------- P11: damage
+def test_p11_damage_closed_forms(orc):
+    shape = (40, 30)
+    dx, m = 1e-3, 3
+    g = orc.geom(shape, dx, m * dx)
+    chi = np.ones(shape, np.uint8)
+    lam = np.ones(shape, np.uint8)
+    d, _ = orc.damage_index(g, chi, lam)
+    assert np.all(d == 0)
+    # a planted through crack: a delta-thick layer of failed nodes (Sec. 3.4.3)
+    lam[18:18 + m, :] = 0
+    d, _ = orc.damage_index(g, chi, lam)
+    assert np.all(d[18:18 + m] == 1.0)
+    flank = np.concatenate([d[18 - m:18, m:-m], d[18 + m:18 + 2 * m, m:-m]])
+    assert np.all(flank > 0) and np.all(flank < 0.5)
+    far = np.concatenate([d[:18 - m], d[18 + 2 * m:]])
+    assert np.all(far == 0)
+
+
+# ----------------------------------------------------- P12: adjoint
+def test_p12_force_adjoint_fd(orc):
+    shape = (11, 13)
+    dx, delta = 1e-3, 3e-3
+    rng = np.random.default_rng(12)
+    chi = wl.random_mask(shape, 12)
+    s = rng.uniform(0.7, 1.3, size=shape)
+    phi = chi * s
+    u = rng.normal(size=(2,) + shape)
+    gb = rng.normal(size=(2,) + shape)
+    g = orc.geom(shape, dx, delta)
+    alpha = 1.0
+    ub, pb = orc.bb_force_adjoint(g, alpha, phi, u, gb)
+    # transpose test for u
+    du = rng.normal(size=u.shape)
+    lhs = (gb * orc.bb_force(g, alpha, phi, du)).sum()
+    assert lhs == pytest.approx((ub * du).sum(), rel=1e-12)
+    # the functional is quadratic in phi: central differences are exact
+    dphi = rng.normal(size=shape) * chi
+    J = lambda p: (gb * orc.bb_force(g, alpha, p, u)).sum()
+    eps = 1e-3
+    fd = (J(phi + eps * dphi) - J(phi - eps * dphi)) / (2 * eps)
+    assert (pb * dphi).sum() == pytest.approx(fd, rel=1e-9)
+
+
+def test_p12_verlet_adjoint_fd(orc):
+    shape = (9, 10)
+    dx, delta = 1e-3, 3e-3
+    rng = np.random.default_rng(13)
+    chi = np.ones(shape, np.uint8)
+    chiO = np.stack([chi, chi]).copy()
+    chiO[:, 0] = 0
+    s = rng.uniform(0.8, 1.2, size=shape)
+    alpha = orc.bb_alpha(2, 72e9, delta)
+    rho, dt, nsteps = 2440.0, 2e-8, 12
+    g = orc.geom(shape, dx, delta)
+    mdl = orc.model("bb", E=72e9, alpha=alpha, rho=rho)
+    u0 = rng.normal(0, 1e-7, size=(2,) + shape) * chiO
+    v0 = rng.normal(0, 1.0, size=(2,) + shape) * chiO
+    b = rng.normal(0, 1e7, size=(2,) + shape)
+    target = rng.normal(0, 1e-7, size=(2,) + shape)
+
+    def loss(u_init, v_init, s_):
+        o = orc.verlet(g, mdl, chi, chiO, u_init, v_init, dt, nsteps, b=b, s=s_)
+        return ((o["u"] - target) ** 2).sum(), o
+
+    J0, o = loss(u0, v0, s)
+    ubT = 2 * (o["u"] - target)
+    ub0, vb0, pb = orc.verlet_adjoint(g, alpha, rho, chiO, chi * s, b, u0, v0, dt, nsteps,
+                                      ubT, np.zeros_like(ubT))
+    du = rng.normal(size=u0.shape) * chiO * 1e-7
+    eps = 1e-2
+    fd = (loss(u0 + eps * du, v0, s)[0] - loss(u0 - eps * du, v0, s)[0]) / (2 * eps)
+    assert (ub0 * du).sum() == pytest.approx(fd, rel=1e-8)
+    dv = rng.normal(size=v0.shape) * chiO
+    fd = (loss(u0, v0 + eps * dv, s)[0] - loss(u0, v0 - eps * dv, s)[0]) / (2 * eps)
+    assert (vb0 * dv).sum() == pytest.approx(fd, rel=1e-8)
+    ds = rng.normal(size=shape)
+    eps = 1e-5
+    fd = (loss(u0, v0, s + eps * ds)[0] - loss(u0, v0, s - eps * ds)[0]) / (2 * eps)
+    # phibar is the cotangent of phi = chi s; chi = 1 here
+    assert (pb * ds).sum() == pytest.approx(fd, rel=1e-6)
