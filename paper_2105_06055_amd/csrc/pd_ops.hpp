@@ -1,0 +1,517 @@
+// pd_ops.hpp -- per-node input generators, spectral multipliers and
+// assembly epilogues of the FCBM-EC convolution chains.
+//
+// Every chain evaluates sums of the form (paper Eq. 13-14, 45)
+//     sum_n a_n(x) [c_n (*) b_n](x)
+// as: generator  -> b_n(x') on the body box (zero on the padding)
+//     multiplier -> per wavenumber, combines F(b_n) with the kernel spectra
+//     epilogue   -> a_n(x) times the convolutions, plus pointwise terms.
+// Convolutions are correlations (K (*) g)(x) = sum_o K(o) g(x + o) over the
+// horizon stencil, which is what the bond sums of Eq. 55 are; their
+// multiplier is sum_o K(o) e^{+2 pi i k.o/n}.  The volume dV and the 1/N of
+// the inverse DFT are folded into the kernel partial spectra (taps).
+//
+// Kernel component order inside a plan:
+//   bond-based: C_ij (i <= j, sym index), then omega_0 (integrity plans)
+//   LPS       : C_ij (6), then a0_i = omega xi_i (3)          [taps]
+//               plus omega r^2 (static fields only)
+// C_ij is even in every axis except i and j, a0_i is odd in axis i; a
+// component odd in P axes has the multiplier i^P * (real sum).
+#pragma once
+
+#include <stdint.h>
+
+#include "pd_fft.hpp"
+
+namespace pdk {
+
+__host__ __device__ constexpr int nsym(int D) { return D * (D + 1) / 2; }
+__host__ __device__ constexpr int symi(int D, int i, int j) {
+    return (i <= j) ? (i * D - (i * (i - 1)) / 2 + (j - i)) : (j * D - (j * (j - 1)) / 2 + (i - j));
+}
+
+// Weight kinds (match pd_weight_kind).
+enum { WK_NONE = 0, WK_LAMBDA = 1, WK_SCALE = 2 };
+
+// ----------------------------------------------------------------------------
+// Node context shared by generators and epilogues.
+template <class T>
+struct NodeCtx {
+    long nb;                   // body nodes
+    const uint8_t* chiB;       // [nb]
+    const uint8_t* chiO;       // [D][nb]
+    const T* stat;             // static fields [ncs][nb]
+};
+
+// Bond weight phi(x) = chi_B [lambda | s].
+template <class T, int WK>
+__device__ __forceinline__ T node_phi(const NodeCtx<T>& c, long i, const uint8_t* lam, const T* s) {
+    T p = c.chiB[i] ? T(1) : T(0);
+    if constexpr (WK == WK_LAMBDA) p = lam[i] ? p : T(0);
+    if constexpr (WK == WK_SCALE) p *= s[i];
+    return p;
+}
+
+// ============================================================================
+// Generators: gen(i, in[NIN]) for a body node i.
+// ============================================================================
+
+// Bond-based / LPS displacement inputs:  phi u_j  [, phi]  [, phi u_i u_j].
+// VV = 1 first applies the embedded-constraint position update (Eq. 83)
+//     u <- chi_O [u + dt v + c2 F] + (1 - chi_O) w   (written back to u)
+// and, for integrity weights with failure on, lambda <- lambda && W <= Wc
+// (Eq. 63, irreversible), written back to lambda.
+template <class T, int D, int WK, bool WPHI, bool ENERGY, bool VV>
+struct GenU {
+    static constexpr int NIN = D + (WPHI ? 1 : 0) + (ENERGY ? nsym(D) : 0);
+    NodeCtx<T> c;
+    T* u;                      // [D][nb] (updated in place when VV)
+    const uint8_t* lam_in;     // integrity
+    uint8_t* lam_out;          // VV + failure: updated integrity
+    const T* s;                // scale weight
+    const T* v; const T* F; const T* w; const T* W;
+    T dt, c2, Wc;
+    int fail;                  // VV: apply the failure rule
+    __device__ __forceinline__ void gen(long i, T (&in)[NIN]) const {
+        T ud[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            T x = u[d * c.nb + i];
+            if constexpr (VV) {
+                const long k = d * c.nb + i;
+                x = c.chiO[k] ? x + dt * v[k] + c2 * F[k] : (w ? w[k] : T(0));
+                u[k] = x;
+            }
+            ud[d] = x;
+        }
+        T phi;
+        if constexpr (VV && WK == WK_LAMBDA) {
+            uint8_t l = lam_in[i];
+            if (fail) {
+                l = (l && W[i] <= Wc) ? 1 : 0;
+                lam_out[i] = l;
+            }
+            phi = (c.chiB[i] && l) ? T(1) : T(0);
+        } else {
+            phi = node_phi<T, WK>(c, i, lam_in, s);
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) in[d] = phi * ud[d];
+        int o = D;
+        if constexpr (WPHI) in[o++] = phi;
+        if constexpr (ENERGY) {
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int b = a; b < D; ++b) in[o + symi(D, a, b)] = phi * ud[a] * ud[b];
+        }
+    }
+};
+
+// LPS stage B input: chi_B theta.
+template <class T>
+struct GenTheta {
+    static constexpr int NIN = 1;
+    NodeCtx<T> c;
+    const T* theta;
+    __device__ __forceinline__ void gen(long i, T (&in)[1]) const {
+        in[0] = c.chiB[i] ? theta[i] : T(0);
+    }
+};
+
+// Damage count input: chi_B lambda.
+template <class T>
+struct GenPhi {
+    static constexpr int NIN = 1;
+    NodeCtx<T> c;
+    const uint8_t* lam;
+    __device__ __forceinline__ void gen(long i, T (&in)[1]) const {
+        in[0] = (c.chiB[i] && lam[i]) ? T(1) : T(0);
+    }
+};
+
+// Weighted bond-based adjoint inputs: phi u_j, phi, phi g_i, and
+// phi (g_i u_j + g_j u_i) for i < j, phi g_i u_i on the diagonal.
+template <class T, int D, int WK>
+struct GenAdj {
+    static constexpr int NIN = 2 * D + 1 + nsym(D);
+    NodeCtx<T> c;
+    const T* u; const T* u2; const T* g; const uint8_t* lam; const T* s;
+    __device__ __forceinline__ void gen(long i, T (&in)[NIN]) const {
+        T phi = node_phi<T, WK>(c, i, lam, s);
+        T ud[D], gd[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            ud[d] = u[d * c.nb + i] + (u2 ? u2[d * c.nb + i] : T(0));
+            gd[d] = g[d * c.nb + i];
+            in[d] = phi * ud[d];
+            in[D + 1 + d] = phi * gd[d];
+        }
+        in[D] = phi;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = a; b < D; ++b)
+                in[2 * D + 1 + symi(D, a, b)] = (a == b) ? phi * gd[a] * ud[a]
+                                                         : phi * (gd[a] * ud[b] + gd[b] * ud[a]);
+    }
+};
+
+// Plain scalar field (tests).
+template <class T>
+struct GenScalar {
+    static constexpr int NIN = 1;
+    const T* x;
+    __device__ __forceinline__ void gen(long i, T (&in)[1]) const { in[0] = x[i]; }
+};
+
+// ============================================================================
+// Multipliers: mul(K, kz, in, out); K[c] is the real kernel sum of component
+// C0 + c at this wavenumber.
+// ============================================================================
+
+template <class T>
+__device__ __forceinline__ cx<T> kmul(T k, cx<T> a) { return {k * a.r, k * a.i}; }
+// multiply by i k
+template <class T>
+__device__ __forceinline__ cx<T> kmuli(T k, cx<T> a) { return {-k * a.i, k * a.r}; }
+
+// Bond-based: conv_i = sum_j M[C_ij] U_j; [G_c = M[C_c] Phi]; [E = sum_c m_c M[C_c] F_c]
+// with M[C_ij] = K (i == j) or -K (i != j: two odd axes, i^2 = -1).
+template <class T, int D, bool WPHI, bool ENERGY>
+struct MulBB {
+    static constexpr int NIN = D + (WPHI ? 1 : 0) + (ENERGY ? nsym(D) : 0);
+    static constexpr int NOUT = D + (WPHI ? nsym(D) : 0) + (ENERGY ? 1 : 0);
+    static constexpr int C0 = 0, NC = nsym(D);
+    __device__ __forceinline__ void mul(const T* K, int, const cx<T>* in, cx<T>* out) const {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            cx<T> acc = {T(0), T(0)};
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                T k = (i == j) ? K[symi(D, i, j)] : -K[symi(D, i, j)];
+                acc = acc + kmul(k, in[j]);
+            }
+            out[i] = acc;
+        }
+        int o = D;
+        if constexpr (WPHI) {
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int b = a; b < D; ++b) {
+                    T k = (a == b) ? K[symi(D, a, b)] : -K[symi(D, a, b)];
+                    out[o + symi(D, a, b)] = kmul(k, in[D]);
+                }
+            o += nsym(D);
+        }
+        if constexpr (ENERGY) {
+            const int ib = D + (WPHI ? 1 : 0);
+            cx<T> acc = {T(0), T(0)};
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int b = a; b < D; ++b) {
+                    T k = (a == b) ? K[symi(D, a, b)] : -T(2) * K[symi(D, a, b)];
+                    acc = acc + kmul(k, in[ib + symi(D, a, b)]);
+                }
+            out[o] = acc;
+        }
+    }
+};
+
+// LPS dilatation convolution: S = sum_i M[a0_i] U_i, M[a0_i] = i K.
+template <class T>
+struct MulLPSA {
+    static constexpr int NIN = 3, NOUT = 1, C0 = 6, NC = 3;
+    __device__ __forceinline__ void mul(const T* K, int, const cx<T>* in, cx<T>* out) const {
+        cx<T> acc = kmuli(K[0], in[0]);
+        acc = acc + kmuli(K[1], in[1]);
+        acc = acc + kmuli(K[2], in[2]);
+        out[0] = acc;
+    }
+};
+
+// LPS force convolutions: conv_i = sum_j M[C_ij] U_j + k_a M[a0_i] Theta.
+template <class T>
+struct MulLPSB {
+    static constexpr int NIN = 4, NOUT = 3, C0 = 0, NC = 9;
+    T ka;
+    __device__ __forceinline__ void mul(const T* K, int, const cx<T>* in, cx<T>* out) const {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            cx<T> acc = kmuli(ka * K[6 + i], in[3]);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                T k = (i == j) ? K[symi(3, i, j)] : -K[symi(3, i, j)];
+                acc = acc + kmul(k, in[j]);
+            }
+            out[i] = acc;
+        }
+    }
+};
+
+// Damage count: omega_0 (*) (chi_B lambda) over the bonds (centre excluded).
+template <class T, int D>
+struct MulCount {
+    static constexpr int NIN = 1, NOUT = 1, C0 = nsym(D), NC = 1;
+    __device__ __forceinline__ void mul(const T* K, int, const cx<T>* in, cx<T>* out) const {
+        out[0] = kmul(K[0], in[0]);
+    }
+};
+
+// Weighted bond-based adjoint: conv_i (D), G_c (nsym), cg_i = C (*) phi g (D),
+// E' = sum_c M[C_c] F(s_c) (1).
+template <class T, int D>
+struct MulAdj {
+    static constexpr int NIN = 2 * D + 1 + nsym(D);
+    static constexpr int NOUT = 2 * D + nsym(D) + 1;
+    static constexpr int C0 = 0, NC = nsym(D);
+    __device__ __forceinline__ void mul(const T* K, int, const cx<T>* in, cx<T>* out) const {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            cx<T> a = {T(0), T(0)}, b = {T(0), T(0)};
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                T k = (i == j) ? K[symi(D, i, j)] : -K[symi(D, i, j)];
+                a = a + kmul(k, in[j]);
+                b = b + kmul(k, in[D + 1 + j]);
+            }
+            out[i] = a;
+            out[D + nsym(D) + i] = b;
+        }
+        cx<T> e = {T(0), T(0)};
+#pragma unroll
+        for (int p = 0; p < D; ++p)
+#pragma unroll
+            for (int q = p; q < D; ++q) {
+                T k = (p == q) ? K[symi(D, p, q)] : -K[symi(D, p, q)];
+                out[D + symi(D, p, q)] = kmul(k, in[D]);
+                e = e + kmul(k, in[2 * D + 1 + symi(D, p, q)]);
+            }
+        out[2 * D + nsym(D)] = e;
+    }
+};
+
+// Test multiplier: a single kernel component odd in P axes, i^P K.
+template <class T>
+struct MulTest {
+    static constexpr int NIN = 1, NOUT = 1, C0 = 0, NC = 1;
+    int P;
+    __device__ __forceinline__ void mul(const T* K, int, const cx<T>* in, cx<T>* out) const {
+        out[0] = mul_ipow(kmul(K[0], in[0]), P);
+    }
+};
+
+// ============================================================================
+// Epilogues: fin(i, val[NOUT], red[NRED]).  val are the (normalised)
+// convolutions at node i.
+// ============================================================================
+
+// Bond-based force / Verlet finish.
+//   L_i = phi (conv_i - sum_j G_ij u_j)          (Eq. 18, 46, 100 with weights)
+//   W   = 1/2 phi (E - 2 u_j conv_j + u_i u_j G_ij) (Eq. 47, 102)
+// G is the static chi_B field (WPHI = false) or comes from the chain.
+// VV: F' = L + b, v <- chi_O [v + c1 (F + F')]  (Eq. 84); optional energy
+// partial sums (KE, PE, EXT, |chi_O F'|^2).
+template <class T, int D, int WK, bool WPHI, bool ENERGY, bool VV, bool ENRED>
+struct FinBB {
+    static constexpr int NOUT = D + (WPHI ? nsym(D) : 0) + (ENERGY ? 1 : 0);
+    static constexpr int NRED = ENRED ? 4 : 0;
+    NodeCtx<T> c;
+    const T* u; const uint8_t* lam; const T* s;
+    T* L; T* Wout;
+    T* v; T* F; const T* b;   // VV
+    T c1, rho;
+    __device__ __forceinline__ void fin(long i, const T (&val)[NOUT], double* red) const {
+        T phi = node_phi<T, WK>(c, i, lam, s);
+        T ud[D], Gm[nsym(D)];
+#pragma unroll
+        for (int d = 0; d < D; ++d) ud[d] = u[d * c.nb + i];
+#pragma unroll
+        for (int q = 0; q < nsym(D); ++q) Gm[q] = WPHI ? val[D + q] : c.stat[q * c.nb + i];
+        T Li[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            T acc = val[a];
+#pragma unroll
+            for (int bb = 0; bb < D; ++bb) acc -= Gm[symi(D, a, bb)] * ud[bb];
+            Li[a] = phi * acc;
+        }
+        if constexpr (ENERGY) {
+            T e = val[D + (WPHI ? nsym(D) : 0)];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                e -= T(2) * ud[a] * val[a];
+#pragma unroll
+                for (int bb = 0; bb < D; ++bb) e += ud[a] * ud[bb] * Gm[symi(D, a, bb)];
+            }
+            Wout[i] = T(0.5) * phi * e;
+        }
+        if constexpr (VV) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const long k = a * c.nb + i;
+                T bk = b ? b[k] : T(0);
+                T Fn = Li[a] + bk;
+                T vn = c.chiO[k] ? v[k] + c1 * (F[k] + Fn) : T(0);
+                v[k] = vn;
+                F[k] = Fn;
+                if constexpr (ENRED) {
+                    red[0] += 0.5 * double(rho) * double(vn) * double(vn);
+                    red[1] += -0.5 * double(ud[a]) * double(Li[a]);
+                    red[2] += -double(bk) * double(ud[a]);
+                    if (c.chiO[k]) red[3] += double(Fn) * double(Fn);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < D; ++a) L[a * c.nb + i] = Li[a];
+        }
+    }
+};
+
+// LPS dilatation (Eq. 96 with the sign reading of Eq. 93):
+//   theta = 3 chi / m (S - g_i u_i),  0 where chi = 0 or m = 0.
+template <class T>
+struct FinTheta {
+    static constexpr int NOUT = 1, NRED = 0;
+    NodeCtx<T> c;
+    const T* u; T* theta;
+    __device__ __forceinline__ void fin(long i, const T (&val)[1], double*) const {
+        T m = c.stat[9 * c.nb + i];
+        T th = T(0);
+        if (c.chiB[i] && m != T(0)) {
+            T acc = val[0];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) acc -= c.stat[(6 + d) * c.nb + i] * u[d * c.nb + i];
+            th = T(3) / m * acc;
+        }
+        theta[i] = th;
+    }
+};
+
+// LPS force (Eq. 95 with the sign reading of Eq. 92):
+//   L_i = chi (conv_i + k_a theta g_i - G_ij u_j), conv_i including k_a a (*) chi theta.
+// MODE 0: write L;  MODE 1: Verlet finish (as FinBB);  MODE 2: CG operator
+// Ap = -chi_O L with partial sum p.Ap;  MODE 3: FP64 residual
+// r = chi_O (L + b) with partial |r|^2.
+template <class T, int D, int MODE, bool ENRED>
+struct FinLin {
+    // Shared by bond-based (static G) and LPS for the solver / VV modes.
+    static constexpr int NOUT = D;
+    static constexpr int NRED = (MODE == 1) ? (ENRED ? 4 : 0) : ((MODE >= 2) ? 1 : 0);
+    NodeCtx<T> c;
+    int lps;
+    T ka;
+    const T* u; const T* theta;
+    T* L; T* v; T* F; const T* b;
+    T c1, rho;
+    __device__ __forceinline__ void fin(long i, const T (&val)[D], double* red) const {
+        T chi = c.chiB[i] ? T(1) : T(0);
+        T ud[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) ud[d] = u[d * c.nb + i];
+        T th = lps ? theta[i] : T(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            T acc = val[a];
+#pragma unroll
+            for (int bb = 0; bb < D; ++bb) acc -= c.stat[symi(D, a, bb) * c.nb + i] * ud[bb];
+            if (lps) acc += ka * th * c.stat[(6 + a) * c.nb + i];
+            T La = chi * acc;
+            const long k = a * c.nb + i;
+            if constexpr (MODE == 0) {
+                L[k] = La;
+            } else if constexpr (MODE == 1) {
+                T bk = b ? b[k] : T(0);
+                T Fn = La + bk;
+                T vn = c.chiO[k] ? v[k] + c1 * (F[k] + Fn) : T(0);
+                v[k] = vn;
+                F[k] = Fn;
+                if constexpr (ENRED) {
+                    red[0] += 0.5 * double(rho) * double(vn) * double(vn);
+                    red[1] += -0.5 * double(ud[a]) * double(La);
+                    red[2] += -double(bk) * double(ud[a]);
+                    if (c.chiO[k]) red[3] += double(Fn) * double(Fn);
+                }
+            } else if constexpr (MODE == 2) {
+                T ap = c.chiO[k] ? -La : T(0);
+                L[k] = ap;
+                red[0] += double(ud[a]) * double(ap);
+            } else {
+                T r = c.chiO[k] ? La + b[k] : T(0);
+                L[k] = r;
+                red[0] += double(r) * double(r);
+            }
+        }
+    }
+};
+
+// Damage index: cnt = rint(omega_0 (*) phi) + phi(x), beta(x) static,
+// d = 1 - phi cnt / beta on chi_B.
+template <class T>
+struct FinCount {
+    static constexpr int NOUT = 1, NRED = 0;
+    NodeCtx<T> c;
+    int beta_comp;
+    const uint8_t* lam; T* d;
+    __device__ __forceinline__ void fin(long i, const T (&val)[1], double*) const {
+        int phi = (c.chiB[i] && lam[i]) ? 1 : 0;
+        long cnt = (long)rint(val[0]) + phi;
+        long beta = (long)rint(c.stat[beta_comp * c.nb + i]) + (c.chiB[i] ? 1 : 0);
+        d[i] = c.chiB[i] ? T(1.0 - double(phi * cnt) / double(beta)) : T(0);
+    }
+};
+
+// Weighted bond-based adjoint epilogue:
+//   u_bar_i = phi (cg_i - G_ij g_j)
+//   phi_bar = g_i (conv_i - G_ij u_j) + u_j cg_j - E'
+//   s_bar   = chi_B phi_bar  (scale weights, phi = chi_B s)
+template <class T, int D, int WK>
+struct FinAdj {
+    static constexpr int NOUT = 2 * D + nsym(D) + 1;
+    static constexpr int NRED = 0;
+    NodeCtx<T> c;
+    const T* u; const T* u2; const T* g; const uint8_t* lam; const T* s;
+    T* ubar; T* wbar;
+    T wscale;       // wbar = wscale * chi_B phi_bar (+ previous value if accumulate)
+    int accumulate;
+    __device__ __forceinline__ void fin(long i, const T (&val)[NOUT], double*) const {
+        T phi = node_phi<T, WK>(c, i, lam, s);
+        T ud[D], gd[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            ud[d] = u[d * c.nb + i] + (u2 ? u2[d * c.nb + i] : T(0));
+            gd[d] = g[d * c.nb + i];
+        }
+        T pb = -val[2 * D + nsym(D)];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            T acc_u = val[D + nsym(D) + a];
+            T acc_c = val[a];
+#pragma unroll
+            for (int bb = 0; bb < D; ++bb) {
+                T Gab = val[D + symi(D, a, bb)];
+                acc_u -= Gab * gd[bb];
+                acc_c -= Gab * ud[bb];
+            }
+            if (ubar) ubar[a * c.nb + i] = phi * acc_u;
+            pb += gd[a] * acc_c + ud[a] * val[D + nsym(D) + a];
+        }
+        if (wbar) {
+            T add = c.chiB[i] ? wscale * pb : T(0);
+            wbar[i] = accumulate ? wbar[i] + add : add;
+        }
+    }
+};
+
+// Plain scalar output (tests).
+template <class T>
+struct FinScalar {
+    static constexpr int NOUT = 1, NRED = 0;
+    T* out;
+    __device__ __forceinline__ void fin(long i, const T (&val)[1], double*) const { out[i] = val[0]; }
+};
+
+}  // namespace pdk

@@ -1,0 +1,63 @@
+// pd_plan.hpp -- host-side plan object and chain runners (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/pd_fcbm.h"
+#include "pd_passes.hpp"
+
+struct pd_plan_s {
+    // geometry
+    int dim;
+    int n[3], b[3];
+    double dx[3];
+    double delta;
+    int influence;
+    pd_kernel kern;
+    pd_dtype dtype;
+    int flags;
+    hipStream_t stream0;
+    int device;
+    int max_lds;                 // bytes of LDS a block may use
+    pdk::Geo geo;
+    long nb, nfft;
+    // stencil and kernels
+    int ns;                      // bonds per node
+    int ntap;                    // taps along the last axis (max |o_last| + 1)
+    int nct, ncs;                // taps components, static components
+    uint32_t oddmask;            // last-axis parity of each taps component
+    double alpha, m0, kappa, mu, ka, Wc, dt_max, dV;
+    int beta_comp;               // static component holding the omega_0 bond count
+    // device buffers
+    void* tw;                    // T twiddles: table for length N at [N, 2N)
+    double* tw64;                // FP64 twiddles, same layout
+    void* taps;                  // T [nct][ntap][NP]
+    void* stat;                  // T [ncs][nb]
+    uint8_t* chiB;               // [nb]
+    uint8_t* chiO;               // [dim][nb]
+    void* SA;                    // complex T workspaces (see pd_passes.hpp)
+    void* SB;
+    void* SC;
+    long saf_cap, sbf_cap, scf_cap;   // field capacity of each workspace
+    void* theta;                 // T [nb] (LPS)
+    void* vtmp;                  // T [dim][nb] scratch (solver / adjoint)
+    void* vtmp2;                 // T [dim][nb]
+    double* partials;            // per-block reduction partials
+    long partials_cap;
+    double* red;                 // final reductions [8]
+    double* red_host;            // pinned host copy [8]
+    int* offs_dev;               // stencil offsets [ns][3]
+    double* kval_dev;            // kernel values [ns][ncs]
+    size_t bytes;
+    pd_plan_s* sub32;            // FP32 operator for the mixed solve
+    pd_plan_s* parent;           // set on sub32
+};
+
+namespace pdh {
+
+pd_status check(hipError_t e);
+
+}  // namespace pdh
