@@ -70,7 +70,7 @@ typedef enum {
 
 typedef struct {
     int dim;              /* 2 or 3 */
-    int64_t fft_n[3];     /* FFT grid (x, y, z), powers of two: x in [32, 2048],
+    int64_t fft_n[3];     /* FFT grid (x, y, z), powers of two: x in [16, 2048],
                              y and z in [16, 1024]; fft_n[2] = 1 when dim == 2 */
     int64_t body_n[3];    /* body box (x, y, z), >= 1; body_n[2] = 1 when dim == 2.
                              Requires fft_n[d] - body_n[d] >= ceil(delta/dx[d]) so
@@ -121,6 +121,7 @@ typedef struct {
     double dt_max;            /* largest stable velocity-Verlet step for the periodic
                                  operator (2/sqrt(lambda_max/rho)) */
     int64_t workspace_bytes;  /* device memory held by the plan */
+    int64_t lds_per_block;    /* LDS bytes a workgroup may use on this device */
 } pd_plan_info;
 
 /* Build a plan: validates sizes and padding, samples the kernels on the
@@ -222,6 +223,25 @@ pd_status pd_static_solve(pd_plan plan, const void* b, const void* w, void* u_in
  * Eq. 48, rounded to the nearest integer) and beta the node's family size
  * inside the body.  lambda uint8 [body], d_out plan dtype [body]. */
 pd_status pd_damage_index(pd_plan plan, const uint8_t* lambda, void* d_out, void* stream);
+
+/* Pass timing (measurement support).  While enabled, every kernel launch of
+ * the plan (and of its FP32 sub-operator) is bracketed by two hipEvents
+ * recorded on the launch stream, together with the pass's algorithmic HBM
+ * bytes (what the pass must read and write: its spectral slabs, kernel
+ * partial spectra and per-node fields, each once).  pd_profile_read waits
+ * for the recorded events, aggregates them by pass name (e.g. "zmul_4x3":
+ * last-axis pass with 4 input and 3 output fields), writes up to cap
+ * records, sets *n_out to the number of distinct passes and clears the
+ * record list.  Enabling adds two event records per launch. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;       /* summed event-measured duration */
+    double bytes;          /* summed algorithmic bytes */
+} pd_pass_time;
+
+pd_status pd_profile_enable(pd_plan plan, int enable);
+pd_status pd_profile_read(pd_plan plan, pd_pass_time* out, int cap, int* n_out);
 
 /* Static description of a status code. */
 const char* pd_status_str(pd_status status);

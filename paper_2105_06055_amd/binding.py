@@ -51,7 +51,8 @@ class Mask(C.Structure):
 class PlanInfo(C.Structure):
     _fields_ = [("dim", C.c_int), ("body_nodes", C.c_int64), ("fft_points", C.c_int64),
                 ("stencil_size", C.c_int), ("alpha", C.c_double), ("m0", C.c_double),
-                ("Wc", C.c_double), ("dt_max", C.c_double), ("workspace_bytes", C.c_int64)]
+                ("Wc", C.c_double), ("dt_max", C.c_double), ("workspace_bytes", C.c_int64),
+                ("lds_per_block", C.c_int64)]
 
 
 class State(C.Structure):

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
@@ -141,8 +142,6 @@ inline cx<T>* SAp(pd_plan p) { return reinterpret_cast<cx<T>*>(p->SA); }
 template <class T>
 inline cx<T>* SBp(pd_plan p) { return reinterpret_cast<cx<T>*>(p->SB); }
 template <class T>
-inline cx<T>* SCp(pd_plan p) { return reinterpret_cast<cx<T>*>(p->SC); }
-template <class T>
 inline const cx<T>* TWp(pd_plan p) { return reinterpret_cast<const cx<T>*>(p->tw); }
 
 template <class T>
@@ -159,11 +158,8 @@ template <class T>
 int rows_per_block(pd_plan p) {
     const int Tc = p->geo.Nc / 8;
     int Lt = (sizeof(T) == 4) ? 16 : 8;
-    while (Lt > 1 && Tc * Lt > 1024) Lt >>= 1;
-    const size_t lds = (size_t)Lt * (p->geo.Nc + 2) * sizeof(cx<T>);
-    if (lds > (size_t)p->max_lds) {
-        while (Lt > 1 && (size_t)Lt * (p->geo.Nc + 2) * sizeof(cx<T>) > (size_t)p->max_lds) Lt >>= 1;
-    }
+    while (Lt > 1 && Tc * Lt > 512) Lt >>= 1;
+    while (Lt > 1 && ((size_t)Lt * (p->geo.Nc + 2) + p->geo.n1) * sizeof(cx<T>) > (size_t)p->max_lds) Lt >>= 1;
     return Lt;
 }
 
@@ -171,7 +167,7 @@ template <class T>
 int cols_per_block(pd_plan p, int nc_taps) {
     const int Tn = p->geo.n3 / 8;
     int Lc = (sizeof(T) == 4) ? 16 : 8;
-    while (Lc > 1 && Tn * Lc > 1024) Lc >>= 1;
+    while (Lc > 1 && Tn * Lc > 512) Lc >>= 1;
     while (Lc > p->geo.n2) Lc >>= 1;
     auto need = [&](int L) {
         return (size_t)p->geo.n3 * L * sizeof(cx<T>) + (size_t)L * nc_taps * p->ntap * sizeof(T);
@@ -186,6 +182,29 @@ void allow_lds(K kern, size_t bytes) {
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Records a pair of events around one launch when timing is enabled.
+struct ProfScope {
+    pd_plan p;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    ProfScope(pd_plan p_, hipStream_t st_) : p(p_), st(st_) {
+        if (p->prof && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, st);
+    }
+    void done(const char* name, double bytes) {
+        if (!p->prof || !a) return;
+        hipEvent_t b;
+        if (hipEventCreate(&b) != hipSuccess) return;
+        (void)hipEventRecord(b, st);
+        ProfRec r;
+        std::snprintf(r.name, sizeof(r.name), "%s", name);
+        r.a = a;
+        r.b = b;
+        r.bytes = bytes;
+        p->prof->push_back(r);
+        a = nullptr;
+    }
+};
+
 template <class T>
 long xinv_blocks(pd_plan p) {
     const int Lt = rows_per_block<T>(p);
@@ -198,53 +217,74 @@ pd_status launch_xfwd(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
     const Geo& g = p->geo;
     const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
     dim3 grid((g.b2 + Lt - 1) / Lt, g.b3), block(Tc * Lt);
-    size_t lds = (size_t)Lt * (g.Nc + 2) * sizeof(cx<T>);
+    size_t lds = ((size_t)Lt * (g.Nc + 2) + g.n1) * sizeof(cx<T>);
     allow_lds(k_xfwd<T, G>, lds);
+    ProfScope ps(p, st);
     hipLaunchKernelGGL((k_xfwd<T, G>), grid, block, lds, st, g, gen, SA, TWp<T>(p));
+    if (p->prof) {
+        char nm[32];
+        std::snprintf(nm, sizeof nm, "xfwd_%d", G::NIN);
+        ps.done(nm, gen.nbytes() * (double)g.nb + (double)G::NIN * g.b3 * g.h1 * g.b2 * sizeof(cx<T>));
+    }
     return pdh::check(hipGetLastError());
 }
 
-// Pass 2
+// Last-axis multiply pass over contiguous lines.
+template <class T, class M>
+pd_status launch_lastmul(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, const T* taps, int ntap,
+                         uint32_t oddmask, hipStream_t st) {
+    const int Tn = ln.N / 8;
+    int Lw = std::max(1, 256 / Tn);
+    auto need = [&](int L) {
+        return ((size_t)L * (ln.N + 1) + ln.N) * sizeof(cx<T>) + (size_t)L * M::NC * ntap * sizeof(T);
+    };
+    while (Lw > 1 && need(Lw) > (size_t)p->max_lds) Lw >>= 1;
+    size_t lds = need(Lw);
+    dim3 grid((unsigned)((ln.nlines + Lw - 1) / Lw)), block(Lw * Tn);
+    allow_lds(k_lastmul<T, M>, lds);
+    ProfScope ps(p, st);
+    hipLaunchKernelGGL((k_lastmul<T, M>), grid, block, lds, st, ln, mul, S, taps, ntap, oddmask, TWp<T>(p));
+    if (p->prof) {
+        char nm[32];
+        std::snprintf(nm, sizeof nm, "lastmul_%dx%d", M::NIN, M::NOUT);
+        ps.done(nm, (double)(M::NIN + M::NOUT) * ln.nlines * ln.len * sizeof(cx<T>) +
+                        (double)M::NC * ntap * ln.nlines * sizeof(T));
+    }
+    return pdh::check(hipGetLastError());
+}
+
+// planes per block of the transposing y passes
+template <class T>
+int planes_per_block(pd_plan p) {
+    const int Tn = p->geo.n2 / 8;
+    int Lz = (sizeof(T) == 4) ? 16 : 8;
+    while (Lz > 1 && Tn * Lz > 1024) Lz >>= 1;
+    while (Lz > 1 && ((size_t)Lz * (p->geo.n2 + 1) + p->geo.n2) * sizeof(cx<T>) > (size_t)p->max_lds) Lz >>= 1;
+    return Lz;
+}
+
+// 3D y passes with transpose; F fields starting at SA field 0 / SB field fb.
 template <class T, int SIGN>
-pd_status launch_lines(pd_plan p, int N, long nlines, const cx<T>* in, long in_pitch, int in_len,
-                       cx<T>* out, long out_pitch, int out_len, hipStream_t st) {
-    if (nlines <= 0) return PD_OK;
-    const int Tn = N / 8;
-    int Lw = std::max(1, 256 / Tn);
-    size_t lds = (size_t)Lw * (N + 1) * sizeof(cx<T>);
-    while (Lw > 1 && lds > (size_t)p->max_lds) { Lw >>= 1; lds = (size_t)Lw * (N + 1) * sizeof(cx<T>); }
-    dim3 grid((unsigned)((nlines + Lw - 1) / Lw)), block(Lw * Tn);
-    allow_lds(k_lines<T, SIGN>, lds);
-    hipLaunchKernelGGL((k_lines<T, SIGN>), grid, block, lds, st, N, nlines, in, in_pitch, in_len, out,
-                       out_pitch, out_len, TWp<T>(p));
-    return pdh::check(hipGetLastError());
-}
-
-// Pass 3
-template <class T, class M>
-pd_status launch_lmul(pd_plan p, const M& mul, const T* taps, int ntap, uint32_t oddmask, hipStream_t st) {
+pd_status launch_ytrans(pd_plan p, int F, int fb, hipStream_t st) {
+    if (F <= 0) return PD_OK;
     const Geo& g = p->geo;
-    const int Tn = g.n2 / 8;
-    int Lw = std::max(1, 256 / Tn);
-    size_t lds = (size_t)Lw * (g.n2 + 1) * sizeof(cx<T>);
-    while (Lw > 1 && lds > (size_t)p->max_lds) { Lw >>= 1; lds = (size_t)Lw * (g.n2 + 1) * sizeof(cx<T>); }
-    dim3 grid((g.h1 + Lw - 1) / Lw), block(Lw * Tn);
-    allow_lds(k_lmul<T, M>, lds);
-    hipLaunchKernelGGL((k_lmul<T, M>), grid, block, lds, st, g, mul, SAp<T>(p), taps, ntap, oddmask, TWp<T>(p));
-    return pdh::check(hipGetLastError());
-}
-
-// Pass 4
-template <class T, class M>
-pd_status launch_zcol(pd_plan p, const M& mul, const cx<T>* SB, cx<T>* SC, const T* taps, int ntap,
-                      uint32_t oddmask, hipStream_t st) {
-    const Geo& g = p->geo;
-    const int Tn = g.n3 / 8;
-    const int Lc = cols_per_block<T>(p, M::NC);
-    dim3 grid(g.n2 / Lc, g.h1), block(Lc * Tn);
-    size_t lds = (size_t)g.n3 * Lc * sizeof(cx<T>) + (size_t)Lc * M::NC * ntap * sizeof(T);
-    allow_lds(k_zcol<T, M>, lds);
-    hipLaunchKernelGGL((k_zcol<T, M>), grid, block, lds, st, g, mul, SB, SC, taps, ntap, oddmask, TWp<T>(p));
+    const int Tn = g.n2 / 8, Lz = planes_per_block<T>(p);
+    dim3 grid((g.b3 + Lz - 1) / Lz, g.h1, F), block(Lz * Tn);
+    size_t lds = ((size_t)Lz * (g.n2 + 1) + g.n2) * sizeof(cx<T>);
+    cx<T>* SB = SBp<T>(p) + (long)fb * p->sbf;
+    ProfScope ps(p, st);
+    if (SIGN < 0) {
+        allow_lds(k_ytf<T>, lds);
+        hipLaunchKernelGGL((k_ytf<T>), grid, block, lds, st, g, SAp<T>(p), SB, p->Pz, TWp<T>(p));
+    } else {
+        allow_lds(k_yti<T>, lds);
+        hipLaunchKernelGGL((k_yti<T>), grid, block, lds, st, g, SB, SAp<T>(p), p->Pz, TWp<T>(p));
+    }
+    if (p->prof) {
+        char nm[32];
+        std::snprintf(nm, sizeof nm, "%s_%d", SIGN < 0 ? "ytf" : "yti", g.n2);
+        ps.done(nm, (double)F * g.b3 * g.h1 * (g.b2 + g.n2) * sizeof(cx<T>));
+    }
     return pdh::check(hipGetLastError());
 }
 
@@ -254,13 +294,19 @@ pd_status launch_xinv(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st) 
     const Geo& g = p->geo;
     const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
     dim3 grid((g.b2 + Lt - 1) / Lt, g.b3), block(Tc * Lt);
-    size_t lds = (size_t)Lt * (g.Nc + 2) * sizeof(cx<T>);
+    size_t lds = ((size_t)Lt * (g.Nc + 2) + g.n1) * sizeof(cx<T>);
     size_t red_lds = (size_t)((Tc * Lt + 63) / 64) * 8 * sizeof(double);
     lds = std::max(lds, red_lds);
     const long nblk = (long)grid.x * grid.y;
     if (F::NRED > 0 && nblk * F::NRED > p->partials_cap) return PD_EINVAL;
     allow_lds(k_xinv<T, F>, lds);
+    ProfScope ps(p, st);
     hipLaunchKernelGGL((k_xinv<T, F>), grid, block, lds, st, g, fin, SA, p->partials, TWp<T>(p));
+    if (p->prof) {
+        char nm[32];
+        std::snprintf(nm, sizeof nm, "xinv_%d", F::NOUT);
+        ps.done(nm, fin.nbytes() * (double)g.nb + (double)F::NOUT * g.b3 * g.h1 * g.b2 * sizeof(cx<T>));
+    }
     PD_TRY(pdh::check(hipGetLastError()));
     if (F::NRED > 0) {
         hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, p->partials, nblk, F::NRED, p->red);
@@ -269,11 +315,13 @@ pd_status launch_xinv(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st) 
     return PD_OK;
 }
 
-// One full chain.  sb_off: SB field slot the generator's fields go to (3D);
-// the multiplier then reads SB slots [0, M::NIN).
+// One full chain.  3D: sb_off is the SB field slot the generator's fields go
+// to; the multiplier reads SB slots [0, M::NIN) and writes slots
+// [out_off, out_off + M::NOUT) (out_off > 0 keeps the input spectra for a
+// later chain, as the LPS dilatation stage does for the force stage).
 template <class T, class G, class M, class F>
 pd_status run_chain(pd_plan p, const G& gen, const M& mul, const F& fin, hipStream_t st, int sb_off = 0,
-                    const T* taps = nullptr, int ntap = 0, uint32_t oddmask = 0xffffffffu) {
+                    int out_off = 0, const T* taps = nullptr, int ntap = 0, uint32_t oddmask = 0xffffffffu) {
     static_assert(M::NOUT == F::NOUT, "multiplier/epilogue mismatch");
     const Geo& g = p->geo;
     if (!taps) {
@@ -284,16 +332,15 @@ pd_status run_chain(pd_plan p, const G& gen, const M& mul, const F& fin, hipStre
     if (std::max(G::NIN, M::NOUT) > p->saf_cap) return PD_EINVAL;
     PD_TRY(launch_xfwd<T>(p, gen, SAp<T>(p), st));
     if (g.dim == 2) {
-        static_assert(true, "");
         if (G::NIN != M::NIN) return PD_EINVAL;
-        PD_TRY(launch_lmul<T>(p, mul, taps, ntap, oddmask, st));
+        Lines ln{(long)g.h1, (long)g.P2, g.saf, g.b2, g.n2, 0};
+        PD_TRY(launch_lastmul<T>(p, ln, mul, SAp<T>(p), taps, ntap, oddmask, st));
     } else {
-        if (sb_off + G::NIN > p->sbf_cap || M::NIN > p->sbf_cap || M::NOUT > p->scf_cap) return PD_EINVAL;
-        const long rows = (long)g.b3 * g.h1;
-        PD_TRY(launch_lines<T, -1>(p, g.n2, rows * G::NIN, SAp<T>(p), g.P2, g.b2,
-                                   SBp<T>(p) + (long)sb_off * g.sbf, g.n2, g.n2, st));
-        PD_TRY(launch_zcol<T>(p, mul, SBp<T>(p), SCp<T>(p), taps, ntap, oddmask, st));
-        PD_TRY(launch_lines<T, 1>(p, g.n2, rows * M::NOUT, SCp<T>(p), g.n2, g.n2, SAp<T>(p), g.P2, g.b2, st));
+        if (sb_off + G::NIN > p->sbf_cap || M::NIN > p->sbf_cap || out_off + M::NOUT > p->sbf_cap) return PD_EINVAL;
+        PD_TRY((launch_ytrans<T, -1>(p, G::NIN, sb_off, st)));
+        Lines ln{(long)g.h1 * g.n2, (long)p->Pz, p->sbf, g.b3, g.n3, out_off};
+        PD_TRY(launch_lastmul<T>(p, ln, mul, SBp<T>(p), taps, ntap, oddmask, st));
+        PD_TRY((launch_ytrans<T, 1>(p, M::NOUT, out_off, st)));
     }
     PD_TRY(launch_xinv<T>(p, fin, SAp<T>(p), st));
     return PD_OK;
@@ -475,11 +522,18 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
 void plan_free(pd_plan p) {
     if (!p) return;
     if (p->stream0) (void)hipStreamSynchronize(p->stream0);
-    void* bufs[] = {p->tw, p->tw64, p->taps, p->stat, p->chiB, p->chiO, p->SA, p->SB, p->SC, p->theta,
+    void* bufs[] = {p->tw, p->tw64, p->taps, p->stat, p->chiB, p->chiO, p->SA, p->SB, p->theta,
                     p->vtmp, p->vtmp2, p->partials, p->red, p->offs_dev, p->kval_dev};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->red_host) (void)hipHostFree(p->red_host);
+    if (p->prof) {
+        for (ProfRec& r : *p->prof) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        delete p->prof;
+    }
     if (p->sub32) plan_free(p->sub32);
     delete p;
 }
@@ -531,16 +585,15 @@ pd_status plan_alloc(pd_plan p, hipStream_t st, const uint8_t* chiB_h, const uin
         capA = std::max(capA, D + 1 + nsym(D));
     }
     p->saf_cap = capA;
-    p->sbf_cap = capB;
-    p->scf_cap = capC;
+    p->sbf_cap = std::max(capB, capC);
+    p->scf_cap = 0;
     size_t szA = sizeof(cx<T>) * (size_t)g.saf * capA;
     HIP_TRY(hipMalloc(&p->SA, szA));
     p->bytes += szA;
     if (D == 3) {
-        size_t szB = sizeof(cx<T>) * (size_t)g.sbf * capB, szC = sizeof(cx<T>) * (size_t)g.sbf * capC;
+        size_t szB = sizeof(cx<T>) * (size_t)p->sbf * std::max(capB, capC);
         HIP_TRY(hipMalloc(&p->SB, szB));
-        HIP_TRY(hipMalloc(&p->SC, szC));
-        p->bytes += szB + szC;
+        p->bytes += szB;
     }
     if (p->kern.model == PD_LPS_LINEAR) {
         HIP_TRY(hipMalloc(&p->theta, sizeof(T) * p->nb));
@@ -583,7 +636,7 @@ pd_status plan_create_impl(const pd_grid* grid, const pd_horizon* hz, const pd_k
         if (!(grid->dx[d] > 0)) return PD_EINVAL;
         if (b < 1 || n < 1) return PD_EINVAL;
         if (!is_pow2(n)) return PD_EUNSUPPORTED;
-        const long lo = (d == 0) ? 32 : 16, hi = (d == 0) ? 2048 : 1024;
+        const long lo = 16, hi = (d == 0) ? 2048 : 1024;
         if (n < lo || n > hi) return PD_EUNSUPPORTED;
         const long m = (long)std::ceil(hz->delta / grid->dx[d] * (1.0 - 1e-12));
         if (n - b < m) return PD_EINVAL;  // a bond would wrap around the periodic box
@@ -616,6 +669,8 @@ pd_status plan_create_impl(const pd_grid* grid, const pd_horizon* hz, const pd_k
     g.nb = (long)g.b1 * g.b2 * g.b3;
     g.saf = (long)g.b3 * g.h1 * g.P2;
     g.sbf = (long)g.b3 * g.h1 * g.n2;
+    p->Pz = ((g.b3 + 15) / 16) * 16;
+    p->sbf = (long)g.h1 * g.n2 * p->Pz;
     p->nb = g.nb;
     p->nfft = (long)g.n1 * g.n2 * g.n3;
     p->dV = p->dx[0] * p->dx[1] * (D == 3 ? p->dx[2] : 1.0);
@@ -668,7 +723,7 @@ pd_status force_impl(pd_plan p, const T* u, const void* weight, T* L, T* W, hipS
         fA.c = ctx<T>(p);
         fA.u = u;
         fA.theta = reinterpret_cast<T*>(p->theta);
-        PD_TRY(run_chain<T>(p, gA, MulLPSA<T>{}, fA, st));
+        PD_TRY(run_chain<T>(p, gA, MulLPSA<T>{}, fA, st, 0, 3));
         // stage B: force
         GenTheta<T> gB{};
         gB.c = ctx<T>(p);
@@ -868,7 +923,7 @@ pd_status lin_apply(pd_plan p, const T* x, T* out, const T* b, hipStream_t st) {
         fA.c = ctx<T>(p);
         fA.u = x;
         fA.theta = reinterpret_cast<T*>(p->theta);
-        PD_TRY(run_chain<T>(p, gA, MulLPSA<T>{}, fA, st));
+        PD_TRY(run_chain<T>(p, gA, MulLPSA<T>{}, fA, st, 0, 3));
         GenTheta<T> gB{};
         gB.c = ctx<T>(p);
         gB.theta = reinterpret_cast<const T*>(p->theta);
@@ -917,7 +972,7 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, hipSt
         fA.c = ctx<T>(p);
         fA.u = u;
         fA.theta = reinterpret_cast<T*>(p->theta);
-        PD_TRY(run_chain<T>(p, gA, MulLPSA<T>{}, fA, st));
+        PD_TRY(run_chain<T>(p, gA, MulLPSA<T>{}, fA, st, 0, 3));
         GenTheta<T> gB{};
         gB.c = ctx<T>(p);
         gB.theta = reinterpret_cast<const T*>(p->theta);
@@ -1289,7 +1344,7 @@ pd_status test_conv_impl(pd_plan p, const T* x, const int* sh, int parity, T* ou
         mm.P = P;
         FinScalar<T> ff{};
         ff.out = out;
-        s = run_chain<T>(p, gg, mm, ff, st, 0, taps, ntap, (uint32_t)par[D - 1]);
+        s = run_chain<T>(p, gg, mm, ff, st, 0, 0, taps, ntap, (uint32_t)par[D - 1]);
     }
     (void)hipStreamSynchronize(st);
     if (od) (void)hipFree(od);
@@ -1325,6 +1380,7 @@ pd_status pd_plan_query(pd_plan p, pd_plan_info* info) {
     info->Wc = p->Wc;
     info->dt_max = p->dt_max;
     info->workspace_bytes = (int64_t)p->bytes + (p->sub32 ? (int64_t)p->sub32->bytes : 0);
+    info->lds_per_block = p->max_lds;
     return PD_OK;
 }
 
@@ -1390,6 +1446,55 @@ const char* pd_status_str(pd_status s) {
         case PD_EUNSUPPORTED: return "unsupported";
     }
     return "unknown status";
+}
+
+pd_status pd_profile_enable(pd_plan p, int enable) {
+    if (!p) return PD_EINVAL;
+    pd_plan plans[2] = {p, p->sub32};
+    for (pd_plan q : plans) {
+        if (!q) continue;
+        if (enable && !q->prof) q->prof = new std::vector<ProfRec>();
+        if (!enable && q->prof) {
+            (void)hipDeviceSynchronize();
+            for (ProfRec& r : *q->prof) {
+                (void)hipEventDestroy(r.a);
+                (void)hipEventDestroy(r.b);
+            }
+            delete q->prof;
+            q->prof = nullptr;
+        }
+    }
+    return PD_OK;
+}
+
+pd_status pd_profile_read(pd_plan p, pd_pass_time* out, int cap, int* n_out) {
+    if (!p || !n_out || (cap > 0 && !out)) return PD_EINVAL;
+    std::vector<pd_pass_time> agg;
+    pd_plan plans[2] = {p, p->sub32};
+    for (pd_plan q : plans) {
+        if (!q || !q->prof) continue;
+        for (ProfRec& r : *q->prof) {
+            float ms = 0.f;
+            if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) ms = 0.f;
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+            size_t k = 0;
+            for (; k < agg.size(); ++k)
+                if (std::strncmp(agg[k].name, r.name, sizeof(agg[k].name)) == 0) break;
+            if (k == agg.size()) {
+                pd_pass_time t{};
+                std::snprintf(t.name, sizeof(t.name), "%s", r.name);
+                agg.push_back(t);
+            }
+            agg[k].launches += 1;
+            agg[k].total_ms += ms;
+            agg[k].bytes += r.bytes;
+        }
+        q->prof->clear();
+    }
+    *n_out = (int)agg.size();
+    for (int i = 0; i < (int)agg.size() && i < cap; ++i) out[i] = agg[i];
+    return PD_OK;
 }
 
 pd_status pd_test_conv(pd_plan p, const void* x, const int* shift, int parity, void* out, void* stream) {

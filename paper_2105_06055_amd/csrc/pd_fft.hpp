@@ -94,26 +94,19 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int e) {
     return w;
 }
 
-// One Stockham stage of radix R on the 8 register points of thread j.
-// Butterfly b = j + T*s (s < 8/R) reads the points b + r*N/R, which sit in
-// register q = s + r*(8/R); its outputs go to (b/Ns)*Ns*R + (b%Ns) + r*Ns.
+// First Stockham stage (sub-transform size 1, so no twiddles) of radix R on
+// the 8 register points of thread j.  Butterfly b = j + T*s (s < 8/R) reads
+// the points b + r*N/R, held in register q = s + r*(8/R), and writes its
+// outputs to points b*R + r (to LDS, or kept in registers when this is also
+// the last stage, N == R == 8).
 template <int R, int SIGN, class T>
-__device__ __forceinline__ void fft_stage(cx<T> (&v)[8], int j, int Tn, int N, int Ns,
-                                          const cx<T>* __restrict__ tw, cx<T>* lds, int ls,
-                                          bool last) {
+__device__ __forceinline__ void fft_first(cx<T> (&v)[8], int j, int lgT, cx<T>* lds, bool last) {
     constexpr int S = 8 / R;
-    const int wstep = N / (Ns * R);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const int b = j + Tn * s;
-        const int k = b % Ns;
         cx<T> x[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) x[r] = v[s + r * S];
-        if (Ns > 1) {
-#pragma unroll
-            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], twiddle<SIGN>(tw, (r * k * wstep) & (N - 1)));
-        }
         if constexpr (R == 8) dft8<SIGN>(x);
         else if constexpr (R == 4) dft4<SIGN>(x[0], x[1], x[2], x[3]);
         else dft2<SIGN>(x[0], x[1]);
@@ -121,40 +114,70 @@ __device__ __forceinline__ void fft_stage(cx<T> (&v)[8], int j, int Tn, int N, i
 #pragma unroll
             for (int r = 0; r < R; ++r) v[s + r * S] = x[r];
         } else {
-            const int base = (b / Ns) * Ns * R + k;
+            const int base = (j + (s << lgT)) * R;
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[(base + r * Ns) * ls] = x[r];
+            for (int r = 0; r < R; ++r) lds[base + r] = x[r];
         }
     }
 }
 
-// Full line transform.  Every thread of the block must call this (it
-// contains block-wide barriers), with the same N.  lds points at this
-// thread's line, ls is the LDS distance between consecutive points.
+// Radix-8 Stockham stage with sub-transform size Ns = 2^lgNs: thread j
+// (= butterfly j) reads points j + r*N/8 (register r), multiplies by the
+// twiddles W_{8Ns}^{r k}, k = j mod Ns (table index r*k*N/(8Ns)), and
+// writes point ((j >> lgNs) << (lgNs+3)) | k  +  r*Ns.  Only shifts, masks
+// and adds for the index math.
 template <int SIGN, class T>
-__device__ __forceinline__ void fft_line(cx<T> (&v)[8], int j, int N, const cx<T>* __restrict__ tw,
-                                         cx<T>* lds, int ls) {
-    const int Tn = N >> 3;
-    int log2n = 31 - __clz(N);
-    int n8 = log2n / 3;
-    int rem = log2n - 3 * n8;
-    int nst = n8 + (rem ? 1 : 0);
-    int Ns = 1;
-    __syncthreads();  // the caller may still be reading this LDS region
-    for (int st = 0; st < nst; ++st) {
-        const bool last = (st == nst - 1);
-        const int R = (st < n8) ? 8 : (1 << rem);
-        if (R == 8) fft_stage<8, SIGN>(v, j, Tn, N, Ns, tw, lds, ls, last);
-        else if (R == 4) fft_stage<4, SIGN>(v, j, Tn, N, Ns, tw, lds, ls, last);
-        else fft_stage<2, SIGN>(v, j, Tn, N, Ns, tw, lds, ls, last);
-        Ns *= R;
-        if (!last) {
-            __syncthreads();
+__device__ __forceinline__ void fft_r8(cx<T> (&v)[8], int j, int lgN, int lgNs, const cx<T>* __restrict__ tw,
+                                       int lgtws, cx<T>* lds, bool last) {
+    const int k = j & ((1 << lgNs) - 1);
+    const int e1 = k << (lgN - lgNs - 3 + lgtws);
+    int e = e1;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = lds[(j + Tn * q) * ls];
-            __syncthreads();
-        }
+    for (int r = 1; r < 8; ++r) {
+        v[r] = cmul(v[r], twiddle<SIGN>(tw, e));
+        e += e1;
     }
+    dft8<SIGN>(v);
+    if (!last) {
+        const int base = ((j >> lgNs) << (lgNs + 3)) | k;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) lds[base + (r << lgNs)] = v[r];
+    }
+}
+
+// Full line transform of N = 2^lgN points (8 <= N <= 2048).  Every thread of
+// the block must call this (it contains block-wide barriers), with the same
+// N.  lds points at this thread's line (N contiguous complex values).  The
+// twiddle exp(-2 pi i e/N) is tw[e << lgtws] (lgtws > 0 reuses the table of
+// a multiple length; the table normally sits in LDS).
+template <int SIGN, class T>
+__device__ __forceinline__ void fft_line(cx<T> (&v)[8], int j, int lgN, const cx<T>* __restrict__ tw, int lgtws,
+                                         cx<T>* lds) {
+    const int lgT = lgN - 3;
+    const int nst = (lgN + 2) / 3;      // first stage + radix-8 stages
+    const int r0 = lgN - 3 * (nst - 1);  // log2 of the first radix: 1, 2 or 3
+    __syncthreads();  // the caller may still be reading this LDS region
+    bool last = (nst == 1);
+    if (r0 == 3) fft_first<8, SIGN>(v, j, lgT, lds, last);
+    else if (r0 == 2) fft_first<4, SIGN>(v, j, lgT, lds, last);
+    else fft_first<2, SIGN>(v, j, lgT, lds, last);
+    int lgNs = r0;
+    for (int st = 1; st < nst; ++st) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = lds[j + (q << lgT)];
+        __syncthreads();
+        last = (st == nst - 1);
+        fft_r8<SIGN>(v, j, lgN, lgNs, tw, lgtws, lds, last);
+        lgNs += 3;
+    }
+}
+
+// Copy the length-N twiddle table (global, at twb + N) into LDS; the caller's
+// first fft_line barrier orders it before any use.
+template <class T>
+__device__ __forceinline__ void stage_twiddles(cx<T>* dst, const cx<T>* __restrict__ twb, int N) {
+    for (int e = threadIdx.x; e < N; e += blockDim.x) dst[e] = twb[N + e];
 }
 
 }  // namespace pdk

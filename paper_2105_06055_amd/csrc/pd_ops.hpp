@@ -72,6 +72,18 @@ struct GenU {
     const T* v; const T* F; const T* w; const T* W;
     T dt, c2, Wc;
     int fail;                  // VV: apply the failure rule
+    // algorithmic bytes moved per body node (reads + writes)
+    __host__ double nbytes() const {
+        const double t = sizeof(T);
+        double b = D * t + 1;
+        if (WK == WK_LAMBDA) b += 1;
+        if (WK == WK_SCALE) b += t;
+        if (VV) {
+            b += D * (3 * t + 1) + (w ? D * t : 0.0);
+            if (WK == WK_LAMBDA && fail) b += t + 1;
+        }
+        return b;
+    }
     __device__ __forceinline__ void gen(long i, T (&in)[NIN]) const {
         T ud[D];
 #pragma unroll
@@ -114,6 +126,7 @@ struct GenTheta {
     static constexpr int NIN = 1;
     NodeCtx<T> c;
     const T* theta;
+    __host__ double nbytes() const { return sizeof(T) + 1.0; }
     __device__ __forceinline__ void gen(long i, T (&in)[1]) const {
         in[0] = c.chiB[i] ? theta[i] : T(0);
     }
@@ -125,6 +138,7 @@ struct GenPhi {
     static constexpr int NIN = 1;
     NodeCtx<T> c;
     const uint8_t* lam;
+    __host__ double nbytes() const { return 2.0; }
     __device__ __forceinline__ void gen(long i, T (&in)[1]) const {
         in[0] = (c.chiB[i] && lam[i]) ? T(1) : T(0);
     }
@@ -137,6 +151,10 @@ struct GenAdj {
     static constexpr int NIN = 2 * D + 1 + nsym(D);
     NodeCtx<T> c;
     const T* u; const T* u2; const T* g; const uint8_t* lam; const T* s;
+    __host__ double nbytes() const {
+        const double t = sizeof(T);
+        return (2 * D + (u2 ? D : 0)) * t + 1 + (WK == WK_SCALE ? t : 0.0) + (WK == WK_LAMBDA ? 1.0 : 0.0);
+    }
     __device__ __forceinline__ void gen(long i, T (&in)[NIN]) const {
         T phi = node_phi<T, WK>(c, i, lam, s);
         T ud[D], gd[D];
@@ -162,6 +180,7 @@ template <class T>
 struct GenScalar {
     static constexpr int NIN = 1;
     const T* x;
+    __host__ double nbytes() const { return sizeof(T); }
     __device__ __forceinline__ void gen(long i, T (&in)[1]) const { in[0] = x[i]; }
 };
 
@@ -183,6 +202,42 @@ struct MulBB {
     static constexpr int NIN = D + (WPHI ? 1 : 0) + (ENERGY ? nsym(D) : 0);
     static constexpr int NOUT = D + (WPHI ? nsym(D) : 0) + (ENERGY ? 1 : 0);
     static constexpr int C0 = 0, NC = nsym(D);
+    // components output O depends on
+    template <int O>
+    __host__ __device__ static constexpr uint32_t need() {
+        if (O < D) {
+            uint32_t m = 0;
+            for (int j = 0; j < D; ++j) m |= 1u << symi(D, O, j);
+            return m;
+        }
+        if (WPHI && O < D + nsym(D)) return 1u << (O - D);
+        return (1u << nsym(D)) - 1u;
+    }
+    template <int O>
+    __device__ __forceinline__ cx<T> one(const T* K, const cx<T>* in) const {
+        cx<T> acc = {T(0), T(0)};
+        if constexpr (O < D) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                T k = (O == j) ? K[symi(D, O, j)] : -K[symi(D, O, j)];
+                acc = acc + kmul(k, in[j]);
+            }
+        } else if constexpr (WPHI && O < D + nsym(D)) {
+            constexpr int c = O - D;
+            constexpr bool diag = (c == 0) || (D == 2 ? c == 2 : (c == 3 || c == 5));
+            acc = kmul(diag ? K[c] : -K[c], in[D]);
+        } else {
+            const int ib = D + (WPHI ? 1 : 0);
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int b = a; b < D; ++b) {
+                    T k = (a == b) ? K[symi(D, a, b)] : -T(2) * K[symi(D, a, b)];
+                    acc = acc + kmul(k, in[ib + symi(D, a, b)]);
+                }
+        }
+        return acc;
+    }
     __device__ __forceinline__ void mul(const T* K, int, const cx<T>* in, cx<T>* out) const {
 #pragma unroll
         for (int i = 0; i < D; ++i) {
@@ -224,6 +279,14 @@ struct MulBB {
 template <class T>
 struct MulLPSA {
     static constexpr int NIN = 3, NOUT = 1, C0 = 6, NC = 3;
+    template <int O>
+    __host__ __device__ static constexpr uint32_t need() { return 7u; }
+    template <int O>
+    __device__ __forceinline__ cx<T> one(const T* K, const cx<T>* in) const {
+        cx<T> acc = kmuli(K[0], in[0]);
+        acc = acc + kmuli(K[1], in[1]);
+        return acc + kmuli(K[2], in[2]);
+    }
     __device__ __forceinline__ void mul(const T* K, int, const cx<T>* in, cx<T>* out) const {
         cx<T> acc = kmuli(K[0], in[0]);
         acc = acc + kmuli(K[1], in[1]);
@@ -237,6 +300,20 @@ template <class T>
 struct MulLPSB {
     static constexpr int NIN = 4, NOUT = 3, C0 = 0, NC = 9;
     T ka;
+    template <int O>
+    __host__ __device__ static constexpr uint32_t need() {
+        return (1u << symi(3, O, 0)) | (1u << symi(3, O, 1)) | (1u << symi(3, O, 2)) | (1u << (6 + O));
+    }
+    template <int O>
+    __device__ __forceinline__ cx<T> one(const T* K, const cx<T>* in) const {
+        cx<T> acc = kmuli(ka * K[6 + O], in[3]);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            T k = (O == j) ? K[symi(3, O, j)] : -K[symi(3, O, j)];
+            acc = acc + kmul(k, in[j]);
+        }
+        return acc;
+    }
     __device__ __forceinline__ void mul(const T* K, int, const cx<T>* in, cx<T>* out) const {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -255,6 +332,10 @@ struct MulLPSB {
 template <class T, int D>
 struct MulCount {
     static constexpr int NIN = 1, NOUT = 1, C0 = nsym(D), NC = 1;
+    template <int O>
+    __host__ __device__ static constexpr uint32_t need() { return 1u; }
+    template <int O>
+    __device__ __forceinline__ cx<T> one(const T* K, const cx<T>* in) const { return kmul(K[0], in[0]); }
     __device__ __forceinline__ void mul(const T* K, int, const cx<T>* in, cx<T>* out) const {
         out[0] = kmul(K[0], in[0]);
     }
@@ -267,6 +348,44 @@ struct MulAdj {
     static constexpr int NIN = 2 * D + 1 + nsym(D);
     static constexpr int NOUT = 2 * D + nsym(D) + 1;
     static constexpr int C0 = 0, NC = nsym(D);
+    // outputs: conv_i (D) | G_c (nsym) | cg_i (D) | E' (1)
+    template <int O>
+    __host__ __device__ static constexpr uint32_t need() {
+        if (O < D || (O >= D + nsym(D) && O < 2 * D + nsym(D))) {
+            const int i = O < D ? O : O - D - nsym(D);
+            uint32_t m = 0;
+            for (int j = 0; j < D; ++j) m |= 1u << symi(D, i, j);
+            return m;
+        }
+        if (O < D + nsym(D)) return 1u << (O - D);
+        return (1u << nsym(D)) - 1u;
+    }
+    template <int O>
+    __device__ __forceinline__ cx<T> one(const T* K, const cx<T>* in) const {
+        cx<T> acc = {T(0), T(0)};
+        if constexpr (O < D || (O >= D + nsym(D) && O < 2 * D + nsym(D))) {
+            constexpr int i = O < D ? O : O - D - nsym(D);
+            constexpr int base = O < D ? 0 : D + 1;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                T k = (i == j) ? K[symi(D, i, j)] : -K[symi(D, i, j)];
+                acc = acc + kmul(k, in[base + j]);
+            }
+        } else if constexpr (O < D + nsym(D)) {
+            constexpr int c = O - D;
+            constexpr bool diag = (c == 0) || (D == 2 ? c == 2 : (c == 3 || c == 5));
+            acc = kmul(diag ? K[c] : -K[c], in[D]);
+        } else {
+#pragma unroll
+            for (int p = 0; p < D; ++p)
+#pragma unroll
+                for (int q = p; q < D; ++q) {
+                    T k = (p == q) ? K[symi(D, p, q)] : -K[symi(D, p, q)];
+                    acc = acc + kmul(k, in[2 * D + 1 + symi(D, p, q)]);
+                }
+        }
+        return acc;
+    }
     __device__ __forceinline__ void mul(const T* K, int, const cx<T>* in, cx<T>* out) const {
 #pragma unroll
         for (int i = 0; i < D; ++i) {
@@ -298,6 +417,12 @@ template <class T>
 struct MulTest {
     static constexpr int NIN = 1, NOUT = 1, C0 = 0, NC = 1;
     int P;
+    template <int O>
+    __host__ __device__ static constexpr uint32_t need() { return 1u; }
+    template <int O>
+    __device__ __forceinline__ cx<T> one(const T* K, const cx<T>* in) const {
+        return mul_ipow(kmul(K[0], in[0]), P);
+    }
     __device__ __forceinline__ void mul(const T* K, int, const cx<T>* in, cx<T>* out) const {
         out[0] = mul_ipow(kmul(K[0], in[0]), P);
     }
@@ -323,6 +448,15 @@ struct FinBB {
     T* L; T* Wout;
     T* v; T* F; const T* b;   // VV
     T c1, rho;
+    __host__ double nbytes() const {
+        const double t = sizeof(T);
+        double r = D * t + 1 + (WK == WK_LAMBDA ? 1.0 : 0.0) + (WK == WK_SCALE ? t : 0.0);
+        if (!WPHI) r += nsym(D) * t;
+        if (ENERGY) r += t;
+        if (VV) r += D * (4 * t + 1) + (b ? D * t : 0.0);
+        else r += D * t;
+        return r;
+    }
     __device__ __forceinline__ void fin(long i, const T (&val)[NOUT], double* red) const {
         T phi = node_phi<T, WK>(c, i, lam, s);
         T ud[D], Gm[nsym(D)];
@@ -378,6 +512,7 @@ struct FinTheta {
     static constexpr int NOUT = 1, NRED = 0;
     NodeCtx<T> c;
     const T* u; T* theta;
+    __host__ double nbytes() const { return 8.0 * sizeof(T) + 1.0; }
     __device__ __forceinline__ void fin(long i, const T (&val)[1], double*) const {
         T m = c.stat[9 * c.nb + i];
         T th = T(0);
@@ -407,6 +542,15 @@ struct FinLin {
     const T* u; const T* theta;
     T* L; T* v; T* F; const T* b;
     T c1, rho;
+    __host__ double nbytes() const {
+        const double t = sizeof(T);
+        double r = D * t + 1 + nsym(D) * t + (lps ? (1 + D) * t : 0.0);
+        if (MODE == 0) r += D * t;
+        else if (MODE == 1) r += D * (4 * t + 1) + (b ? D * t : 0.0);
+        else if (MODE == 2) r += D * (t + 1);
+        else r += D * (2 * t + 1);
+        return r;
+    }
     __device__ __forceinline__ void fin(long i, const T (&val)[D], double* red) const {
         T chi = c.chiB[i] ? T(1) : T(0);
         T ud[D];
@@ -456,6 +600,7 @@ struct FinCount {
     NodeCtx<T> c;
     int beta_comp;
     const uint8_t* lam; T* d;
+    __host__ double nbytes() const { return 2.0 + 2.0 * sizeof(T); }
     __device__ __forceinline__ void fin(long i, const T (&val)[1], double*) const {
         int phi = (c.chiB[i] && lam[i]) ? 1 : 0;
         long cnt = (long)rint(val[0]) + phi;
@@ -477,6 +622,11 @@ struct FinAdj {
     T* ubar; T* wbar;
     T wscale;       // wbar = wscale * chi_B phi_bar (+ previous value if accumulate)
     int accumulate;
+    __host__ double nbytes() const {
+        const double t = sizeof(T);
+        return (2 * D + (u2 ? D : 0)) * t + 1 + (WK == WK_SCALE ? t : 0.0) + (ubar ? D * t : 0.0) +
+               (wbar ? (accumulate ? 2 : 1) * t : 0.0);
+    }
     __device__ __forceinline__ void fin(long i, const T (&val)[NOUT], double*) const {
         T phi = node_phi<T, WK>(c, i, lam, s);
         T ud[D], gd[D];
@@ -511,6 +661,7 @@ template <class T>
 struct FinScalar {
     static constexpr int NOUT = 1, NRED = 0;
     T* out;
+    __host__ double nbytes() const { return sizeof(T); }
     __device__ __forceinline__ void fin(long i, const T (&val)[1], double*) const { out[i] = val[0]; }
 };
 

@@ -3,25 +3,29 @@
 // Spectral data layout (complex T, x-spectrum index kx in [0, n1/2]):
 //   SA  "row spectra"   [field][z < b3][kx < h1][y < P2]  (y contiguous, only
 //                       body rows y < b2 are meaningful)
-//   SB  "plane spectra" [field][z < b3][kx < h1][ky < n2] (3D only)
-//   SC  "output planes" [field][z < b3][kx < h1][ky < n2] (3D only)
+//   SB  "column spectra" [field][kx < h1][ky < n2][z < Pz] (3D only, z
+//                       contiguous, only body planes z < b3 are meaningful)
 // Only body rows/planes are ever transformed or stored: the padding of the
 // periodic box (Sec. 4.2.2) is known to be zero on the way in and is not
 // needed on the way out, so each pass is pruned to the body extent.
 //
-// Passes (2D uses 1, 3, 5; 3D uses all five):
-//   1 k_xfwd    real rows of the body -> generator -> r2c FFT along x (length
-//               n1 via an n1/2 complex FFT) -> transposed store into SA
-//   2 k_lines   contiguous complex FFT along y (3D forward: SA -> SB)
-//   3 k_lmul    2D last axis: FFT along y, spectral multiply, inverse FFT
-//   4 k_zcol    3D last axis: z columns (strided, coalesced across ky),
-//               FFT, spectral multiply, inverse FFT, body planes only
-//   5 k_xinv    transposed load from SA, c2r along x, epilogue per node
+// Passes (2D: xfwd, lastmul, xinv; 3D: xfwd, ytf, lastmul, yti, xinv):
+//   k_xfwd     real rows of the body -> generator -> r2c FFT along x (length
+//              n1 via an n1/2 complex FFT) -> transposed store into SA
+//   k_ytf      3D: FFT along y of SA rows, transposed store into SB
+//   k_lastmul  contiguous lines along the last axis: FFT, spectral multiply,
+//              inverse FFT, body points only (SA in 2D, SB in 3D, in place)
+//   k_yti      3D: transposed load from SB, inverse FFT along y into SA
+//   k_xinv     transposed load from SA, c2r along x, epilogue per node
+// Every pass reads and writes contiguous runs: the two transposes sit in
+// the x and y passes, so the multiply pass works on contiguous lines.
 // The spectral multiply evaluates the kernel spectra from partial spectra
 // ("taps") along the last axis:
 //   M_c(k) = i^P_c * sum_{t=0}^{m} B_c[t](k_prefix) trig_c(2 pi k_last t / n_last)
 // with trig = cos (component even in the last axis) or sin (odd).
 #pragma once
+
+#include <type_traits>
 
 #include "pd_ops.hpp"
 
@@ -34,7 +38,7 @@ struct Geo {
     int h1, Nc, P2;     // n1/2+1, n1/2, row pitch of SA (>= b2)
     long nb;            // body nodes
     long saf;           // field stride of SA: b3*h1*P2
-    long sbf;           // field stride of SB/SC: b3*h1*n2
+    long sbf;           // b3*h1*n2 (spectral points of the body planes)
 };
 
 // Block-wide deterministic FP64 reduction of NR values; thread 0 writes the
@@ -67,12 +71,12 @@ __device__ __forceinline__ void block_reduce_store(double (&red)[NR], double* ou
 // Pass 1: generator + r2c along x + transposed store.
 // grid (ceil(b2/Lt), b3), block Tc*Lt, Tc = Nc/8; dynamic LDS Lt*(Nc+2) complex.
 template <class T, class G>
-__global__ void __launch_bounds__(1024) k_xfwd(Geo g, G gen, cx<T>* __restrict__ SA,
+__global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ SA,
                                                const cx<T>* __restrict__ twb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int NF = G::NIN;
-    const int Nc = g.Nc, Tc = Nc >> 3;
+    const int Nc = g.Nc, Tc = Nc >> 3, lgNc = 31 - __clz(Nc);
     const int nthr = blockDim.x;
     const int Lt = nthr / Tc;
     const int tid = threadIdx.x, j = tid % Tc, l = tid / Tc;
@@ -96,13 +100,14 @@ __global__ void __launch_bounds__(1024) k_xfwd(Geo g, G gen, cx<T>* __restrict__
 #pragma unroll
         for (int f = 0; f < NF; ++f) v[f][q] = {a[f], b[f]};
     }
-    const cx<T>* twN = twb + Nc;
-    const cx<T>* twn1 = twb + g.n1;
+    // twiddles of length n1 in LDS after the rows; W_Nc^e = W_n1^(2e)
+    cx<T>* twn1 = lds + Lt * pitch;
+    stage_twiddles(twn1, twb, g.n1);
     cx<T>* row = lds + l * pitch;
     const int ll = tid % Lt, kk = tid / Lt, kstep = nthr / Lt;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        fft_line<-1>(v[f], j, Nc, twN, row, 1);
+        fft_line<-1>(v[f], j, lgNc, twn1, 1, row);
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 8; ++q) row[j + Tc * q] = v[f][q];
@@ -135,170 +140,187 @@ __global__ void __launch_bounds__(1024) k_xfwd(Geo g, G gen, cx<T>* __restrict__
     }
 }
 
+// Output O of the spectral multiply for the 8 wavenumbers of thread j along
+// the last axis (k = j + Tn*q): evaluate the kernel multipliers of the
+// components output O needs from the taps B[c*ntap + t] of this line, then
+// combine the transformed inputs.
+template <int O, class T, class M, int NIN>
+__device__ __forceinline__ void spectral_out(const M& mul, const T* __restrict__ B, int ntap, uint32_t oddmask,
+                                             int j, int Tn, int n_last, const cx<T>* __restrict__ twl,
+                                             const cx<T> (&vin)[NIN][8], cx<T> (&w)[8]) {
+    constexpr uint32_t need = M::template need<O>();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int k = j + Tn * q;
+        T K[M::NC > 0 ? M::NC : 1];
+#pragma unroll
+        for (int c = 0; c < M::NC; ++c)
+            if ((need >> c) & 1u) K[c] = B[c * ntap];
+        for (int t = 1; t < ntap; ++t) {
+            cx<T> tw = twl[(k * t) & (n_last - 1)];
+            const T cs = tw.r, sn = -tw.i;
+#pragma unroll
+            for (int c = 0; c < M::NC; ++c)
+                if ((need >> c) & 1u) K[c] += B[c * ntap + t] * (((oddmask >> (M::C0 + c)) & 1u) ? sn : cs);
+        }
+        cx<T> a[NIN];
+#pragma unroll
+        for (int f = 0; f < NIN; ++f) a[f] = vin[f][q];
+        w[q] = mul.template one<O>(K, a);
+    }
+}
+
+// Compile-time loop over the outputs: multiply, inverse FFT, store.
+template <int O, int NO>
+struct OutLoop {
+    template <class F>
+    __device__ __forceinline__ static void run(F&& f) {
+        f(std::integral_constant<int, O>{});
+        OutLoop<O + 1, NO>::run(f);
+    }
+};
+template <int NO>
+struct OutLoop<NO, NO> {
+    template <class F>
+    __device__ __forceinline__ static void run(F&&) {}
+};
+
 // ----------------------------------------------------------------------------
-// Pass 2: plain contiguous line FFTs (one field line per line slot).
-// Line li reads in[li*in_pitch + p] for p < in_len (zero beyond) and writes
-// out[li*out_pitch + p] for p < out_len.  block Lw*(N/8), LDS Lw*(N+1).
-template <class T, int SIGN>
-__global__ void __launch_bounds__(1024) k_lines(int N, long nlines, const cx<T>* __restrict__ in,
-                                                long in_pitch, int in_len, cx<T>* __restrict__ out,
-                                                long out_pitch, int out_len,
-                                                const cx<T>* __restrict__ twb) {
+// Last-axis pass: contiguous lines along the last axis (y in 2D, z in 3D).
+// Line li (0 <= li < nlines) of field f starts at base + f*fstride + li*pitch
+// and holds len body points (zero-padded to the FFT length N).  The line is
+// also the taps prefix index: kx in 2D, kx*n2 + ky in 3D.  FFT, spectral
+// multiply, inverse FFT, body points stored back in place (a block owns
+// whole lines of every field).
+struct Lines {
+    long nlines, pitch, fstride;
+    int len, N;
+    int out_off;   // outputs go to fields out_off .. out_off + NOUT - 1
+};
+
+// block Lw*(N/8), LDS Lw*(N+1) complex + taps Lw*NC*ntap.
+template <class T, class M>
+__global__ void __launch_bounds__(256) k_lastmul(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps,
+                                                 int ntap, uint32_t oddmask, const cx<T>* __restrict__ twb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-    const int Tn = N >> 3;
+    constexpr int NI = M::NIN, NO = M::NOUT;
+    const int N = ln.N, Tn = N >> 3, lgN = 31 - __clz(N);
     const int Lw = blockDim.x / Tn;
     const int tid = threadIdx.x, j = tid % Tn, l = tid / Tn;
     const long li = (long)blockIdx.x * Lw + l;
-    const bool ok = li < nlines;
-    cx<T> v[8];
-    const cx<T>* src = in + li * in_pitch;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int p = j + Tn * q;
-        v[q] = (ok && p < in_len) ? src[p] : cx<T>{T(0), T(0)};
+    const bool ok = li < ln.nlines;
+    const long lic = ok ? li : 0;
+    // twiddles after the FFT area, then the taps of this block's lines [l][c][t]
+    cx<T>* tw = lds + (long)Lw * (N + 1);
+    stage_twiddles(tw, twb, N);
+    T* tl = reinterpret_cast<T*>(tw + N);
+    for (int e = tid; e < Lw * M::NC * ntap; e += blockDim.x) {
+        const int ll = e / (M::NC * ntap), ct = e % (M::NC * ntap);
+        const long kk = min((long)blockIdx.x * Lw + ll, ln.nlines - 1);
+        tl[e] = taps[((long)(M::C0 + ct / ntap) * ntap + ct % ntap) * ln.nlines + kk];
     }
-    fft_line<SIGN>(v, j, N, twb + N, lds + l * (N + 1), 1);
-    if (ok) {
-        cx<T>* dst = out + li * out_pitch;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int p = j + Tn * q;
-            if (p < out_len) dst[p] = v[q];
-        }
-    }
-}
-
-// Evaluate the kernel multipliers of components [C0, C0+NC) at last-axis
-// wavenumber k from taps B[c*ntap + t] (already for this line) and apply.
-template <class T, class M, int NIN, int NOUT>
-__device__ __forceinline__ void spectral_mul(const M& mul, const T* __restrict__ B, int ntap,
-                                             uint32_t oddmask, int k, int n_last,
-                                             const cx<T>* __restrict__ twl, cx<T> (&vin)[NIN][8],
-                                             cx<T> (&vout)[NOUT][8], int q) {
-    T K[M::NC > 0 ? M::NC : 1];
-#pragma unroll
-    for (int c = 0; c < M::NC; ++c) K[c] = B[c * ntap];
-    for (int t = 1; t < ntap; ++t) {
-        cx<T> w = twl[(k * t) & (n_last - 1)];
-        const T cs = w.r, sn = -w.i;
-#pragma unroll
-        for (int c = 0; c < M::NC; ++c)
-            K[c] += B[c * ntap + t] * (((oddmask >> (M::C0 + c)) & 1u) ? sn : cs);
-    }
-    cx<T> a[NIN], o[NOUT];
-#pragma unroll
-    for (int f = 0; f < NIN; ++f) a[f] = vin[f][q];
-    mul.mul(K, k, a, o);
-#pragma unroll
-    for (int f = 0; f < NOUT; ++f) vout[f][q] = o[f];
-}
-
-// ----------------------------------------------------------------------------
-// Pass 3 (2D): lines along y for each kx: FFT, multiply, inverse FFT.
-// In place on SA (a block owns whole kx lines of every field).
-// block Lw*(n2/8), LDS Lw*(n2+1) complex.
-template <class T, class M>
-__global__ void __launch_bounds__(1024) k_lmul(Geo g, M mul, cx<T>* SA, const T* __restrict__ taps,
-                                               int ntap, uint32_t oddmask,
-                                               const cx<T>* __restrict__ twb) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-    constexpr int NI = M::NIN, NO = M::NOUT;
-    const int N = g.n2, Tn = N >> 3;
-    const int Lw = blockDim.x / Tn;
-    const int tid = threadIdx.x, j = tid % Tn, l = tid / Tn;
-    const int kx = blockIdx.x * Lw + l;
-    const bool ok = kx < g.h1;
-    const int kxc = ok ? kx : 0;
     cx<T> vin[NI][8];
 #pragma unroll
     for (int f = 0; f < NI; ++f) {
-        const cx<T>* src = SA + f * g.saf + (long)kxc * g.P2;
+        const cx<T>* src = S + f * ln.fstride + lic * ln.pitch;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int p = j + Tn * q;
-            vin[f][q] = (ok && p < g.b2) ? src[p] : cx<T>{T(0), T(0)};
+            vin[f][q] = (ok && p < ln.len) ? src[p] : cx<T>{T(0), T(0)};
         }
     }
-    const cx<T>* tw = twb + N;
     cx<T>* line = lds + l * (N + 1);
 #pragma unroll
-    for (int f = 0; f < NI; ++f) fft_line<-1>(vin[f], j, N, tw, line, 1);
-    // taps of this kx for the components in use
-    T Bt[(M::NC > 0 ? M::NC : 1) * 9];
-    const int NP = g.h1;
-    for (int c = 0; c < M::NC; ++c)
-        for (int t = 0; t < ntap; ++t) Bt[c * ntap + t] = taps[((long)(M::C0 + c) * ntap + t) * NP + kxc];
-    cx<T> vout[NO][8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) spectral_mul<T, M, NI, NO>(mul, Bt, ntap, oddmask, j + Tn * q, N, tw, vin, vout, q);
-#pragma unroll
-    for (int o = 0; o < NO; ++o) {
-        fft_line<1>(vout[o], j, N, tw, line, 1);
+    for (int f = 0; f < NI; ++f) fft_line<-1>(vin[f], j, lgN, tw, 0, line);
+    const T* Bt = tl + l * (M::NC * ntap);
+    OutLoop<0, NO>::run([&](auto Oc) {
+        constexpr int O = decltype(Oc)::value;
+        cx<T> w[8];
+        spectral_out<O, T, M, NI>(mul, Bt, ntap, oddmask, j, Tn, N, tw, vin, w);
+        fft_line<1>(w, j, lgN, tw, 0, line);
         if (ok) {
-            cx<T>* dst = SA + o * g.saf + (long)kx * g.P2;
+            cx<T>* dst = S + (ln.out_off + O) * ln.fstride + li * ln.pitch;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int p = j + Tn * q;
-                if (p < g.b2) dst[p] = vout[o][q];
+                if (p < ln.len) dst[p] = w[q];
             }
         }
-    }
+    });
 }
 
 // ----------------------------------------------------------------------------
-// Pass 4 (3D): z columns of a tile of Lc consecutive ky at fixed kx:
-// FFT along z (body planes in), multiply, inverse FFT (body planes out).
-// grid (n2/Lc, h1), block Lc*(n3/8), threads ky-fastest for coalescing.
-// LDS: n3*Lc complex (point-major) + taps Lc*NC*ntap.
-template <class T, class M>
-__global__ void __launch_bounds__(1024) k_zcol(Geo g, M mul, const cx<T>* __restrict__ SB,
-                                               cx<T>* __restrict__ SC, const T* __restrict__ taps,
-                                               int ntap, uint32_t oddmask,
-                                               const cx<T>* __restrict__ twb) {
+// 3D y passes with a transpose, so that the z pass reads contiguous lines.
+//   forward: SA [f][z][kx][y<b2]  --FFT along y-->  SB [f][kx][ky][z<Pz]
+//   inverse: SB [f][kx][ky][z]    --iFFT along y--> SA [f][z][kx][y<b2]
+// A block takes Lz consecutive body planes z0..z0+Lz-1 of one (f, kx), so
+// every ky row of the transposed side is a contiguous run of Lz values.
+// grid (ceil(b3/Lz), h1, F), block Lz*(n2/8), LDS Lz*(n2+1) complex.
+template <class T>
+__global__ void __launch_bounds__(1024) k_ytf(Geo g, const cx<T>* __restrict__ SA, cx<T>* __restrict__ SB,
+                                              int Pz, const cx<T>* __restrict__ twb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-    constexpr int NI = M::NIN, NO = M::NOUT;
-    const int N = g.n3, Tn = N >> 3;
-    const int Lc = blockDim.x / Tn;
-    const int tid = threadIdx.x, l = tid % Lc, j = tid / Lc;
-    const int kx = blockIdx.y;
-    const int ky = blockIdx.x * Lc + l;
-    T* tl = reinterpret_cast<T*>(lds + (long)N * Lc);
-    const long NP = (long)g.h1 * g.n2;
-    for (int e = tid; e < Lc * M::NC * ntap; e += blockDim.x) {
-        const int ll = e % Lc, ct = e / Lc;  // ct = c*ntap + t
-        const int c = ct / ntap, t = ct % ntap;
-        tl[ll * (M::NC * ntap) + ct] = taps[((long)(M::C0 + c) * ntap + t) * NP + (long)kx * g.n2 + blockIdx.x * Lc + ll];
-    }
-    const long plane = (long)g.h1 * g.n2;
-    const long col = (long)kx * g.n2 + ky;
-    cx<T> vin[NI][8];
+    const int N = g.n2, Tn = N >> 3, lgN = 31 - __clz(N);
+    const int Lz = blockDim.x / Tn;
+    const int tid = threadIdx.x, j = tid % Tn, l = tid / Tn;
+    const int kx = blockIdx.y, f = blockIdx.z;
+    const int z0 = blockIdx.x * Lz, z = z0 + l;
+    const bool ok = z < g.b3;
+    cx<T> v[8];
+    const cx<T>* src = SA + f * g.saf + ((long)(ok ? z : 0) * g.h1 + kx) * g.P2;
 #pragma unroll
-    for (int f = 0; f < NI; ++f) {
-        const cx<T>* src = SB + f * g.sbf + col;
+    for (int q = 0; q < 8; ++q) {
+        const int p = j + Tn * q;
+        v[q] = (ok && p < g.b2) ? src[p] : cx<T>{T(0), T(0)};
+    }
+    cx<T>* tw = lds + (long)Lz * (N + 1);
+    stage_twiddles(tw, twb, N);
+    cx<T>* line = lds + l * (N + 1);
+    fft_line<-1>(v, j, lgN, tw, 0, line);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) line[j + Tn * q] = v[q];
+    __syncthreads();
+    const int ll = tid % Lz, kk = tid / Lz, kstep = blockDim.x / Lz;
+    if (z0 + ll < g.b3) {
+        cx<T>* dst = SB + ((long)f * g.h1 + kx) * g.n2 * Pz + z0 + ll;
+        for (int ky = kk; ky < N; ky += kstep) dst[(long)ky * Pz] = lds[ll * (N + 1) + ky];
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(1024) k_yti(Geo g, const cx<T>* __restrict__ SB, cx<T>* __restrict__ SA,
+                                              int Pz, const cx<T>* __restrict__ twb) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+    const int N = g.n2, Tn = N >> 3, lgN = 31 - __clz(N);
+    const int Lz = blockDim.x / Tn;
+    const int tid = threadIdx.x, j = tid % Tn, l = tid / Tn;
+    const int kx = blockIdx.y, f = blockIdx.z;
+    const int z0 = blockIdx.x * Lz, z = z0 + l;
+    const int ll = tid % Lz, kk = tid / Lz, kstep = blockDim.x / Lz;
+    cx<T>* tw = lds + (long)Lz * (N + 1);
+    stage_twiddles(tw, twb, N);
+    {
+        const bool okr = z0 + ll < g.b3;
+        const cx<T>* src = SB + ((long)f * g.h1 + kx) * g.n2 * Pz + z0 + ll;
+        for (int ky = kk; ky < N; ky += kstep)
+            lds[ll * (N + 1) + ky] = okr ? src[(long)ky * Pz] : cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    cx<T>* line = lds + l * (N + 1);
+    cx<T> v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = line[j + Tn * q];
+    fft_line<1>(v, j, lgN, tw, 0, line);
+    if (z < g.b3) {
+        cx<T>* dst = SA + f * g.saf + ((long)z * g.h1 + kx) * g.P2;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int p = j + Tn * q;
-            vin[f][q] = (p < g.b3) ? src[p * plane] : cx<T>{T(0), T(0)};
-        }
-    }
-    const cx<T>* tw = twb + N;
-#pragma unroll
-    for (int f = 0; f < NI; ++f) fft_line<-1>(vin[f], j, N, tw, lds + l, Lc);
-    const T* Bt = tl + l * (M::NC * ntap);
-    cx<T> vout[NO][8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) spectral_mul<T, M, NI, NO>(mul, Bt, ntap, oddmask, j + Tn * q, N, tw, vin, vout, q);
-#pragma unroll
-    for (int o = 0; o < NO; ++o) {
-        fft_line<1>(vout[o], j, N, tw, lds + l, Lc);
-        cx<T>* dst = SC + o * g.sbf + col;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int p = j + Tn * q;
-            if (p < g.b3) dst[p * plane] = vout[o][q];
+            if (p < g.b2) dst[p] = v[q];
         }
     }
 }
@@ -308,13 +330,13 @@ __global__ void __launch_bounds__(1024) k_zcol(Geo g, M mul, const cx<T>* __rest
 // grid (ceil(b2/Lt), b3), block Tc*Lt; LDS Lt*(Nc+2) complex + reduction.
 // partials: per block NRED doubles at (blockIdx.y*gridDim.x + blockIdx.x)*NRED.
 template <class T, class F>
-__global__ void __launch_bounds__(1024) k_xinv(Geo g, F fin, const cx<T>* __restrict__ SA,
+__global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restrict__ SA,
                                                double* __restrict__ partials,
                                                const cx<T>* __restrict__ twb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int NO = F::NOUT;
-    const int Nc = g.Nc, Tc = Nc >> 3;
+    const int Nc = g.Nc, Tc = Nc >> 3, lgNc = 31 - __clz(Nc);
     const int nthr = blockDim.x;
     const int Lt = nthr / Tc;
     const int tid = threadIdx.x, j = tid % Tc, l = tid / Tc;
@@ -323,8 +345,8 @@ __global__ void __launch_bounds__(1024) k_xinv(Geo g, F fin, const cx<T>* __rest
     const int y = y0 + l;
     const int pitch = Nc + 2;
     cx<T>* row = lds + l * pitch;
-    const cx<T>* twN = twb + Nc;
-    const cx<T>* twn1 = twb + g.n1;
+    cx<T>* twn1 = lds + Lt * pitch;
+    stage_twiddles(twn1, twb, g.n1);
     const int ll = tid % Lt, kk = tid / Lt, kstep = nthr / Lt;
     T val[NO][16];
 #pragma unroll
@@ -347,7 +369,7 @@ __global__ void __launch_bounds__(1024) k_xinv(Geo g, F fin, const cx<T>* __rest
             cx<T> Dm = cmul(w, A - B);
             v[q] = (A + B) + cx<T>{-Dm.i, Dm.r};
         }
-        fft_line<1>(v, j, Nc, twN, row, 1);
+        fft_line<1>(v, j, lgNc, twn1, 1, row);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             val[o][2 * q] = v[q].r;

@@ -9,6 +9,14 @@
 #include "../../include/pd_fcbm.h"
 #include "pd_passes.hpp"
 
+// One timed kernel launch (profiling mode): events recorded on the launch
+// stream right before and after the kernel, plus its algorithmic bytes.
+struct ProfRec {
+    char name[32];
+    hipEvent_t a, b;
+    double bytes;
+};
+
 struct pd_plan_s {
     // geometry
     int dim;
@@ -40,8 +48,9 @@ struct pd_plan_s {
     uint8_t* chiO;               // [dim][nb]
     void* SA;                    // complex T workspaces (see pd_passes.hpp)
     void* SB;
-    void* SC;
     long saf_cap, sbf_cap, scf_cap;   // field capacity of each workspace
+    int Pz;                      // z pitch of SB (body planes rounded up to 16)
+    long sbf;                    // field stride of SB: h1*n2*Pz
     void* theta;                 // T [nb] (LPS)
     void* vtmp;                  // T [dim][nb] scratch (solver / adjoint)
     void* vtmp2;                 // T [dim][nb]
@@ -52,6 +61,7 @@ struct pd_plan_s {
     int* offs_dev;               // stencil offsets [ns][3]
     double* kval_dev;            // kernel values [ns][ncs]
     size_t bytes;
+    std::vector<ProfRec>* prof;  // non-null while pass timing is enabled
     pd_plan_s* sub32;            // FP32 operator for the mixed solve
     pd_plan_s* parent;           // set on sub32
 };

@@ -36,7 +36,7 @@ def expected_conv(x, fft, shift, parity):
 
 CASES_2D = [((16, 32), (13, 21)), ((64, 128), (40, 100)), ((128, 64), (100, 40)),
             ((512, 1024), (400, 1000)), ((32, 2048), (9, 1700)), ((1024, 64), (1000, 33))]
-CASES_3D = [((16, 16, 32), (9, 11, 20)), ((32, 64, 32), (20, 50, 17)), ((64, 32, 128), (50, 21, 100)),
+CASES_3D = [((16, 16, 32), (9, 11, 20)), ((16, 32, 16), (12, 20, 12)), ((32, 64, 32), (20, 50, 17)), ((64, 32, 128), (50, 21, 100)),
             ((256, 16, 64), (200, 5, 40))]
 
 
