@@ -176,6 +176,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cg-size", type=int, default=128)
     ap.add_argument("--cg-fft", type=int, default=256)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run one 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; the multi-GPU (slab + halo) path is a design "
@@ -186,6 +188,14 @@ def main():
 
     from paper_2105_06055_amd import workloads
     torch.cuda.set_device(0)
+    if args.copy_calib:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 1 GiB read + 1 GiB written")
+        del src, dst
+        torch.cuda.empty_cache()
     log(f"[bench] workload: LPS {args.size}^3 nodes in {args.fft}^3 FFT grid")
     wl = workloads.block_voids_dynamics(nb=args.size, nfft=args.fft)
     nodes = wl.nodes

@@ -159,7 +159,7 @@ int rows_per_block(pd_plan p) {
     const int Tc = p->geo.Nc / 8;
     int Lt = (sizeof(T) == 4) ? 16 : 8;
     while (Lt > 1 && Tc * Lt > 512) Lt >>= 1;
-    while (Lt > 1 && ((size_t)Lt * (p->geo.Nc + 2) + p->geo.n1) * sizeof(cx<T>) > (size_t)p->max_lds) Lt >>= 1;
+    while (Lt > 1 && ((size_t)Lt * row_pitch(p->geo.Nc) + tw_lds_len(p->geo.n1)) * sizeof(cx<T>) > (size_t)p->max_lds) Lt >>= 1;
     return Lt;
 }
 
@@ -217,7 +217,7 @@ pd_status launch_xfwd(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
     const Geo& g = p->geo;
     const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
     dim3 grid((g.b2 + Lt - 1) / Lt, g.b3), block(Tc * Lt);
-    size_t lds = ((size_t)Lt * (g.Nc + 2) + g.n1) * sizeof(cx<T>);
+    size_t lds = ((size_t)Lt * row_pitch(g.Nc) + tw_lds_len(g.n1)) * sizeof(cx<T>);
     allow_lds(k_xfwd<T, G>, lds);
     ProfScope ps(p, st);
     hipLaunchKernelGGL((k_xfwd<T, G>), grid, block, lds, st, g, gen, SA, TWp<T>(p));
@@ -236,7 +236,7 @@ pd_status launch_lastmul(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, con
     const int Tn = ln.N / 8;
     int Lw = std::max(1, 256 / Tn);
     auto need = [&](int L) {
-        return ((size_t)L * (ln.N + 1) + ln.N) * sizeof(cx<T>) + (size_t)L * M::NC * ntap * sizeof(T);
+        return ((size_t)L * line_pitch(ln.N) + tw_lds_len(ln.N)) * sizeof(cx<T>) + (size_t)L * M::NC * ntap * sizeof(T);
     };
     while (Lw > 1 && need(Lw) > (size_t)p->max_lds) Lw >>= 1;
     size_t lds = need(Lw);
@@ -259,7 +259,7 @@ int planes_per_block(pd_plan p) {
     const int Tn = p->geo.n2 / 8;
     int Lz = (sizeof(T) == 4) ? 16 : 8;
     while (Lz > 1 && Tn * Lz > 1024) Lz >>= 1;
-    while (Lz > 1 && ((size_t)Lz * (p->geo.n2 + 1) + p->geo.n2) * sizeof(cx<T>) > (size_t)p->max_lds) Lz >>= 1;
+    while (Lz > 1 && ((size_t)Lz * line_pitch(p->geo.n2) + tw_lds_len(p->geo.n2)) * sizeof(cx<T>) > (size_t)p->max_lds) Lz >>= 1;
     return Lz;
 }
 
@@ -270,7 +270,7 @@ pd_status launch_ytrans(pd_plan p, int F, int fb, hipStream_t st) {
     const Geo& g = p->geo;
     const int Tn = g.n2 / 8, Lz = planes_per_block<T>(p);
     dim3 grid((g.b3 + Lz - 1) / Lz, g.h1, F), block(Lz * Tn);
-    size_t lds = ((size_t)Lz * (g.n2 + 1) + g.n2) * sizeof(cx<T>);
+    size_t lds = ((size_t)Lz * line_pitch(g.n2) + tw_lds_len(g.n2)) * sizeof(cx<T>);
     cx<T>* SB = SBp<T>(p) + (long)fb * p->sbf;
     ProfScope ps(p, st);
     if (SIGN < 0) {
@@ -294,7 +294,7 @@ pd_status launch_xinv(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st) 
     const Geo& g = p->geo;
     const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
     dim3 grid((g.b2 + Lt - 1) / Lt, g.b3), block(Tc * Lt);
-    size_t lds = ((size_t)Lt * (g.Nc + 2) + g.n1) * sizeof(cx<T>);
+    size_t lds = ((size_t)Lt * row_pitch(g.Nc) + tw_lds_len(g.n1)) * sizeof(cx<T>);
     size_t red_lds = (size_t)((Tc * Lt + 63) / 64) * 8 * sizeof(double);
     lds = std::max(lds, red_lds);
     const long nblk = (long)grid.x * grid.y;

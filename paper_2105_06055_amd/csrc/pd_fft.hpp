@@ -19,6 +19,15 @@
 
 namespace pdk {
 
+// LDS position of FFT point i: one padding slot after every 8 points, so the
+// stride-8 and stride-64 access patterns of the Stockham stages spread over
+// the LDS banks instead of piling onto a few.  A line of N points therefore
+// occupies fft_lds_len(N) complex slots.
+__host__ __device__ __forceinline__ int fft_pad(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int fft_lds_len(int N) { return N + N / 8; }
+// LDS slots of a staged twiddle table of length N (plain layout).
+__host__ __device__ constexpr int tw_lds_len(int N) { return N; }
+
 template <class T>
 struct __align__(2 * sizeof(T)) cx {
     T r, i;
@@ -95,12 +104,12 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int e) {
 }
 
 // First Stockham stage (sub-transform size 1, so no twiddles) of radix R on
-// the 8 register points of thread j.  Butterfly b = j + T*s (s < 8/R) reads
-// the points b + r*N/R, held in register q = s + r*(8/R), and writes its
-// outputs to points b*R + r (to LDS, or kept in registers when this is also
-// the last stage, N == R == 8).
+// the 8 register points of thread j, for lines of N >= 16 points (so it is
+// never the last stage).  Butterfly b = j + T*s (s < 8/R) reads the points
+// b + r*N/R, held in register q = s + r*(8/R), and writes its outputs to
+// points b*R + r in LDS.
 template <int R, int SIGN, class T>
-__device__ __forceinline__ void fft_first(cx<T> (&v)[8], int j, int lgT, cx<T>* lds, bool last) {
+__device__ __forceinline__ void fft_first(const cx<T> (&v)[8], int j, int lgT, cx<T>* lds) {
     constexpr int S = 8 / R;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -110,14 +119,9 @@ __device__ __forceinline__ void fft_first(cx<T> (&v)[8], int j, int lgT, cx<T>* 
         if constexpr (R == 8) dft8<SIGN>(x);
         else if constexpr (R == 4) dft4<SIGN>(x[0], x[1], x[2], x[3]);
         else dft2<SIGN>(x[0], x[1]);
-        if (last) {
+        const int base = (j + (s << lgT)) * R;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[s + r * S] = x[r];
-        } else {
-            const int base = (j + (s << lgT)) * R;
-#pragma unroll
-            for (int r = 0; r < R; ++r) lds[base + r] = x[r];
-        }
+        for (int r = 0; r < R; ++r) lds[fft_pad(base + r)] = x[r];
     }
 }
 
@@ -141,34 +145,36 @@ __device__ __forceinline__ void fft_r8(cx<T> (&v)[8], int j, int lgN, int lgNs, 
     if (!last) {
         const int base = ((j >> lgNs) << (lgNs + 3)) | k;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) lds[base + (r << lgNs)] = v[r];
+        for (int r = 0; r < 8; ++r) lds[fft_pad(base + (r << lgNs))] = v[r];
     }
 }
 
 // Full line transform of N = 2^lgN points (8 <= N <= 2048).  Every thread of
 // the block must call this (it contains block-wide barriers), with the same
-// N.  lds points at this thread's line (N contiguous complex values).  The
+// N.  lds points at this thread's line (fft_lds_len(N) complex slots).  The
 // twiddle exp(-2 pi i e/N) is tw[e << lgtws] (lgtws > 0 reuses the table of
-// a multiple length; the table normally sits in LDS).
+// a multiple length; the table normally sits in LDS, see stage_twiddles).
 template <int SIGN, class T>
 __device__ __forceinline__ void fft_line(cx<T> (&v)[8], int j, int lgN, const cx<T>* __restrict__ tw, int lgtws,
                                          cx<T>* lds) {
+    __syncthreads();  // the caller may still be reading this LDS region
+    if (lgN == 3) {   // a single 8-point transform in registers
+        dft8<SIGN>(v);
+        return;
+    }
     const int lgT = lgN - 3;
     const int nst = (lgN + 2) / 3;      // first stage + radix-8 stages
     const int r0 = lgN - 3 * (nst - 1);  // log2 of the first radix: 1, 2 or 3
-    __syncthreads();  // the caller may still be reading this LDS region
-    bool last = (nst == 1);
-    if (r0 == 3) fft_first<8, SIGN>(v, j, lgT, lds, last);
-    else if (r0 == 2) fft_first<4, SIGN>(v, j, lgT, lds, last);
-    else fft_first<2, SIGN>(v, j, lgT, lds, last);
+    if (r0 == 3) fft_first<8, SIGN>(v, j, lgT, lds);
+    else if (r0 == 2) fft_first<4, SIGN>(v, j, lgT, lds);
+    else fft_first<2, SIGN>(v, j, lgT, lds);
     int lgNs = r0;
     for (int st = 1; st < nst; ++st) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = lds[j + (q << lgT)];
+        for (int q = 0; q < 8; ++q) v[q] = lds[fft_pad(j + (q << lgT))];
         __syncthreads();
-        last = (st == nst - 1);
-        fft_r8<SIGN>(v, j, lgN, lgNs, tw, lgtws, lds, last);
+        fft_r8<SIGN>(v, j, lgN, lgNs, tw, lgtws, lds, st == nst - 1);
         lgNs += 3;
     }
 }

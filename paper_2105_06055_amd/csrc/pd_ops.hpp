@@ -202,6 +202,9 @@ struct MulBB {
     static constexpr int NIN = D + (WPHI ? 1 : 0) + (ENERGY ? nsym(D) : 0);
     static constexpr int NOUT = D + (WPHI ? nsym(D) : 0) + (ENERGY ? 1 : 0);
     static constexpr int C0 = 0, NC = nsym(D);
+    // components odd along the last axis (y in 2D: C_xy; z in 3D: C_xz, C_yz)
+    static constexpr bool RT_ODD = false;
+    static constexpr uint32_t ODD = (D == 2) ? (1u << 1) : ((1u << 2) | (1u << 4));
     // components output O depends on
     template <int O>
     __host__ __device__ static constexpr uint32_t need() {
@@ -279,6 +282,8 @@ struct MulBB {
 template <class T>
 struct MulLPSA {
     static constexpr int NIN = 3, NOUT = 1, C0 = 6, NC = 3;
+    static constexpr bool RT_ODD = false;
+    static constexpr uint32_t ODD = (1u << 2) | (1u << 4) | (1u << 8);
     template <int O>
     __host__ __device__ static constexpr uint32_t need() { return 7u; }
     template <int O>
@@ -299,6 +304,8 @@ struct MulLPSA {
 template <class T>
 struct MulLPSB {
     static constexpr int NIN = 4, NOUT = 3, C0 = 0, NC = 9;
+    static constexpr bool RT_ODD = false;
+    static constexpr uint32_t ODD = (1u << 2) | (1u << 4) | (1u << 8);
     T ka;
     template <int O>
     __host__ __device__ static constexpr uint32_t need() {
@@ -332,6 +339,8 @@ struct MulLPSB {
 template <class T, int D>
 struct MulCount {
     static constexpr int NIN = 1, NOUT = 1, C0 = nsym(D), NC = 1;
+    static constexpr bool RT_ODD = false;
+    static constexpr uint32_t ODD = 0u;
     template <int O>
     __host__ __device__ static constexpr uint32_t need() { return 1u; }
     template <int O>
@@ -348,6 +357,8 @@ struct MulAdj {
     static constexpr int NIN = 2 * D + 1 + nsym(D);
     static constexpr int NOUT = 2 * D + nsym(D) + 1;
     static constexpr int C0 = 0, NC = nsym(D);
+    static constexpr bool RT_ODD = false;
+    static constexpr uint32_t ODD = (D == 2) ? (1u << 1) : ((1u << 2) | (1u << 4));
     // outputs: conv_i (D) | G_c (nsym) | cg_i (D) | E' (1)
     template <int O>
     __host__ __device__ static constexpr uint32_t need() {
@@ -416,6 +427,8 @@ struct MulAdj {
 template <class T>
 struct MulTest {
     static constexpr int NIN = 1, NOUT = 1, C0 = 0, NC = 1;
+    static constexpr bool RT_ODD = true;   // parity comes with the test kernel
+    static constexpr uint32_t ODD = 0u;
     int P;
     template <int O>
     __host__ __device__ static constexpr uint32_t need() { return 1u; }

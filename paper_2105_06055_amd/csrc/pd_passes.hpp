@@ -31,6 +31,12 @@
 
 namespace pdk {
 
+// LDS pitch (complex slots) of a row holding an Nc-point FFT line plus the
+// Nyquist value; odd, so column-wise (transposed) accesses are conflict-free.
+__host__ __device__ constexpr int row_pitch(int Nc) { return (fft_lds_len(Nc) + 2) | 1; }
+// LDS pitch of an N-point line used by the y and last-axis passes.
+__host__ __device__ constexpr int line_pitch(int N) { return (fft_lds_len(N) + 1) | 1; }
+
 struct Geo {
     int dim;
     int n1, n2, n3;     // FFT grid
@@ -84,7 +90,7 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
     const int y0 = blockIdx.x * Lt;
     const int y = y0 + l;
     const bool rowok = y < g.b2;
-    const int pitch = Nc + 2;
+    const int pitch = row_pitch(Nc);
     cx<T> v[NF][8];
     const long rbase = ((long)z * g.b2 + y) * g.b1;
 #pragma unroll
@@ -149,6 +155,7 @@ __device__ __forceinline__ void spectral_out(const M& mul, const T* __restrict__
                                              int j, int Tn, int n_last, const cx<T>* __restrict__ twl,
                                              const cx<T> (&vin)[NIN][8], cx<T> (&w)[8]) {
     constexpr uint32_t need = M::template need<O>();
+    const uint32_t odd = M::RT_ODD ? oddmask : M::ODD;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int k = j + Tn * q;
@@ -156,12 +163,17 @@ __device__ __forceinline__ void spectral_out(const M& mul, const T* __restrict__
 #pragma unroll
         for (int c = 0; c < M::NC; ++c)
             if ((need >> c) & 1u) K[c] = B[c * ntap];
-        for (int t = 1; t < ntap; ++t) {
-            cx<T> tw = twl[(k * t) & (n_last - 1)];
-            const T cs = tw.r, sn = -tw.i;
+        // taps t = 1 .. ntap-1 (ntap <= 9), unrolled with a guard
 #pragma unroll
-            for (int c = 0; c < M::NC; ++c)
-                if ((need >> c) & 1u) K[c] += B[c * ntap + t] * (((oddmask >> (M::C0 + c)) & 1u) ? sn : cs);
+        for (int t = 1; t < 9; ++t) {
+            if (t < ntap) {
+                cx<T> tw = twl[(k * t) & (n_last - 1)];
+                const T cs = tw.r, sn = -tw.i;
+#pragma unroll
+                for (int c = 0; c < M::NC; ++c)
+                    if ((need >> c) & 1u)
+                        K[c] += B[c * ntap + t] * (((odd >> (M::C0 + c)) & 1u) ? sn : cs);
+            }
         }
         cx<T> a[NIN];
 #pragma unroll
@@ -212,9 +224,9 @@ __global__ void __launch_bounds__(256) k_lastmul(Lines ln, M mul, cx<T>* S, cons
     const bool ok = li < ln.nlines;
     const long lic = ok ? li : 0;
     // twiddles after the FFT area, then the taps of this block's lines [l][c][t]
-    cx<T>* tw = lds + (long)Lw * (N + 1);
+    cx<T>* tw = lds + (long)Lw * line_pitch(N);
     stage_twiddles(tw, twb, N);
-    T* tl = reinterpret_cast<T*>(tw + N);
+    T* tl = reinterpret_cast<T*>(tw + tw_lds_len(N));
     for (int e = tid; e < Lw * M::NC * ntap; e += blockDim.x) {
         const int ll = e / (M::NC * ntap), ct = e % (M::NC * ntap);
         const long kk = min((long)blockIdx.x * Lw + ll, ln.nlines - 1);
@@ -230,7 +242,7 @@ __global__ void __launch_bounds__(256) k_lastmul(Lines ln, M mul, cx<T>* S, cons
             vin[f][q] = (ok && p < ln.len) ? src[p] : cx<T>{T(0), T(0)};
         }
     }
-    cx<T>* line = lds + l * (N + 1);
+    cx<T>* line = lds + l * line_pitch(N);
 #pragma unroll
     for (int f = 0; f < NI; ++f) fft_line<-1>(vin[f], j, lgN, tw, 0, line);
     const T* Bt = tl + l * (M::NC * ntap);
@@ -275,9 +287,9 @@ __global__ void __launch_bounds__(1024) k_ytf(Geo g, const cx<T>* __restrict__ S
         const int p = j + Tn * q;
         v[q] = (ok && p < g.b2) ? src[p] : cx<T>{T(0), T(0)};
     }
-    cx<T>* tw = lds + (long)Lz * (N + 1);
+    cx<T>* tw = lds + (long)Lz * line_pitch(N);
     stage_twiddles(tw, twb, N);
-    cx<T>* line = lds + l * (N + 1);
+    cx<T>* line = lds + l * line_pitch(N);
     fft_line<-1>(v, j, lgN, tw, 0, line);
     __syncthreads();
 #pragma unroll
@@ -286,7 +298,7 @@ __global__ void __launch_bounds__(1024) k_ytf(Geo g, const cx<T>* __restrict__ S
     const int ll = tid % Lz, kk = tid / Lz, kstep = blockDim.x / Lz;
     if (z0 + ll < g.b3) {
         cx<T>* dst = SB + ((long)f * g.h1 + kx) * g.n2 * Pz + z0 + ll;
-        for (int ky = kk; ky < N; ky += kstep) dst[(long)ky * Pz] = lds[ll * (N + 1) + ky];
+        for (int ky = kk; ky < N; ky += kstep) dst[(long)ky * Pz] = lds[ll * line_pitch(N) + ky];
     }
 }
 
@@ -301,16 +313,16 @@ __global__ void __launch_bounds__(1024) k_yti(Geo g, const cx<T>* __restrict__ S
     const int kx = blockIdx.y, f = blockIdx.z;
     const int z0 = blockIdx.x * Lz, z = z0 + l;
     const int ll = tid % Lz, kk = tid / Lz, kstep = blockDim.x / Lz;
-    cx<T>* tw = lds + (long)Lz * (N + 1);
+    cx<T>* tw = lds + (long)Lz * line_pitch(N);
     stage_twiddles(tw, twb, N);
     {
         const bool okr = z0 + ll < g.b3;
         const cx<T>* src = SB + ((long)f * g.h1 + kx) * g.n2 * Pz + z0 + ll;
         for (int ky = kk; ky < N; ky += kstep)
-            lds[ll * (N + 1) + ky] = okr ? src[(long)ky * Pz] : cx<T>{T(0), T(0)};
+            lds[ll * line_pitch(N) + ky] = okr ? src[(long)ky * Pz] : cx<T>{T(0), T(0)};
     }
     __syncthreads();
-    cx<T>* line = lds + l * (N + 1);
+    cx<T>* line = lds + l * line_pitch(N);
     cx<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) v[q] = line[j + Tn * q];
@@ -343,7 +355,7 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     const int z = blockIdx.y;
     const int y0 = blockIdx.x * Lt;
     const int y = y0 + l;
-    const int pitch = Nc + 2;
+    const int pitch = row_pitch(Nc);
     cx<T>* row = lds + l * pitch;
     cx<T>* twn1 = lds + Lt * pitch;
     stage_twiddles(twn1, twb, g.n1);
