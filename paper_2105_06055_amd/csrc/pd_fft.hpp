@@ -33,6 +33,22 @@ struct __align__(2 * sizeof(T)) cx {
     T r, i;
 };
 
+// LDS-typed view of a pointer into dynamic shared memory: index arithmetic
+// on it stays 32-bit (a generic pointer would force 64-bit address math).
+// The address space only exists in the device compilation pass; the host
+// pass (which never runs this code) sees a plain pointer.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using lds_ptr = __attribute__((address_space(3))) T*;
+#else
+template <class T>
+using lds_ptr = T*;
+#endif
+template <class T>
+__device__ __forceinline__ lds_ptr<T> as_lds(T* p) { return (lds_ptr<T>)p; }
+template <class T>
+__device__ __forceinline__ lds_ptr<const T> as_lds(const T* p) { return (lds_ptr<const T>)p; }
+
 template <class T>
 __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
 template <class T>
@@ -97,7 +113,7 @@ __device__ __forceinline__ void dft8(cx<T>* x) {
 }
 
 template <int SIGN, class T>
-__device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int e) {
+__device__ __forceinline__ cx<T> twiddle(lds_ptr<const cx<T>> tw, int e) {
     cx<T> w = tw[e];
     if constexpr (SIGN > 0) w.i = -w.i;
     return w;
@@ -109,7 +125,7 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int e) {
 // b + r*N/R, held in register q = s + r*(8/R), and writes its outputs to
 // points b*R + r in LDS.
 template <int R, int SIGN, class T>
-__device__ __forceinline__ void fft_first(const cx<T> (&v)[8], int j, int lgT, cx<T>* lds) {
+__device__ __forceinline__ void fft_first(const cx<T> (&v)[8], int j, int lgT, lds_ptr<cx<T>> lds) {
     constexpr int S = 8 / R;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -131,8 +147,8 @@ __device__ __forceinline__ void fft_first(const cx<T> (&v)[8], int j, int lgT, c
 // writes point ((j >> lgNs) << (lgNs+3)) | k  +  r*Ns.  Only shifts, masks
 // and adds for the index math.
 template <int SIGN, class T>
-__device__ __forceinline__ void fft_r8(cx<T> (&v)[8], int j, int lgN, int lgNs, const cx<T>* __restrict__ tw,
-                                       int lgtws, cx<T>* lds, bool last) {
+__device__ __forceinline__ void fft_r8(cx<T> (&v)[8], int j, int lgN, int lgNs, lds_ptr<const cx<T>> tw,
+                                       int lgtws, lds_ptr<cx<T>> lds, bool last) {
     const int k = j & ((1 << lgNs) - 1);
     const int e1 = k << (lgN - lgNs - 3 + lgtws);
     int e = e1;
@@ -155,8 +171,10 @@ __device__ __forceinline__ void fft_r8(cx<T> (&v)[8], int j, int lgN, int lgNs, 
 // twiddle exp(-2 pi i e/N) is tw[e << lgtws] (lgtws > 0 reuses the table of
 // a multiple length; the table normally sits in LDS, see stage_twiddles).
 template <int SIGN, class T>
-__device__ __forceinline__ void fft_line(cx<T> (&v)[8], int j, int lgN, const cx<T>* __restrict__ tw, int lgtws,
-                                         cx<T>* lds) {
+__device__ __forceinline__ void fft_line(cx<T> (&v)[8], int j, int lgN, const cx<T>* __restrict__ tw_g, int lgtws,
+                                         cx<T>* lds_g) {
+    lds_ptr<const cx<T>> tw = as_lds(tw_g);
+    lds_ptr<cx<T>> lds = as_lds(lds_g);
     __syncthreads();  // the caller may still be reading this LDS region
     if (lgN == 3) {   // a single 8-point transform in registers
         dft8<SIGN>(v);

@@ -110,38 +110,41 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
     cx<T>* twn1 = lds + Lt * pitch;
     stage_twiddles(twn1, twb, g.n1);
     cx<T>* row = lds + l * pitch;
+    lds_ptr<cx<T>> rowv = as_lds(row);
+    lds_ptr<cx<T>> ldsv = as_lds(lds);
+    lds_ptr<const cx<T>> twv = as_lds(twn1);
     const int ll = tid % Lt, kk = tid / Lt, kstep = nthr / Lt;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         fft_line<-1>(v[f], j, lgNc, twn1, 1, row);
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 8; ++q) row[j + Tc * q] = v[f][q];
+        for (int q = 0; q < 8; ++q) rowv[j + Tc * q] = v[f][q];
         __syncthreads();
         cx<T> X[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int k = j + Tc * q;
-            cx<T> A = row[k];
-            cx<T> B = cconj(row[(Nc - k) & (Nc - 1)]);
+            cx<T> A = rowv[k];
+            cx<T> B = cconj(rowv[(Nc - k) & (Nc - 1)]);
             cx<T> E = cscale(A + B, T(0.5));
             cx<T> Dm = A - B;
             cx<T> O = {T(0.5) * Dm.i, T(-0.5) * Dm.r};
-            X[q] = E + cmul(twn1[k], O);
+            X[q] = E + cmul(twv[k], O);
         }
         cx<T> Xn = {T(0), T(0)};
         if (j == 0) {
-            cx<T> A = row[0];
+            cx<T> A = rowv[0];
             Xn = {A.r - A.i, T(0)};
         }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 8; ++q) row[j + Tc * q] = X[q];
-        if (j == 0) row[Nc] = Xn;
+        for (int q = 0; q < 8; ++q) rowv[j + Tc * q] = X[q];
+        if (j == 0) rowv[Nc] = Xn;
         __syncthreads();
         if (y0 + ll < g.b2) {
             cx<T>* dst = SA + f * g.saf + (long)z * g.h1 * g.P2 + y0 + ll;
-            for (int kx = kk; kx < g.h1; kx += kstep) dst[(long)kx * g.P2] = lds[ll * pitch + kx];
+            for (int kx = kk; kx < g.h1; kx += kstep) dst[(long)kx * g.P2] = ldsv[ll * pitch + kx];
         }
     }
 }
@@ -151,18 +154,28 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
 // components output O needs from the taps B[c*ntap + t] of this line, then
 // combine the transformed inputs.
 template <int O, class T, class M, int NIN>
-__device__ __forceinline__ void spectral_out(const M& mul, const T* __restrict__ B, int ntap, uint32_t oddmask,
-                                             int j, int Tn, int n_last, const cx<T>* __restrict__ twl,
+__device__ __forceinline__ void spectral_out(const M& mul, const T* __restrict__ B_g, int ntap, uint32_t oddmask,
+                                             int j, int Tn, int n_last, const cx<T>* __restrict__ twl_g,
                                              const cx<T> (&vin)[NIN][8], cx<T> (&w)[8]) {
     constexpr uint32_t need = M::template need<O>();
     const uint32_t odd = M::RT_ODD ? oddmask : M::ODD;
+    lds_ptr<const T> B = as_lds(B_g);
+    lds_ptr<const cx<T>> twl = as_lds(twl_g);
+    // this line's taps of the components output O needs, once per line
+    T Bt[M::NC > 0 ? M::NC : 1][9];
+#pragma unroll
+    for (int c = 0; c < M::NC; ++c)
+        if ((need >> c) & 1u) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) Bt[c][t] = (t < ntap) ? B[c * ntap + t] : T(0);
+        }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int k = j + Tn * q;
         T K[M::NC > 0 ? M::NC : 1];
 #pragma unroll
         for (int c = 0; c < M::NC; ++c)
-            if ((need >> c) & 1u) K[c] = B[c * ntap];
+            if ((need >> c) & 1u) K[c] = Bt[c][0];
         // taps t = 1 .. ntap-1 (ntap <= 9), unrolled with a guard
 #pragma unroll
         for (int t = 1; t < 9; ++t) {
@@ -171,8 +184,7 @@ __device__ __forceinline__ void spectral_out(const M& mul, const T* __restrict__
                 const T cs = tw.r, sn = -tw.i;
 #pragma unroll
                 for (int c = 0; c < M::NC; ++c)
-                    if ((need >> c) & 1u)
-                        K[c] += B[c * ntap + t] * (((odd >> (M::C0 + c)) & 1u) ? sn : cs);
+                    if ((need >> c) & 1u) K[c] += Bt[c][t] * (((odd >> (M::C0 + c)) & 1u) ? sn : cs);
             }
         }
         cx<T> a[NIN];
@@ -292,13 +304,15 @@ __global__ void __launch_bounds__(1024) k_ytf(Geo g, const cx<T>* __restrict__ S
     cx<T>* line = lds + l * line_pitch(N);
     fft_line<-1>(v, j, lgN, tw, 0, line);
     __syncthreads();
+    lds_ptr<cx<T>> linev = as_lds(line);
+    lds_ptr<cx<T>> ldsv = as_lds(lds);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) line[j + Tn * q] = v[q];
+    for (int q = 0; q < 8; ++q) linev[j + Tn * q] = v[q];
     __syncthreads();
     const int ll = tid % Lz, kk = tid / Lz, kstep = blockDim.x / Lz;
     if (z0 + ll < g.b3) {
         cx<T>* dst = SB + ((long)f * g.h1 + kx) * g.n2 * Pz + z0 + ll;
-        for (int ky = kk; ky < N; ky += kstep) dst[(long)ky * Pz] = lds[ll * line_pitch(N) + ky];
+        for (int ky = kk; ky < N; ky += kstep) dst[(long)ky * Pz] = ldsv[ll * line_pitch(N) + ky];
     }
 }
 
@@ -316,16 +330,18 @@ __global__ void __launch_bounds__(1024) k_yti(Geo g, const cx<T>* __restrict__ S
     cx<T>* tw = lds + (long)Lz * line_pitch(N);
     stage_twiddles(tw, twb, N);
     {
+        lds_ptr<cx<T>> ldsv = as_lds(lds);
         const bool okr = z0 + ll < g.b3;
         const cx<T>* src = SB + ((long)f * g.h1 + kx) * g.n2 * Pz + z0 + ll;
         for (int ky = kk; ky < N; ky += kstep)
-            lds[ll * line_pitch(N) + ky] = okr ? src[(long)ky * Pz] : cx<T>{T(0), T(0)};
+            ldsv[ll * line_pitch(N) + ky] = okr ? src[(long)ky * Pz] : cx<T>{T(0), T(0)};
     }
     __syncthreads();
     cx<T>* line = lds + l * line_pitch(N);
+    lds_ptr<cx<T>> linev = as_lds(line);
     cx<T> v[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = line[j + Tn * q];
+    for (int q = 0; q < 8; ++q) v[q] = linev[j + Tn * q];
     fft_line<1>(v, j, lgN, tw, 0, line);
     if (z < g.b3) {
         cx<T>* dst = SA + f * g.saf + ((long)z * g.h1 + kx) * g.P2;
@@ -361,6 +377,9 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     stage_twiddles(twn1, twb, g.n1);
     const int ll = tid % Lt, kk = tid / Lt, kstep = nthr / Lt;
     T val[NO][16];
+    lds_ptr<cx<T>> rowv = as_lds(row);
+    lds_ptr<cx<T>> ldsv = as_lds(lds);
+    lds_ptr<const cx<T>> twv = as_lds(twn1);
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
         __syncthreads();
@@ -368,16 +387,16 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
             const bool okr = (y0 + ll) < g.b2;
             const cx<T>* src = SA + o * g.saf + (long)z * g.h1 * g.P2 + y0 + ll;
             for (int kx = kk; kx < g.h1; kx += kstep)
-                lds[ll * pitch + kx] = okr ? src[(long)kx * g.P2] : cx<T>{T(0), T(0)};
+                ldsv[ll * pitch + kx] = okr ? src[(long)kx * g.P2] : cx<T>{T(0), T(0)};
         }
         __syncthreads();
         cx<T> v[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int k = j + Tc * q;
-            cx<T> A = row[k];
-            cx<T> B = cconj(row[Nc - k]);
-            cx<T> w = cconj(twn1[k]);
+            cx<T> A = rowv[k];
+            cx<T> B = cconj(rowv[Nc - k]);
+            cx<T> w = cconj(twv[k]);
             cx<T> Dm = cmul(w, A - B);
             v[q] = (A + B) + cx<T>{-Dm.i, Dm.r};
         }
