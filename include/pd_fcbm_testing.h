@@ -23,6 +23,13 @@ extern "C" {
  * Synchronises the stream. */
 pd_status pd_test_conv(pd_plan plan, const void* x, const int* shift, int parity, void* out, void* stream);
 
+/* Kernel selection for A/B tests: generic_only != 0 makes every later call on
+ * `plan` (and on its FP32 operator, for PD_PLAN_MIXED plans) use the generic
+ * runtime-length last-axis kernel instead of the specialised one (512-point
+ * lines, 4 taps).  Both compute the same multiplier; results agree to
+ * rounding.  PD_EINVAL for a null plan. */
+pd_status pd_test_set_generic(pd_plan plan, int generic_only);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,6 +41,7 @@ constexpr double kPi = 3.14159265358979323846;
 //   B_c[t](k') = (t ? 2 : 1) / Nfft * sum_{o in S, o_last = t} K_c(o) prod_{d<last} trig_{p_cd}(2 pi k_d o_d / n_d)
 // with trig = cos for even and sin for odd axes (Eq. 56-58: the kernel
 // spectrum as a quadrature sum over the horizon, split along the last axis).
+// Layout [k' (line)][component][tap]: the taps of one line are contiguous.
 template <class T>
 __global__ void k_taps(int dim, int n1, int n2, int h1, long NP, int ntap, int ns,
                        const int* __restrict__ offs, const double* __restrict__ kval, int kstride,
@@ -79,7 +80,7 @@ __global__ void k_taps(int dim, int n1, int n2, int h1, long NP, int ntap, int n
         }
     }
     const double sc = (t ? 2.0 : 1.0) * inv_nfft;
-    for (int c = 0; c < nct; ++c) taps[((long)c * ntap + t) * NP + p] = T(acc[c] * sc);
+    for (int c = 0; c < nct; ++c) taps[((long)p * nct + c) * ntap + t] = T(acc[c] * sc);
 }
 
 // Static embedded-constraint fields by direct quadrature over the horizon
@@ -229,21 +230,38 @@ pd_status launch_xfwd(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
     return pdh::check(hipGetLastError());
 }
 
-// Last-axis multiply pass over contiguous lines.
+// Last-axis multiply pass over contiguous lines.  Lines of 512 points with
+// 4 taps (horizon of 3 grid spacings along the last axis) take the
+// specialised kernel; everything else the generic one.
 template <class T, class M>
-pd_status launch_lastmul(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, const T* taps, int ntap,
+pd_status launch_lastmul(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, const T* taps, int ntap, int nct,
                          uint32_t oddmask, hipStream_t st) {
     const int Tn = ln.N / 8;
-    int Lw = std::max(1, 256 / Tn);
-    auto need = [&](int L) {
-        return ((size_t)L * line_pitch(ln.N) + tw_lds_len(ln.N)) * sizeof(cx<T>) + (size_t)L * M::NC * ntap * sizeof(T);
-    };
-    while (Lw > 1 && need(Lw) > (size_t)p->max_lds) Lw >>= 1;
-    size_t lds = need(Lw);
-    dim3 grid((unsigned)((ln.nlines + Lw - 1) / Lw)), block(Lw * Tn);
-    allow_lds(k_lastmul<T, M>, lds);
     ProfScope ps(p, st);
-    hipLaunchKernelGGL((k_lastmul<T, M>), grid, block, lds, st, ln, mul, S, taps, ntap, oddmask, TWp<T>(p));
+    bool fast = false;
+    if constexpr (!M::RT_ODD) fast = (ln.N == 512 && ntap == 4 && p->fast_lastmul);
+    if (fast) {
+        if constexpr (!M::RT_ODD) {
+            constexpr int LG = 9, NT = 4;
+            const int Lw = 4;
+            const size_t lds = ((size_t)Lw * line_pitch(1 << LG) + tw_lds_len(1 << LG)) * sizeof(cx<T>);
+            if (lds > (size_t)p->max_lds) return PD_EUNSUPPORTED;
+            dim3 grid((unsigned)((ln.nlines + Lw - 1) / Lw)), block(Lw * ((1 << LG) / 8));
+            allow_lds(k_lastmul_f<T, M, LG, NT>, lds);
+            hipLaunchKernelGGL((k_lastmul_f<T, M, LG, NT>), grid, block, lds, st, ln, mul, S, taps, nct, TWp<T>(p));
+        }
+    } else {
+        int Lw = std::max(1, 256 / Tn);
+        auto need = [&](int L) {
+            return ((size_t)L * line_pitch(ln.N) + tw_lds_len(ln.N)) * sizeof(cx<T>) +
+                   (size_t)L * M::NC * ntap * sizeof(T);
+        };
+        while (Lw > 1 && need(Lw) > (size_t)p->max_lds) Lw >>= 1;
+        size_t lds = need(Lw);
+        dim3 grid((unsigned)((ln.nlines + Lw - 1) / Lw)), block(Lw * Tn);
+        allow_lds(k_lastmul<T, M>, lds);
+        hipLaunchKernelGGL((k_lastmul<T, M>), grid, block, lds, st, ln, mul, S, taps, ntap, nct, oddmask, TWp<T>(p));
+    }
     if (p->prof) {
         char nm[32];
         std::snprintf(nm, sizeof nm, "lastmul_%dx%d", M::NIN, M::NOUT);
@@ -321,12 +339,14 @@ pd_status launch_xinv(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st) 
 // later chain, as the LPS dilatation stage does for the force stage).
 template <class T, class G, class M, class F>
 pd_status run_chain(pd_plan p, const G& gen, const M& mul, const F& fin, hipStream_t st, int sb_off = 0,
-                    int out_off = 0, const T* taps = nullptr, int ntap = 0, uint32_t oddmask = 0xffffffffu) {
+                    int out_off = 0, const T* taps = nullptr, int ntap = 0, int nct = 1,
+                    uint32_t oddmask = 0xffffffffu) {
     static_assert(M::NOUT == F::NOUT, "multiplier/epilogue mismatch");
     const Geo& g = p->geo;
     if (!taps) {
         taps = reinterpret_cast<const T*>(p->taps);
         ntap = p->ntap;
+        nct = p->nct;
         oddmask = p->oddmask;
     }
     if (std::max(G::NIN, M::NOUT) > p->saf_cap) return PD_EINVAL;
@@ -334,12 +354,12 @@ pd_status run_chain(pd_plan p, const G& gen, const M& mul, const F& fin, hipStre
     if (g.dim == 2) {
         if (G::NIN != M::NIN) return PD_EINVAL;
         Lines ln{(long)g.h1, (long)g.P2, g.saf, g.b2, g.n2, 0};
-        PD_TRY(launch_lastmul<T>(p, ln, mul, SAp<T>(p), taps, ntap, oddmask, st));
+        PD_TRY(launch_lastmul<T>(p, ln, mul, SAp<T>(p), taps, ntap, nct, oddmask, st));
     } else {
         if (sb_off + G::NIN > p->sbf_cap || M::NIN > p->sbf_cap || out_off + M::NOUT > p->sbf_cap) return PD_EINVAL;
         PD_TRY((launch_ytrans<T, -1>(p, G::NIN, sb_off, st)));
         Lines ln{(long)g.h1 * g.n2, (long)p->Pz, p->sbf, g.b3, g.n3, out_off};
-        PD_TRY(launch_lastmul<T>(p, ln, mul, SBp<T>(p), taps, ntap, oddmask, st));
+        PD_TRY(launch_lastmul<T>(p, ln, mul, SBp<T>(p), taps, ntap, nct, oddmask, st));
         PD_TRY((launch_ytrans<T, 1>(p, M::NOUT, out_off, st)));
     }
     PD_TRY(launch_xinv<T>(p, fin, SAp<T>(p), st));
@@ -643,6 +663,7 @@ pd_status plan_create_impl(const pd_grid* grid, const pd_horizon* hz, const pd_k
     }
     pd_plan p = new pd_plan_s();
     std::memset(p, 0, sizeof(*p));
+    p->fast_lastmul = true;
     p->dim = D;
     for (int d = 0; d < 3; ++d) {
         p->n[d] = (int)grid->fft_n[d];
@@ -1344,7 +1365,7 @@ pd_status test_conv_impl(pd_plan p, const T* x, const int* sh, int parity, T* ou
         mm.P = P;
         FinScalar<T> ff{};
         ff.out = out;
-        s = run_chain<T>(p, gg, mm, ff, st, 0, 0, taps, ntap, (uint32_t)par[D - 1]);
+        s = run_chain<T>(p, gg, mm, ff, st, 0, 0, taps, ntap, 1, (uint32_t)par[D - 1]);
     }
     (void)hipStreamSynchronize(st);
     if (od) (void)hipFree(od);
@@ -1501,6 +1522,13 @@ pd_status pd_test_conv(pd_plan p, const void* x, const int* shift, int parity, v
     if (!p || !x || !out || !shift) return PD_EINVAL;
     if (p->dtype == PD_F32) return test_conv_impl<float>(p, (const float*)x, shift, parity, (float*)out, S_(stream));
     return test_conv_impl<double>(p, (const double*)x, shift, parity, (double*)out, S_(stream));
+}
+
+pd_status pd_test_set_generic(pd_plan p, int generic_only) {
+    if (!p) return PD_EINVAL;
+    p->fast_lastmul = !generic_only;
+    if (p->sub32) p->sub32->fast_lastmul = !generic_only;
+    return PD_OK;
 }
 
 }  // extern "C"

@@ -225,7 +225,7 @@ struct Lines {
 // block Lw*(N/8), LDS Lw*(N+1) complex + taps Lw*NC*ntap.
 template <class T, class M>
 __global__ void __launch_bounds__(256) k_lastmul(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps,
-                                                 int ntap, uint32_t oddmask, const cx<T>* __restrict__ twb) {
+                                                 int ntap, int nct, uint32_t oddmask, const cx<T>* __restrict__ twb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int NI = M::NIN, NO = M::NOUT;
@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(256) k_lastmul(Lines ln, M mul, cx<T>* S, cons
     for (int e = tid; e < Lw * M::NC * ntap; e += blockDim.x) {
         const int ll = e / (M::NC * ntap), ct = e % (M::NC * ntap);
         const long kk = min((long)blockIdx.x * Lw + ll, ln.nlines - 1);
-        tl[e] = taps[((long)(M::C0 + ct / ntap) * ntap + ct % ntap) * ln.nlines + kk];
+        tl[e] = taps[(kk * nct + M::C0) * ntap + ct];
     }
     cx<T> vin[NI][8];
 #pragma unroll
@@ -272,6 +272,177 @@ __global__ void __launch_bounds__(256) k_lastmul(Lines ln, M mul, cx<T>* S, cons
             }
         }
     });
+}
+
+// ----------------------------------------------------------------------------
+// Specialised last-axis pass: N = 2^LG points per line (compile time),
+// exactly NT taps per component, and lines of at least 512 points so that a
+// line fills whole wavefronts (N/8 >= 64 threads).  Then
+//  * every address of the FFT stages is a compile-time offset from a
+//    per-thread base;
+//  * a wavefront works on one line only, so the line's taps are
+//    wave-uniform and are read with scalar loads straight from the tap table
+//    (layout [line][component][tap]), kept in scalar registers;
+//  * the trig factors of the taps for the 8 wavenumbers k = j + (N/8) q of
+//    thread j follow from those of j by eighth-turn rotations
+//    (2 pi (N/8) q t / N = pi q t / 4), so each tap costs one table read per
+//    line and no per-wavenumber lookups;
+//  * for at most three outputs, all outputs are formed in one sweep over the
+//    wavenumbers (each kernel component evaluated once) and the input
+//    spectra die before the inverse transforms.
+template <class T, int NT>
+struct TapTrig {
+    // per tap t >= 1: cos, sin of phi_t = 2 pi j t / N and (cos -+ sin)/sqrt2
+    T c[NT], s[NT], a[NT], b[NT];
+    // cos / sin of phi_t + pi m / 4, m = (q t) mod 8
+    template <int M8>
+    __device__ __forceinline__ T cosr(int t) const {
+        if constexpr (M8 == 0) return c[t];
+        else if constexpr (M8 == 1) return a[t];
+        else if constexpr (M8 == 2) return -s[t];
+        else if constexpr (M8 == 3) return -b[t];
+        else if constexpr (M8 == 4) return -c[t];
+        else if constexpr (M8 == 5) return -a[t];
+        else if constexpr (M8 == 6) return s[t];
+        else return b[t];
+    }
+    template <int M8>
+    __device__ __forceinline__ T sinr(int t) const {
+        if constexpr (M8 == 0) return s[t];
+        else if constexpr (M8 == 1) return b[t];
+        else if constexpr (M8 == 2) return c[t];
+        else if constexpr (M8 == 3) return a[t];
+        else if constexpr (M8 == 4) return -s[t];
+        else if constexpr (M8 == 5) return -b[t];
+        else if constexpr (M8 == 6) return -c[t];
+        else return -a[t];
+    }
+};
+
+// Kernel components at wavenumber k = j + (N/8) Q from the line's taps.
+template <int Q, int T0, int NT, class T, class M>
+struct TapSum {
+    __device__ __forceinline__ static void run(const T* __restrict__ Bl, const TapTrig<T, NT>& tr, T* K) {
+        if constexpr (T0 < NT) {
+            constexpr int M8 = (Q * T0) & 7;
+            const T cs = tr.template cosr<M8>(T0), sn = tr.template sinr<M8>(T0);
+#pragma unroll
+            for (int c = 0; c < M::NC; ++c) K[c] += Bl[c * NT + T0] * (((M::ODD >> (M::C0 + c)) & 1u) ? sn : cs);
+            TapSum<Q, T0 + 1, NT, T, M>::run(Bl, tr, K);
+        }
+    }
+};
+
+template <int Q, int NQ>
+struct QLoop {
+    template <class F>
+    __device__ __forceinline__ static void run(F&& f) {
+        f(std::integral_constant<int, Q>{});
+        QLoop<Q + 1, NQ>::run(f);
+    }
+};
+template <int NQ>
+struct QLoop<NQ, NQ> {
+    template <class F>
+    __device__ __forceinline__ static void run(F&&) {}
+};
+
+// block Lw*(N/8) (Lw lines), LDS Lw*line_pitch(N) + N complex.
+template <class T, class M, int LG, int NT>
+__global__ void __launch_bounds__(256) k_lastmul_f(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps, int nct,
+                                                   const cx<T>* __restrict__ twb) {
+    static_assert(LG >= 9 && NT >= 1 && !M::RT_ODD, "specialised pass needs N >= 512");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+    constexpr int NI = M::NIN, NO = M::NOUT, N = 1 << LG, Tn = N >> 3;
+    const int tid = threadIdx.x, j = tid & (Tn - 1);
+    const int l = __builtin_amdgcn_readfirstlane(tid >> (LG - 3));   // wave-uniform line slot
+    const int Lw = blockDim.x >> (LG - 3);
+    const long li = (long)blockIdx.x * Lw + l;
+    const bool ok = li < ln.nlines;
+    const long lic = ok ? li : 0;
+    cx<T>* tw = lds + (long)Lw * line_pitch(N);
+    stage_twiddles(tw, twb, N);
+    cx<T> vin[NI][8];
+#pragma unroll
+    for (int f = 0; f < NI; ++f) {
+        const cx<T>* src = S + f * ln.fstride + lic * ln.pitch;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int p = j + Tn * q;
+            vin[f][q] = (ok && p < ln.len) ? src[p] : cx<T>{T(0), T(0)};
+        }
+    }
+    cx<T>* line = lds + l * line_pitch(N);
+#pragma unroll
+    for (int f = 0; f < NI; ++f) fft_line<-1>(vin[f], j, LG, tw, 0, line);
+    // base trig factors of this thread (the table holds exp(-2 pi i e / N))
+    TapTrig<T, NT> tr;
+    {
+        lds_ptr<const cx<T>> twv = as_lds(tw);
+        const T h = T(0.70710678118654752440084436210484904);
+#pragma unroll
+        for (int t = 1; t < NT; ++t) {
+            const cx<T> w = twv[(j * t) & (N - 1)];
+            tr.c[t] = w.r;
+            tr.s[t] = -w.i;
+            tr.a[t] = (w.r + w.i) * h;
+            tr.b[t] = (w.r - w.i) * h;
+        }
+    }
+    const T* __restrict__ Bl = taps + (lic * nct + M::C0) * NT;
+    auto kvals = [&](auto Qc, T* K) {
+        constexpr int Q = decltype(Qc)::value;
+#pragma unroll
+        for (int c = 0; c < M::NC; ++c) K[c] = Bl[c * NT];
+        TapSum<Q, 1, NT, T, M>::run(Bl, tr, K);
+    };
+    auto store = [&](int O, cx<T> (&w)[8]) {
+        if (ok) {
+            cx<T>* dst = S + (ln.out_off + O) * ln.fstride + li * ln.pitch;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int p = j + Tn * q;
+                if (p < ln.len) dst[p] = w[q];
+            }
+        }
+    };
+    if constexpr (NO <= 3) {
+        cx<T> w[NO][8];
+        QLoop<0, 8>::run([&](auto Qc) {
+            constexpr int Q = decltype(Qc)::value;
+            T K[M::NC];
+            kvals(Qc, K);
+            cx<T> a[NI];
+#pragma unroll
+            for (int f = 0; f < NI; ++f) a[f] = vin[f][Q];
+            OutLoop<0, NO>::run([&](auto Oc) {
+                constexpr int O = decltype(Oc)::value;
+                w[O][Q] = mul.template one<O>(K, a);
+            });
+        });
+#pragma unroll
+        for (int O = 0; O < NO; ++O) {
+            fft_line<1>(w[O], j, LG, tw, 0, line);
+            store(O, w[O]);
+        }
+    } else {
+        OutLoop<0, NO>::run([&](auto Oc) {
+            constexpr int O = decltype(Oc)::value;
+            cx<T> w[8];
+            QLoop<0, 8>::run([&](auto Qc) {
+                constexpr int Q = decltype(Qc)::value;
+                T K[M::NC];
+                kvals(Qc, K);
+                cx<T> a[NI];
+#pragma unroll
+                for (int f = 0; f < NI; ++f) a[f] = vin[f][Q];
+                w[Q] = mul.template one<O>(K, a);
+            });
+            fft_line<1>(w, j, LG, tw, 0, line);
+            store(O, w);
+        });
+    }
 }
 
 // ----------------------------------------------------------------------------

@@ -30,6 +30,7 @@ struct pd_plan_s {
     hipStream_t stream0;
     int device;
     int max_lds;                 // bytes of LDS a block may use
+    bool fast_lastmul;           // specialised last-axis kernel where it applies
     pdk::Geo geo;
     long nb, nfft;
     // stencil and kernels
@@ -42,7 +43,7 @@ struct pd_plan_s {
     // device buffers
     void* tw;                    // T twiddles: table for length N at [N, 2N)
     double* tw64;                // FP64 twiddles, same layout
-    void* taps;                  // T [nct][ntap][NP]
+    void* taps;                  // T [NP][nct][ntap]
     void* stat;                  // T [ncs][nb]
     uint8_t* chiB;               // [nb]
     uint8_t* chiO;               // [dim][nb]

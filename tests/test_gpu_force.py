@@ -116,6 +116,36 @@ def test_lps3d_ragged_voids(orc, dtype):
     plan.close()
 
 
+# Lines of 512 points along the last axis (numpy axis 0) with a horizon of 3
+# spacings take the specialised last-axis kernel: check it against the oracle
+# (ragged body up to the largest body the padding allows) and against the
+# generic kernel on the same plan.
+@pytest.mark.parametrize("dtype", DT)
+@pytest.mark.parametrize("model,body", [("lps", (300, 11, 13)), ("lps", (509, 9, 12)), ("bb", (300, 11, 13)),
+                                        ("bb", (509, 9, 12)), ("bb", (300, 41)), ("bb", (509, 17))])
+def test_specialised_lastaxis_512(orc, dtype, model, body):
+    from paper_2105_06055_amd import binding
+    dx, D = 1e-3, len(body)
+    chi = wl.random_mask(body, 23)
+    u = wl.random_field((D,) + body, 24, 1e-6)
+    fft = (512, 16, 16) if D == 3 else (512, 64)
+    plan = binding.Plan(fft, body, dx, 3 * dx, model=model, E=70e9, nu=0.3 if D == 3 else 1 / 3,
+                        chiB=chi, dtype=dtype)
+    L = plan.force(_dev(u, dtype)).cpu().numpy()
+    g = orc.geom(body, dx, 3 * dx)
+    if model == "lps":
+        Lo, _ = orc.lps_force(g, 70e9, 0.3, chi.astype(float), u)
+    else:
+        Lo = orc.bb_force(g, orc.bb_alpha(D, 70e9, 3 * dx), chi.astype(float), u)
+    _check(L, Lo, u, plan, 2700.0, dtype)
+    plan.set_generic(True)
+    Lg = plan.force(_dev(u, dtype)).cpu().numpy()
+    _check(Lg, Lo, u, plan, 2700.0, dtype)
+    tol = 1e-13 if dtype == torch.float64 else 1e-5
+    assert np.linalg.norm(L - Lg) / np.linalg.norm(Lo) <= tol
+    plan.close()
+
+
 @pytest.mark.parametrize("dtype", DT)
 def test_bb2d_integrity_weights_and_energy(orc, dtype):
     body, fft, dx, m = (40, 50), (64, 64), 1e-3, 3
