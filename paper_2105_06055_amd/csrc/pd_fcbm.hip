@@ -212,22 +212,33 @@ long xinv_blocks(pd_plan p) {
     return (long)((p->geo.b2 + Lt - 1) / Lt) * p->geo.b3;
 }
 
+// Lengths with compile-time specialisations of the x and y passes (the
+// 512^3 box: 256-point complex rows along x, 512-point lines along y); any
+// other length runs the runtime-length kernels (LG = 0).  The specialised x
+// passes also assume a body no longer than half the x box (b1 <= Nc).
+constexpr int kFastLgX = 8, kFastLgY = 9;
+
 // Pass 1
-template <class T, class G>
-pd_status launch_xfwd(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
+template <class T, class G, int LG>
+pd_status launch_xfwd_lg(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
     const Geo& g = p->geo;
     const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
     dim3 grid((g.b2 + Lt - 1) / Lt, g.b3), block(Tc * Lt);
     size_t lds = ((size_t)Lt * row_pitch(g.Nc) + tw_lds_len(g.n1)) * sizeof(cx<T>);
-    allow_lds(k_xfwd<T, G>, lds);
+    allow_lds(k_xfwd<T, G, LG>, lds);
     ProfScope ps(p, st);
-    hipLaunchKernelGGL((k_xfwd<T, G>), grid, block, lds, st, g, gen, SA, TWp<T>(p));
+    hipLaunchKernelGGL((k_xfwd<T, G, LG>), grid, block, lds, st, g, gen, SA, TWp<T>(p));
     if (p->prof) {
         char nm[32];
         std::snprintf(nm, sizeof nm, "xfwd_%d", G::NIN);
         ps.done(nm, gen.nbytes() * (double)g.nb + (double)G::NIN * g.b3 * g.h1 * g.b2 * sizeof(cx<T>));
     }
     return pdh::check(hipGetLastError());
+}
+template <class T, class G>
+pd_status launch_xfwd(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
+    if (p->geo.Nc == (1 << kFastLgX) && p->geo.b1 <= p->geo.Nc) return launch_xfwd_lg<T, G, kFastLgX>(p, gen, SA, st);
+    return launch_xfwd_lg<T, G, 0>(p, gen, SA, st);
 }
 
 // Last-axis multiply pass over contiguous lines.  Lines of 512 points with
@@ -282,9 +293,8 @@ int planes_per_block(pd_plan p) {
 }
 
 // 3D y passes with transpose; F fields starting at SA field 0 / SB field fb.
-template <class T, int SIGN>
-pd_status launch_ytrans(pd_plan p, int F, int fb, hipStream_t st) {
-    if (F <= 0) return PD_OK;
+template <class T, int SIGN, int LG>
+pd_status launch_ytrans_lg(pd_plan p, int F, int fb, hipStream_t st) {
     const Geo& g = p->geo;
     const int Tn = g.n2 / 8, Lz = planes_per_block<T>(p);
     dim3 grid((g.b3 + Lz - 1) / Lz, g.h1, F), block(Lz * Tn);
@@ -292,11 +302,11 @@ pd_status launch_ytrans(pd_plan p, int F, int fb, hipStream_t st) {
     cx<T>* SB = SBp<T>(p) + (long)fb * p->sbf;
     ProfScope ps(p, st);
     if (SIGN < 0) {
-        allow_lds(k_ytf<T>, lds);
-        hipLaunchKernelGGL((k_ytf<T>), grid, block, lds, st, g, SAp<T>(p), SB, p->Pz, TWp<T>(p));
+        allow_lds(k_ytf<T, LG>, lds);
+        hipLaunchKernelGGL((k_ytf<T, LG>), grid, block, lds, st, g, SAp<T>(p), SB, p->Pz, TWp<T>(p));
     } else {
-        allow_lds(k_yti<T>, lds);
-        hipLaunchKernelGGL((k_yti<T>), grid, block, lds, st, g, SB, SAp<T>(p), p->Pz, TWp<T>(p));
+        allow_lds(k_yti<T, LG>, lds);
+        hipLaunchKernelGGL((k_yti<T, LG>), grid, block, lds, st, g, SB, SAp<T>(p), p->Pz, TWp<T>(p));
     }
     if (p->prof) {
         char nm[32];
@@ -305,10 +315,16 @@ pd_status launch_ytrans(pd_plan p, int F, int fb, hipStream_t st) {
     }
     return pdh::check(hipGetLastError());
 }
+template <class T, int SIGN>
+pd_status launch_ytrans(pd_plan p, int F, int fb, hipStream_t st) {
+    if (F <= 0) return PD_OK;
+    if (p->geo.n2 == (1 << kFastLgY)) return launch_ytrans_lg<T, SIGN, kFastLgY>(p, F, fb, st);
+    return launch_ytrans_lg<T, SIGN, 0>(p, F, fb, st);
+}
 
 // Pass 5 (+ deterministic reduction into p->red when F::NRED > 0)
-template <class T, class F>
-pd_status launch_xinv(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st) {
+template <class T, class F, int LG>
+pd_status launch_xinv_lg(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st) {
     const Geo& g = p->geo;
     const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
     dim3 grid((g.b2 + Lt - 1) / Lt, g.b3), block(Tc * Lt);
@@ -317,9 +333,9 @@ pd_status launch_xinv(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st) 
     lds = std::max(lds, red_lds);
     const long nblk = (long)grid.x * grid.y;
     if (F::NRED > 0 && nblk * F::NRED > p->partials_cap) return PD_EINVAL;
-    allow_lds(k_xinv<T, F>, lds);
+    allow_lds(k_xinv<T, F, LG>, lds);
     ProfScope ps(p, st);
-    hipLaunchKernelGGL((k_xinv<T, F>), grid, block, lds, st, g, fin, SA, p->partials, TWp<T>(p));
+    hipLaunchKernelGGL((k_xinv<T, F, LG>), grid, block, lds, st, g, fin, SA, p->partials, TWp<T>(p));
     if (p->prof) {
         char nm[32];
         std::snprintf(nm, sizeof nm, "xinv_%d", F::NOUT);
@@ -331,6 +347,11 @@ pd_status launch_xinv(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st) 
         PD_TRY(pdh::check(hipGetLastError()));
     }
     return PD_OK;
+}
+template <class T, class F>
+pd_status launch_xinv(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st) {
+    if (p->geo.Nc == (1 << kFastLgX) && p->geo.b1 <= p->geo.Nc) return launch_xinv_lg<T, F, kFastLgX>(p, fin, SA, st);
+    return launch_xinv_lg<T, F, 0>(p, fin, SA, st);
 }
 
 // One full chain.  3D: sb_off is the SB field slot the generator's fields go

@@ -76,13 +76,14 @@ __device__ __forceinline__ void block_reduce_store(double (&red)[NR], double* ou
 // ----------------------------------------------------------------------------
 // Pass 1: generator + r2c along x + transposed store.
 // grid (ceil(b2/Lt), b3), block Tc*Lt, Tc = Nc/8; dynamic LDS Lt*(Nc+2) complex.
-template <class T, class G>
+// LG > 0 fixes Nc = 2^LG at compile time (the runtime g.Nc must match).
+template <class T, class G, int LG>
 __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ SA,
                                                const cx<T>* __restrict__ twb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int NF = G::NIN;
-    const int Nc = g.Nc, Tc = Nc >> 3, lgNc = 31 - __clz(Nc);
+    const int lgNc = LG > 0 ? LG : 31 - __clz(g.Nc), Nc = 1 << lgNc, Tc = Nc >> 3;
     const int nthr = blockDim.x;
     const int Lt = nthr / Tc;
     const int tid = threadIdx.x, j = tid % Tc, l = tid / Tc;
@@ -91,20 +92,26 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
     const int y = y0 + l;
     const bool rowok = y < g.b2;
     const int pitch = row_pitch(Nc);
-    cx<T> v[NF][8];
-    const long rbase = ((long)z * g.b2 + y) * g.b1;
+    // The block's rows y0 .. y0+Lt-1 are consecutive in node order, so its
+    // body nodes form one run [nbase, nbase + nval).  The generator runs over
+    // that run with consecutive threads on consecutive nodes (coalesced
+    // loads and stores); its values reach the FFT layout (thread j holds the
+    // x pairs 2(j + Tc q), +1) through a flat [Lt][b1] staging area that
+    // overlays the row buffers.  Nodes per thread: Lt*b1/nthr = 8 b1/Nc,
+    // at most 8 when b1 <= Nc (required for LG > 0), else at most 16.
+    constexpr int RN = LG > 0 ? 8 : 16;
+    const long nbase = ((long)z * g.b2 + y0) * g.b1;
+    const int nval = min(Lt, g.b2 - y0) * g.b1;
+    T gv[NF][RN];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int x0 = 2 * (j + Tc * q);
-        T a[NF], b[NF];
+    for (int r = 0; r < RN; ++r) {
+        const int e = tid + nthr * r;
+        T a[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) { a[f] = T(0); b[f] = T(0); }
-        if (rowok) {
-            if (x0 < g.b1) gen.gen(rbase + x0, a);
-            if (x0 + 1 < g.b1) gen.gen(rbase + x0 + 1, b);
-        }
+        for (int f = 0; f < NF; ++f) a[f] = T(0);
+        if (e < nval) gen.gen(nbase + e, a);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) v[f][q] = {a[f], b[f]};
+        for (int f = 0; f < NF; ++f) gv[f][r] = a[f];
     }
     // twiddles of length n1 in LDS after the rows; W_Nc^e = W_n1^(2e)
     cx<T>* twn1 = lds + Lt * pitch;
@@ -113,13 +120,29 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
     lds_ptr<cx<T>> rowv = as_lds(row);
     lds_ptr<cx<T>> ldsv = as_lds(lds);
     lds_ptr<const cx<T>> twv = as_lds(twn1);
-    const int ll = tid % Lt, kk = tid / Lt, kstep = nthr / Lt;
+    lds_ptr<T> flat = as_lds(reinterpret_cast<T*>(lds));
+    const int ll = tid % Lt, kk = tid / Lt;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        fft_line<-1>(v[f], j, lgNc, twn1, 1, row);
+        __syncthreads();  // the row buffers are free again
+#pragma unroll
+        for (int r = 0; r < RN; ++r) {
+            const int e = tid + nthr * r;
+            if (e < nval) flat[e] = gv[f][r];
+        }
+        __syncthreads();
+        cx<T> v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int x0 = 2 * (j + Tc * q);
+            const T a = (rowok && x0 < g.b1) ? flat[l * g.b1 + x0] : T(0);
+            const T b = (rowok && x0 + 1 < g.b1) ? flat[l * g.b1 + x0 + 1] : T(0);
+            v[q] = {a, b};
+        }
+        fft_line<-1>(v, j, lgNc, twn1, 1, row);
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 8; ++q) rowv[j + Tc * q] = v[f][q];
+        for (int q = 0; q < 8; ++q) rowv[j + Tc * q] = v[q];
         __syncthreads();
         cx<T> X[8];
 #pragma unroll
@@ -142,9 +165,12 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
         for (int q = 0; q < 8; ++q) rowv[j + Tc * q] = X[q];
         if (j == 0) rowv[Nc] = Xn;
         __syncthreads();
+        // kk < Tc: the columns kk + Tc*i (i < 8) cover [0, Nc); kk == 0 adds Nyquist
         if (y0 + ll < g.b2) {
             cx<T>* dst = SA + f * g.saf + (long)z * g.h1 * g.P2 + y0 + ll;
-            for (int kx = kk; kx < g.h1; kx += kstep) dst[(long)kx * g.P2] = ldsv[ll * pitch + kx];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) dst[(long)(kk + Tc * i) * g.P2] = ldsv[ll * pitch + kk + Tc * i];
+            if (kk == 0) dst[(long)Nc * g.P2] = ldsv[ll * pitch + Nc];
         }
     }
 }
@@ -452,12 +478,12 @@ __global__ void __launch_bounds__(256) k_lastmul_f(Lines ln, M mul, cx<T>* S, co
 // A block takes Lz consecutive body planes z0..z0+Lz-1 of one (f, kx), so
 // every ky row of the transposed side is a contiguous run of Lz values.
 // grid (ceil(b3/Lz), h1, F), block Lz*(n2/8), LDS Lz*(n2+1) complex.
-template <class T>
+template <class T, int LG>
 __global__ void __launch_bounds__(1024) k_ytf(Geo g, const cx<T>* __restrict__ SA, cx<T>* __restrict__ SB,
                                               int Pz, const cx<T>* __restrict__ twb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-    const int N = g.n2, Tn = N >> 3, lgN = 31 - __clz(N);
+    const int lgN = LG > 0 ? LG : 31 - __clz(g.n2), N = 1 << lgN, Tn = N >> 3;
     const int Lz = blockDim.x / Tn;
     const int tid = threadIdx.x, j = tid % Tn, l = tid / Tn;
     const int kx = blockIdx.y, f = blockIdx.z;
@@ -480,33 +506,39 @@ __global__ void __launch_bounds__(1024) k_ytf(Geo g, const cx<T>* __restrict__ S
 #pragma unroll
     for (int q = 0; q < 8; ++q) linev[j + Tn * q] = v[q];
     __syncthreads();
-    const int ll = tid % Lz, kk = tid / Lz, kstep = blockDim.x / Lz;
+    // kk < Tn: the rows kk + Tn*i (i < 8) cover [0, N)
+    const int ll = tid % Lz, kk = tid / Lz;
     if (z0 + ll < g.b3) {
-        cx<T>* dst = SB + ((long)f * g.h1 + kx) * g.n2 * Pz + z0 + ll;
-        for (int ky = kk; ky < N; ky += kstep) dst[(long)ky * Pz] = ldsv[ll * line_pitch(N) + ky];
+        cx<T>* dst = SB + ((long)f * g.h1 + kx) * N * Pz + z0 + ll;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) dst[(long)(kk + Tn * i) * Pz] = ldsv[ll * line_pitch(N) + kk + Tn * i];
     }
 }
 
-template <class T>
+template <class T, int LG>
 __global__ void __launch_bounds__(1024) k_yti(Geo g, const cx<T>* __restrict__ SB, cx<T>* __restrict__ SA,
                                               int Pz, const cx<T>* __restrict__ twb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-    const int N = g.n2, Tn = N >> 3, lgN = 31 - __clz(N);
+    const int lgN = LG > 0 ? LG : 31 - __clz(g.n2), N = 1 << lgN, Tn = N >> 3;
     const int Lz = blockDim.x / Tn;
     const int tid = threadIdx.x, j = tid % Tn, l = tid / Tn;
     const int kx = blockIdx.y, f = blockIdx.z;
     const int z0 = blockIdx.x * Lz, z = z0 + l;
-    const int ll = tid % Lz, kk = tid / Lz, kstep = blockDim.x / Lz;
+    const int ll = tid % Lz, kk = tid / Lz;   // kk < Tn
+    {
+        // all eight loads of this thread in flight before the LDS stores
+        const bool okr = z0 + ll < g.b3;
+        const cx<T>* src = SB + ((long)f * g.h1 + kx) * N * Pz + z0 + ll;
+        cx<T> t[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) t[i] = okr ? src[(long)(kk + Tn * i) * Pz] : cx<T>{T(0), T(0)};
+        lds_ptr<cx<T>> ldsv = as_lds(lds);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) ldsv[ll * line_pitch(N) + kk + Tn * i] = t[i];
+    }
     cx<T>* tw = lds + (long)Lz * line_pitch(N);
     stage_twiddles(tw, twb, N);
-    {
-        lds_ptr<cx<T>> ldsv = as_lds(lds);
-        const bool okr = z0 + ll < g.b3;
-        const cx<T>* src = SB + ((long)f * g.h1 + kx) * g.n2 * Pz + z0 + ll;
-        for (int ky = kk; ky < N; ky += kstep)
-            ldsv[ll * line_pitch(N) + ky] = okr ? src[(long)ky * Pz] : cx<T>{T(0), T(0)};
-    }
     __syncthreads();
     cx<T>* line = lds + l * line_pitch(N);
     lds_ptr<cx<T>> linev = as_lds(line);
@@ -528,14 +560,14 @@ __global__ void __launch_bounds__(1024) k_yti(Geo g, const cx<T>* __restrict__ S
 // Pass 5: transposed load of body rows from SA, c2r along x, epilogue.
 // grid (ceil(b2/Lt), b3), block Tc*Lt; LDS Lt*(Nc+2) complex + reduction.
 // partials: per block NRED doubles at (blockIdx.y*gridDim.x + blockIdx.x)*NRED.
-template <class T, class F>
+template <class T, class F, int LG>
 __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restrict__ SA,
                                                double* __restrict__ partials,
                                                const cx<T>* __restrict__ twb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int NO = F::NOUT;
-    const int Nc = g.Nc, Tc = Nc >> 3, lgNc = 31 - __clz(Nc);
+    const int lgNc = LG > 0 ? LG : 31 - __clz(g.Nc), Nc = 1 << lgNc, Tc = Nc >> 3;
     const int nthr = blockDim.x;
     const int Lt = nthr / Tc;
     const int tid = threadIdx.x, j = tid % Tc, l = tid / Tc;
@@ -546,7 +578,20 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     cx<T>* row = lds + l * pitch;
     cx<T>* twn1 = lds + Lt * pitch;
     stage_twiddles(twn1, twb, g.n1);
-    const int ll = tid % Lt, kk = tid / Lt, kstep = nthr / Lt;
+    // transposed load: thread (ll, kk < Tc) fetches the columns kk + Tc*i
+    // (i < 8) and, for kk == 0, the Nyquist column Nc; the next field's
+    // values are fetched while this field is transformed
+    const int ll = tid % Lt, kk = tid / Lt;
+    const bool okr = (y0 + ll) < g.b2;
+    const cx<T>* src0 = SA + (long)z * g.h1 * g.P2 + y0 + ll;
+    cx<T> pre[9];
+    auto fetch = [&](int o) {
+        const cx<T>* src = src0 + o * g.saf;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) pre[i] = okr ? src[(long)(kk + Tc * i) * g.P2] : cx<T>{T(0), T(0)};
+        pre[8] = (okr && kk == 0) ? src[(long)Nc * g.P2] : cx<T>{T(0), T(0)};
+    };
+    fetch(0);
     T val[NO][16];
     lds_ptr<cx<T>> rowv = as_lds(row);
     lds_ptr<cx<T>> ldsv = as_lds(lds);
@@ -554,12 +599,10 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
         __syncthreads();
-        {
-            const bool okr = (y0 + ll) < g.b2;
-            const cx<T>* src = SA + o * g.saf + (long)z * g.h1 * g.P2 + y0 + ll;
-            for (int kx = kk; kx < g.h1; kx += kstep)
-                ldsv[ll * pitch + kx] = okr ? src[(long)kx * g.P2] : cx<T>{T(0), T(0)};
-        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) ldsv[ll * pitch + kk + Tc * i] = pre[i];
+        if (kk == 0) ldsv[ll * pitch + Nc] = pre[8];
+        if (o + 1 < NO) fetch(o + 1);
         __syncthreads();
         cx<T> v[8];
 #pragma unroll
@@ -578,23 +621,44 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
             val[o][2 * q + 1] = v[q].i;
         }
     }
+    // epilogue over the block's run of body nodes with consecutive threads on
+    // consecutive nodes, the values passing through a flat [Lt][b1] staging
+    // area over the row buffers (node slots per thread as in k_xfwd)
+    constexpr int RN = LG > 0 ? 8 : 16;
+    const long nbase = ((long)z * g.b2 + y0) * g.b1;
+    const int nval = min(Lt, g.b2 - y0) * g.b1;
+    lds_ptr<T> flat = as_lds(reinterpret_cast<T*>(lds));
+    T nv[NO][RN];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        __syncthreads();
+        if (y < g.b2) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int x = 2 * (j + Tc * q) + e;
+                    if (x < g.b1) flat[l * g.b1 + x] = val[o][2 * q + e];
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RN; ++r) {
+            const int e = tid + nthr * r;
+            nv[o][r] = e < nval ? flat[e] : T(0);
+        }
+    }
     double red[F::NRED > 0 ? F::NRED : 1];
 #pragma unroll
     for (int r = 0; r < (F::NRED > 0 ? F::NRED : 1); ++r) red[r] = 0.0;
-    if (y < g.b2) {
-        const long rbase = ((long)z * g.b2 + y) * g.b1;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+    for (int r = 0; r < RN; ++r) {
+        const int e = tid + nthr * r;
+        if (e < nval) {
+            T vv[NO];
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int x = 2 * (j + Tc * q) + e;
-                if (x < g.b1) {
-                    T vv[NO];
-#pragma unroll
-                    for (int o = 0; o < NO; ++o) vv[o] = val[o][2 * q + e];
-                    fin.fin(rbase + x, vv, red);
-                }
-            }
+            for (int o = 0; o < NO; ++o) vv[o] = nv[o][r];
+            fin.fin(nbase + e, vv, red);
         }
     }
     if constexpr (F::NRED > 0) {
