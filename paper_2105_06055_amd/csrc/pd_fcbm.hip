@@ -223,6 +223,7 @@ template <class T, class G, int LG>
 pd_status launch_xfwd_lg(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
     const Geo& g = p->geo;
     const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
+    if (LG > 0 && Tc * Lt != xblock_threads<T>()) return PD_EUNSUPPORTED;
     dim3 grid((g.b2 + Lt - 1) / Lt, g.b3), block(Tc * Lt);
     size_t lds = ((size_t)Lt * row_pitch(g.Nc) + tw_lds_len(g.n1)) * sizeof(cx<T>);
     allow_lds(k_xfwd<T, G, LG>, lds);
@@ -327,6 +328,7 @@ template <class T, class F, int LG>
 pd_status launch_xinv_lg(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st) {
     const Geo& g = p->geo;
     const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
+    if (LG > 0 && Tc * Lt != xblock_threads<T>()) return PD_EUNSUPPORTED;
     dim3 grid((g.b2 + Lt - 1) / Lt, g.b3), block(Tc * Lt);
     size_t lds = ((size_t)Lt * row_pitch(g.Nc) + tw_lds_len(g.n1)) * sizeof(cx<T>);
     size_t red_lds = (size_t)((Tc * Lt + 63) / 64) * 8 * sizeof(double);
@@ -772,9 +774,8 @@ pd_status force_impl(pd_plan p, const T* u, const void* weight, T* L, T* W, hipS
         gB.theta = reinterpret_cast<const T*>(p->theta);
         MulLPSB<T> mB{};
         mB.ka = T(p->ka);
-        FinLin<T, 3, 0, false> fB{};
+        FinLin<T, 3, 0, false, true> fB{};
         fB.c = ctx<T>(p);
-        fB.lps = 1;
         fB.ka = T(p->ka);
         fB.u = u;
         fB.theta = reinterpret_cast<const T*>(p->theta);
@@ -788,9 +789,8 @@ pd_status force_impl(pd_plan p, const T* u, const void* weight, T* L, T* W, hipS
             GenU<T, DD, WK_NONE, false, false, false> gg{};
             gg.c = ctx<T>(p);
             gg.u = const_cast<T*>(u);
-            FinLin<T, DD, 0, false> ff{};
+            FinLin<T, DD, 0, false, false> ff{};
             ff.c = ctx<T>(p);
-            ff.lps = 0;
             ff.u = u;
             ff.L = L;
             return run_chain<T>(p, gg, MulBB<T, DD, false, false>{}, ff, st);
@@ -971,9 +971,8 @@ pd_status lin_apply(pd_plan p, const T* x, T* out, const T* b, hipStream_t st) {
         gB.theta = reinterpret_cast<const T*>(p->theta);
         MulLPSB<T> mB{};
         mB.ka = T(p->ka);
-        FinLin<T, 3, MODE, false> fB{};
+        FinLin<T, 3, MODE, false, true> fB{};
         fB.c = ctx<T>(p);
-        fB.lps = 1;
         fB.ka = T(p->ka);
         fB.u = x;
         fB.theta = reinterpret_cast<const T*>(p->theta);
@@ -986,9 +985,8 @@ pd_status lin_apply(pd_plan p, const T* x, T* out, const T* b, hipStream_t st) {
         GenU<T, DD, WK_NONE, false, false, false> gg{};
         gg.c = ctx<T>(p);
         gg.u = const_cast<T*>(x);
-        FinLin<T, DD, MODE, false> ff{};
+        FinLin<T, DD, MODE, false, false> ff{};
         ff.c = ctx<T>(p);
-        ff.lps = 0;
         ff.u = x;
         ff.L = out;
         ff.b = b;
@@ -1020,9 +1018,9 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, hipSt
         gB.theta = reinterpret_cast<const T*>(p->theta);
         MulLPSB<T> mB{};
         mB.ka = T(p->ka);
-        FinLin<T, 3, 1, ENRED> fB{};
+        FinLin<T, 3, 1, ENRED, true> fB{};
         fB.c = ctx<T>(p);
-        fB.lps = 1; fB.ka = T(p->ka); fB.u = u; fB.theta = reinterpret_cast<const T*>(p->theta);
+        fB.ka = T(p->ka); fB.u = u; fB.theta = reinterpret_cast<const T*>(p->theta);
         fB.v = v; fB.F = F; fB.b = b; fB.c1 = c1; fB.rho = rho;
         return run_chain<T>(p, gB, mB, fB, st, 3);
     }
@@ -1033,9 +1031,9 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, hipSt
             GenU<T, DD, WK_NONE, false, false, true> gg{};
             gg.c = ctx<T>(p);
             gg.u = u; gg.v = v; gg.F = F; gg.w = w; gg.dt = dt; gg.c2 = c2;
-            FinLin<T, DD, 1, ENRED> ff{};
+            FinLin<T, DD, 1, ENRED, false> ff{};
             ff.c = ctx<T>(p);
-            ff.lps = 0; ff.u = u; ff.v = v; ff.F = F; ff.b = b; ff.c1 = c1; ff.rho = rho;
+            ff.u = u; ff.v = v; ff.F = F; ff.b = b; ff.c1 = c1; ff.rho = rho;
             return run_chain<T>(p, gg, MulBB<T, DD, false, false>{}, ff, st);
         }
         if constexpr (DD == 3) {

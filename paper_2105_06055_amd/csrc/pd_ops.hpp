@@ -43,17 +43,13 @@ struct NodeCtx {
     const T* stat;             // static fields [ncs][nb]
 };
 
-// Bond weight phi(x) = chi_B [lambda | s].
-template <class T, int WK>
-__device__ __forceinline__ T node_phi(const NodeCtx<T>& c, long i, const uint8_t* lam, const T* s) {
-    T p = c.chiB[i] ? T(1) : T(0);
-    if constexpr (WK == WK_LAMBDA) p = lam[i] ? p : T(0);
-    if constexpr (WK == WK_SCALE) p *= s[i];
-    return p;
-}
-
 // ============================================================================
-// Generators: gen(i, in[NIN]) for a body node i.
+// Generators.  Each node is handled in two steps so that a pass can issue the
+// loads of a whole group of nodes before the first store of any of them:
+//   Ld ld = load(i)               every load for node i, unconditional
+//   gen(i, ld, in[NIN])           arithmetic, selects, stores, the inputs
+// (all choices are selects; an optional array that is absent is replaced by
+// one that is read anyway at the same index).
 // ============================================================================
 
 // Bond-based / LPS displacement inputs:  phi u_j  [, phi]  [, phi u_i u_j].
@@ -84,29 +80,52 @@ struct GenU {
         }
         return b;
     }
-    __device__ __forceinline__ void gen(long i, T (&in)[NIN]) const {
+    struct Ld {
+        T u[D], v[VV ? D : 1], F[VV ? D : 1], w[VV ? D : 1];
+        uint8_t o[VV ? D : 1];
+        uint8_t chiB, lam;
+        T s, W;
+    };
+    __device__ __forceinline__ Ld load(long i) const {
+        Ld L;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const long k = d * c.nb + i;
+            L.u[d] = u[k];
+            if constexpr (VV) {
+                L.v[d] = v[k];
+                L.F[d] = F[k];
+                L.w[d] = (w ? w : u)[k];
+                L.o[d] = c.chiO[k];
+            }
+        }
+        L.chiB = c.chiB[i];
+        L.lam = (WK == WK_LAMBDA) ? lam_in[i] : uint8_t(1);
+        L.s = (WK == WK_SCALE) ? s[i] : T(1);
+        L.W = (VV && WK == WK_LAMBDA) ? W[i] : T(0);
+        return L;
+    }
+    __device__ __forceinline__ void gen(long i, const Ld& L, T (&in)[NIN]) const {
         T ud[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            T x = u[d * c.nb + i];
+            T x = L.u[d];
             if constexpr (VV) {
-                const long k = d * c.nb + i;
-                x = c.chiO[k] ? x + dt * v[k] + c2 * F[k] : (w ? w[k] : T(0));
-                u[k] = x;
+                x = L.o[d] ? x + dt * L.v[d] + c2 * L.F[d] : (w ? L.w[d] : T(0));
+                u[d * c.nb + i] = x;
             }
             ud[d] = x;
         }
-        T phi;
+        uint8_t l = L.lam;
         if constexpr (VV && WK == WK_LAMBDA) {
-            uint8_t l = lam_in[i];
+            const uint8_t keep = (l != 0 && L.W <= Wc) ? 1 : 0;
             if (fail) {
-                l = (l && W[i] <= Wc) ? 1 : 0;
+                l = keep;
                 lam_out[i] = l;
             }
-            phi = (c.chiB[i] && l) ? T(1) : T(0);
-        } else {
-            phi = node_phi<T, WK>(c, i, lam_in, s);
         }
+        T phi = (L.chiB && l) ? T(1) : T(0);
+        if constexpr (WK == WK_SCALE) phi *= L.s;
 #pragma unroll
         for (int d = 0; d < D; ++d) in[d] = phi * ud[d];
         int o = D;
@@ -127,9 +146,9 @@ struct GenTheta {
     NodeCtx<T> c;
     const T* theta;
     __host__ double nbytes() const { return sizeof(T) + 1.0; }
-    __device__ __forceinline__ void gen(long i, T (&in)[1]) const {
-        in[0] = c.chiB[i] ? theta[i] : T(0);
-    }
+    struct Ld { T th; uint8_t chiB; };
+    __device__ __forceinline__ Ld load(long i) const { return {theta[i], c.chiB[i]}; }
+    __device__ __forceinline__ void gen(long, const Ld& L, T (&in)[1]) const { in[0] = L.chiB ? L.th : T(0); }
 };
 
 // Damage count input: chi_B lambda.
@@ -139,8 +158,10 @@ struct GenPhi {
     NodeCtx<T> c;
     const uint8_t* lam;
     __host__ double nbytes() const { return 2.0; }
-    __device__ __forceinline__ void gen(long i, T (&in)[1]) const {
-        in[0] = (c.chiB[i] && lam[i]) ? T(1) : T(0);
+    struct Ld { uint8_t chiB, lam; };
+    __device__ __forceinline__ Ld load(long i) const { return {c.chiB[i], lam[i]}; }
+    __device__ __forceinline__ void gen(long, const Ld& L, T (&in)[1]) const {
+        in[0] = (L.chiB && L.lam) ? T(1) : T(0);
     }
 };
 
@@ -155,13 +176,28 @@ struct GenAdj {
         const double t = sizeof(T);
         return (2 * D + (u2 ? D : 0)) * t + 1 + (WK == WK_SCALE ? t : 0.0) + (WK == WK_LAMBDA ? 1.0 : 0.0);
     }
-    __device__ __forceinline__ void gen(long i, T (&in)[NIN]) const {
-        T phi = node_phi<T, WK>(c, i, lam, s);
+    struct Ld { T u[D], u2[D], g[D]; uint8_t chiB, lam; T s; };
+    __device__ __forceinline__ Ld load(long i) const {
+        Ld L;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            L.u[d] = u[d * c.nb + i];
+            L.u2[d] = (u2 ? u2 : u)[d * c.nb + i];
+            L.g[d] = g[d * c.nb + i];
+        }
+        L.chiB = c.chiB[i];
+        L.lam = (WK == WK_LAMBDA) ? lam[i] : uint8_t(1);
+        L.s = (WK == WK_SCALE) ? s[i] : T(1);
+        return L;
+    }
+    __device__ __forceinline__ void gen(long, const Ld& L, T (&in)[NIN]) const {
+        T phi = (L.chiB && L.lam) ? T(1) : T(0);
+        if constexpr (WK == WK_SCALE) phi *= L.s;
         T ud[D], gd[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            ud[d] = u[d * c.nb + i] + (u2 ? u2[d * c.nb + i] : T(0));
-            gd[d] = g[d * c.nb + i];
+            ud[d] = L.u[d] + (u2 ? L.u2[d] : T(0));
+            gd[d] = L.g[d];
             in[d] = phi * ud[d];
             in[D + 1 + d] = phi * gd[d];
         }
@@ -181,7 +217,9 @@ struct GenScalar {
     static constexpr int NIN = 1;
     const T* x;
     __host__ double nbytes() const { return sizeof(T); }
-    __device__ __forceinline__ void gen(long i, T (&in)[1]) const { in[0] = x[i]; }
+    struct Ld { T x; };
+    __device__ __forceinline__ Ld load(long i) const { return {x[i]}; }
+    __device__ __forceinline__ void gen(long, const Ld& L, T (&in)[1]) const { in[0] = L.x; }
 };
 
 // ============================================================================
@@ -442,8 +480,11 @@ struct MulTest {
 };
 
 // ============================================================================
-// Epilogues: fin(i, val[NOUT], red[NRED]).  val are the (normalised)
-// convolutions at node i.
+// Epilogues, in two steps like the generators:
+//   Ld ld = load(i)                 every load for node i, unconditional
+//   fin(i, ld, val[NOUT], red)      val are the (normalised) convolutions at
+//                                   node i; arithmetic, selects, stores and
+//                                   the partial sums red[NRED]
 // ============================================================================
 
 // Bond-based force / Verlet finish.
@@ -470,28 +511,57 @@ struct FinBB {
         else r += D * t;
         return r;
     }
-    __device__ __forceinline__ void fin(long i, const T (&val)[NOUT], double* red) const {
-        T phi = node_phi<T, WK>(c, i, lam, s);
-        T ud[D], Gm[nsym(D)];
+    struct Ld {
+        T u[D], G[WPHI ? 1 : nsym(D)];
+        T v[VV ? D : 1], F[VV ? D : 1], b[VV ? D : 1];
+        uint8_t o[VV ? D : 1];
+        uint8_t chiB, lam;
+        T s;
+    };
+    __device__ __forceinline__ Ld load(long i) const {
+        Ld Q;
 #pragma unroll
-        for (int d = 0; d < D; ++d) ud[d] = u[d * c.nb + i];
+        for (int d = 0; d < D; ++d) Q.u[d] = u[d * c.nb + i];
+        if constexpr (!WPHI) {
 #pragma unroll
-        for (int q = 0; q < nsym(D); ++q) Gm[q] = WPHI ? val[D + q] : c.stat[q * c.nb + i];
+            for (int q = 0; q < nsym(D); ++q) Q.G[q] = c.stat[q * c.nb + i];
+        }
+        if constexpr (VV) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const long k = d * c.nb + i;
+                Q.v[d] = v[k];
+                Q.F[d] = F[k];
+                Q.b[d] = (b ? b : F)[k];
+                Q.o[d] = c.chiO[k];
+            }
+        }
+        Q.chiB = c.chiB[i];
+        Q.lam = (WK == WK_LAMBDA) ? lam[i] : uint8_t(1);
+        Q.s = (WK == WK_SCALE) ? s[i] : T(1);
+        return Q;
+    }
+    __device__ __forceinline__ void fin(long i, const Ld& Q, const T (&val)[NOUT], double* red) const {
+        T phi = (Q.chiB && Q.lam) ? T(1) : T(0);
+        if constexpr (WK == WK_SCALE) phi *= Q.s;
+        T Gm[nsym(D)];
+#pragma unroll
+        for (int q = 0; q < nsym(D); ++q) Gm[q] = WPHI ? val[D + q] : Q.G[WPHI ? 0 : q];
         T Li[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             T acc = val[a];
 #pragma unroll
-            for (int bb = 0; bb < D; ++bb) acc -= Gm[symi(D, a, bb)] * ud[bb];
+            for (int bb = 0; bb < D; ++bb) acc -= Gm[symi(D, a, bb)] * Q.u[bb];
             Li[a] = phi * acc;
         }
         if constexpr (ENERGY) {
             T e = val[D + (WPHI ? nsym(D) : 0)];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                e -= T(2) * ud[a] * val[a];
+                e -= T(2) * Q.u[a] * val[a];
 #pragma unroll
-                for (int bb = 0; bb < D; ++bb) e += ud[a] * ud[bb] * Gm[symi(D, a, bb)];
+                for (int bb = 0; bb < D; ++bb) e += Q.u[a] * Q.u[bb] * Gm[symi(D, a, bb)];
             }
             Wout[i] = T(0.5) * phi * e;
         }
@@ -499,16 +569,16 @@ struct FinBB {
 #pragma unroll
             for (int a = 0; a < D; ++a) {
                 const long k = a * c.nb + i;
-                T bk = b ? b[k] : T(0);
+                const T bk = b ? Q.b[a] : T(0);
                 T Fn = Li[a] + bk;
-                T vn = c.chiO[k] ? v[k] + c1 * (F[k] + Fn) : T(0);
+                T vn = Q.o[a] ? Q.v[a] + c1 * (Q.F[a] + Fn) : T(0);
                 v[k] = vn;
                 F[k] = Fn;
                 if constexpr (ENRED) {
                     red[0] += 0.5 * double(rho) * double(vn) * double(vn);
-                    red[1] += -0.5 * double(ud[a]) * double(Li[a]);
-                    red[2] += -double(bk) * double(ud[a]);
-                    if (c.chiO[k]) red[3] += double(Fn) * double(Fn);
+                    red[1] += -0.5 * double(Q.u[a]) * double(Li[a]);
+                    red[2] += -double(bk) * double(Q.u[a]);
+                    red[3] += Q.o[a] ? double(Fn) * double(Fn) : 0.0;
                 }
             }
         } else {
@@ -526,16 +596,24 @@ struct FinTheta {
     NodeCtx<T> c;
     const T* u; T* theta;
     __host__ double nbytes() const { return 8.0 * sizeof(T) + 1.0; }
-    __device__ __forceinline__ void fin(long i, const T (&val)[1], double*) const {
-        T m = c.stat[9 * c.nb + i];
-        T th = T(0);
-        if (c.chiB[i] && m != T(0)) {
-            T acc = val[0];
+    struct Ld { T m, g[3], u[3]; uint8_t chiB; };
+    __device__ __forceinline__ Ld load(long i) const {
+        Ld Q;
+        Q.m = c.stat[9 * c.nb + i];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) acc -= c.stat[(6 + d) * c.nb + i] * u[d * c.nb + i];
-            th = T(3) / m * acc;
+        for (int d = 0; d < 3; ++d) {
+            Q.g[d] = c.stat[(6 + d) * c.nb + i];
+            Q.u[d] = u[d * c.nb + i];
         }
-        theta[i] = th;
+        Q.chiB = c.chiB[i];
+        return Q;
+    }
+    __device__ __forceinline__ void fin(long i, const Ld& Q, const T (&val)[1], double*) const {
+        T acc = val[0];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc -= Q.g[d] * Q.u[d];
+        const bool on = Q.chiB && Q.m != T(0);
+        theta[i] = on ? T(3) / (on ? Q.m : T(1)) * acc : T(0);
     }
 };
 
@@ -544,60 +622,88 @@ struct FinTheta {
 // MODE 0: write L;  MODE 1: Verlet finish (as FinBB);  MODE 2: CG operator
 // Ap = -chi_O L with partial sum p.Ap;  MODE 3: FP64 residual
 // r = chi_O (L + b) with partial |r|^2.
-template <class T, int D, int MODE, bool ENRED>
+template <class T, int D, int MODE, bool ENRED, bool LPS>
 struct FinLin {
-    // Shared by bond-based (static G) and LPS for the solver / VV modes.
+    // Shared by bond-based (static G, LPS = false) and LPS for the solver / VV modes.
     static constexpr int NOUT = D;
     static constexpr int NRED = (MODE == 1) ? (ENRED ? 4 : 0) : ((MODE >= 2) ? 1 : 0);
     NodeCtx<T> c;
-    int lps;
     T ka;
     const T* u; const T* theta;
     T* L; T* v; T* F; const T* b;
     T c1, rho;
     __host__ double nbytes() const {
         const double t = sizeof(T);
-        double r = D * t + 1 + nsym(D) * t + (lps ? (1 + D) * t : 0.0);
+        double r = D * t + 1 + nsym(D) * t + (LPS ? (1 + D) * t : 0.0);
         if (MODE == 0) r += D * t;
         else if (MODE == 1) r += D * (4 * t + 1) + (b ? D * t : 0.0);
         else if (MODE == 2) r += D * (t + 1);
         else r += D * (2 * t + 1);
         return r;
     }
-    __device__ __forceinline__ void fin(long i, const T (&val)[D], double* red) const {
-        T chi = c.chiB[i] ? T(1) : T(0);
-        T ud[D];
+    static constexpr bool HAS_O = MODE >= 1;
+    struct Ld {
+        T u[D], G[nsym(D)], g[LPS ? D : 1], th;
+        T v[MODE == 1 ? D : 1], F[MODE == 1 ? D : 1], b[(MODE == 1 || MODE == 3) ? D : 1];
+        uint8_t o[HAS_O ? D : 1];
+        uint8_t chiB;
+    };
+    __device__ __forceinline__ Ld load(long i) const {
+        Ld Q;
+        Q.chiB = c.chiB[i];
 #pragma unroll
-        for (int d = 0; d < D; ++d) ud[d] = u[d * c.nb + i];
-        T th = lps ? theta[i] : T(0);
+        for (int d = 0; d < D; ++d) Q.u[d] = u[d * c.nb + i];
+#pragma unroll
+        for (int q = 0; q < nsym(D); ++q) Q.G[q] = c.stat[q * c.nb + i];
+        Q.th = T(0);
+        if constexpr (LPS) {
+            Q.th = theta[i];
+#pragma unroll
+            for (int d = 0; d < D; ++d) Q.g[d] = c.stat[(6 + d) * c.nb + i];
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const long k = d * c.nb + i;
+            if constexpr (HAS_O) Q.o[d] = c.chiO[k];
+            if constexpr (MODE == 1) {
+                Q.v[d] = v[k];
+                Q.F[d] = F[k];
+                Q.b[d] = (b ? b : F)[k];
+            }
+            if constexpr (MODE == 3) Q.b[d] = b[k];
+        }
+        return Q;
+    }
+    __device__ __forceinline__ void fin(long i, const Ld& Q, const T (&val)[D], double* red) const {
+        const T chi = Q.chiB ? T(1) : T(0);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             T acc = val[a];
 #pragma unroll
-            for (int bb = 0; bb < D; ++bb) acc -= c.stat[symi(D, a, bb) * c.nb + i] * ud[bb];
-            if (lps) acc += ka * th * c.stat[(6 + a) * c.nb + i];
+            for (int bb = 0; bb < D; ++bb) acc -= Q.G[symi(D, a, bb)] * Q.u[bb];
+            if constexpr (LPS) acc += ka * Q.th * Q.g[a];
             T La = chi * acc;
             const long k = a * c.nb + i;
             if constexpr (MODE == 0) {
                 L[k] = La;
             } else if constexpr (MODE == 1) {
-                T bk = b ? b[k] : T(0);
+                const T bk = b ? Q.b[a] : T(0);
                 T Fn = La + bk;
-                T vn = c.chiO[k] ? v[k] + c1 * (F[k] + Fn) : T(0);
+                T vn = Q.o[a] ? Q.v[a] + c1 * (Q.F[a] + Fn) : T(0);
                 v[k] = vn;
                 F[k] = Fn;
                 if constexpr (ENRED) {
                     red[0] += 0.5 * double(rho) * double(vn) * double(vn);
-                    red[1] += -0.5 * double(ud[a]) * double(La);
-                    red[2] += -double(bk) * double(ud[a]);
-                    if (c.chiO[k]) red[3] += double(Fn) * double(Fn);
+                    red[1] += -0.5 * double(Q.u[a]) * double(La);
+                    red[2] += -double(bk) * double(Q.u[a]);
+                    red[3] += Q.o[a] ? double(Fn) * double(Fn) : 0.0;
                 }
             } else if constexpr (MODE == 2) {
-                T ap = c.chiO[k] ? -La : T(0);
+                T ap = Q.o[a] ? -La : T(0);
                 L[k] = ap;
-                red[0] += double(ud[a]) * double(ap);
+                red[0] += double(Q.u[a]) * double(ap);
             } else {
-                T r = c.chiO[k] ? La + b[k] : T(0);
+                T r = Q.o[a] ? La + Q.b[a] : T(0);
                 L[k] = r;
                 red[0] += double(r) * double(r);
             }
@@ -614,11 +720,13 @@ struct FinCount {
     int beta_comp;
     const uint8_t* lam; T* d;
     __host__ double nbytes() const { return 2.0 + 2.0 * sizeof(T); }
-    __device__ __forceinline__ void fin(long i, const T (&val)[1], double*) const {
-        int phi = (c.chiB[i] && lam[i]) ? 1 : 0;
+    struct Ld { T st; uint8_t chiB, lam; };
+    __device__ __forceinline__ Ld load(long i) const { return {c.stat[beta_comp * c.nb + i], c.chiB[i], lam[i]}; }
+    __device__ __forceinline__ void fin(long i, const Ld& Q, const T (&val)[1], double*) const {
+        int phi = (Q.chiB && Q.lam) ? 1 : 0;
         long cnt = (long)rint(val[0]) + phi;
-        long beta = (long)rint(c.stat[beta_comp * c.nb + i]) + (c.chiB[i] ? 1 : 0);
-        d[i] = c.chiB[i] ? T(1.0 - double(phi * cnt) / double(beta)) : T(0);
+        long beta = (long)rint(Q.st) + (Q.chiB ? 1 : 0);
+        d[i] = Q.chiB ? T(1.0 - double(phi * cnt) / double(beta > 0 ? beta : 1)) : T(0);
     }
 };
 
@@ -640,13 +748,29 @@ struct FinAdj {
         return (2 * D + (u2 ? D : 0)) * t + 1 + (WK == WK_SCALE ? t : 0.0) + (ubar ? D * t : 0.0) +
                (wbar ? (accumulate ? 2 : 1) * t : 0.0);
     }
-    __device__ __forceinline__ void fin(long i, const T (&val)[NOUT], double*) const {
-        T phi = node_phi<T, WK>(c, i, lam, s);
+    struct Ld { T u[D], u2[D], g[D]; uint8_t chiB, lam; T s, wb; };
+    __device__ __forceinline__ Ld load(long i) const {
+        Ld Q;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            Q.u[d] = u[d * c.nb + i];
+            Q.u2[d] = (u2 ? u2 : u)[d * c.nb + i];
+            Q.g[d] = g[d * c.nb + i];
+        }
+        Q.chiB = c.chiB[i];
+        Q.lam = (WK == WK_LAMBDA) ? lam[i] : uint8_t(1);
+        Q.s = (WK == WK_SCALE) ? s[i] : T(1);
+        Q.wb = (wbar && accumulate) ? wbar[i] : T(0);
+        return Q;
+    }
+    __device__ __forceinline__ void fin(long i, const Ld& Q, const T (&val)[NOUT], double*) const {
+        T phi = (Q.chiB && Q.lam) ? T(1) : T(0);
+        if constexpr (WK == WK_SCALE) phi *= Q.s;
         T ud[D], gd[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            ud[d] = u[d * c.nb + i] + (u2 ? u2[d * c.nb + i] : T(0));
-            gd[d] = g[d * c.nb + i];
+            ud[d] = Q.u[d] + (u2 ? Q.u2[d] : T(0));
+            gd[d] = Q.g[d];
         }
         T pb = -val[2 * D + nsym(D)];
 #pragma unroll
@@ -663,8 +787,8 @@ struct FinAdj {
             pb += gd[a] * acc_c + ud[a] * val[D + nsym(D) + a];
         }
         if (wbar) {
-            T add = c.chiB[i] ? wscale * pb : T(0);
-            wbar[i] = accumulate ? wbar[i] + add : add;
+            T add = Q.chiB ? wscale * pb : T(0);
+            wbar[i] = accumulate ? Q.wb + add : add;
         }
     }
 };
@@ -675,7 +799,9 @@ struct FinScalar {
     static constexpr int NOUT = 1, NRED = 0;
     T* out;
     __host__ double nbytes() const { return sizeof(T); }
-    __device__ __forceinline__ void fin(long i, const T (&val)[1], double*) const { out[i] = val[0]; }
+    struct Ld {};
+    __device__ __forceinline__ Ld load(long) const { return {}; }
+    __device__ __forceinline__ void fin(long i, const Ld&, const T (&val)[1], double*) const { out[i] = val[0]; }
 };
 
 }  // namespace pdk

@@ -37,6 +37,14 @@ __host__ __device__ constexpr int row_pitch(int Nc) { return (fft_lds_len(Nc) + 
 // LDS pitch of an N-point line used by the y and last-axis passes.
 __host__ __device__ constexpr int line_pitch(int N) { return (fft_lds_len(N) + 1) | 1; }
 
+// Block size of the specialised (LG > 0, Nc = 256) x passes: 16 rows of 32
+// threads in FP32, 8 rows in FP64.
+template <class T>
+__host__ __device__ constexpr int xblock_threads() { return sizeof(T) == 4 ? 512 : 256; }
+
+// Body nodes whose loads the x passes issue together (see k_xfwd).
+constexpr int NODE_GROUP = 4;
+
 struct Geo {
     int dim;
     int n1, n2, n3;     // FFT grid
@@ -84,7 +92,7 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int NF = G::NIN;
     const int lgNc = LG > 0 ? LG : 31 - __clz(g.Nc), Nc = 1 << lgNc, Tc = Nc >> 3;
-    const int nthr = blockDim.x;
+    const int nthr = LG > 0 ? xblock_threads<T>() : (int)blockDim.x;
     const int Lt = nthr / Tc;
     const int tid = threadIdx.x, j = tid % Tc, l = tid / Tc;
     const int z = blockIdx.y;
@@ -103,16 +111,33 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
     const long nbase = ((long)z * g.b2 + y0) * g.b1;
     const int nval = min(Lt, g.b2 - y0) * g.b1;
     T gv[NF][RN];
+    // Node slots in groups of NODE_GROUP: all loads of a group are issued
+    // before its first store (a store may alias any later load, so a
+    // read-modify-write generator would otherwise wait out one memory latency
+    // per slot).  A full block takes a branch-free path.
+    auto run_gen = [&](auto full) {
 #pragma unroll
-    for (int r = 0; r < RN; ++r) {
-        const int e = tid + nthr * r;
-        T a[NF];
+        for (int r0 = 0; r0 < RN; r0 += NODE_GROUP) {
+            typename G::Ld ld[NODE_GROUP];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) a[f] = T(0);
-        if (e < nval) gen.gen(nbase + e, a);
+            for (int q = 0; q < NODE_GROUP; ++q) {
+                const int e = tid + nthr * (r0 + q);
+                if (decltype(full)::value || e < nval) ld[q] = gen.load(nbase + e);
+            }
 #pragma unroll
-        for (int f = 0; f < NF; ++f) gv[f][r] = a[f];
-    }
+            for (int q = 0; q < NODE_GROUP; ++q) {
+                const int e = tid + nthr * (r0 + q);
+                T a[NF];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) a[f] = T(0);
+                if (decltype(full)::value || e < nval) gen.gen(nbase + e, ld[q], a);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) gv[f][r0 + q] = a[f];
+            }
+        }
+    };
+    if (nval == RN * nthr) run_gen(std::true_type{});
+    else run_gen(std::false_type{});
     // twiddles of length n1 in LDS after the rows; W_Nc^e = W_n1^(2e)
     cx<T>* twn1 = lds + Lt * pitch;
     stage_twiddles(twn1, twb, g.n1);
@@ -568,7 +593,7 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int NO = F::NOUT;
     const int lgNc = LG > 0 ? LG : 31 - __clz(g.Nc), Nc = 1 << lgNc, Tc = Nc >> 3;
-    const int nthr = blockDim.x;
+    const int nthr = LG > 0 ? xblock_threads<T>() : (int)blockDim.x;
     const int Lt = nthr / Tc;
     const int tid = threadIdx.x, j = tid % Tc, l = tid / Tc;
     const int z = blockIdx.y;
@@ -651,16 +676,29 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     double red[F::NRED > 0 ? F::NRED : 1];
 #pragma unroll
     for (int r = 0; r < (F::NRED > 0 ? F::NRED : 1); ++r) red[r] = 0.0;
+    auto run_fin = [&](auto full) {
 #pragma unroll
-    for (int r = 0; r < RN; ++r) {
-        const int e = tid + nthr * r;
-        if (e < nval) {
-            T vv[NO];
+        for (int r0 = 0; r0 < RN; r0 += NODE_GROUP) {
+            typename F::Ld ld[NODE_GROUP];
 #pragma unroll
-            for (int o = 0; o < NO; ++o) vv[o] = nv[o][r];
-            fin.fin(nbase + e, vv, red);
+            for (int q = 0; q < NODE_GROUP; ++q) {
+                const int e = tid + nthr * (r0 + q);
+                if (decltype(full)::value || e < nval) ld[q] = fin.load(nbase + e);
+            }
+#pragma unroll
+            for (int q = 0; q < NODE_GROUP; ++q) {
+                const int e = tid + nthr * (r0 + q);
+                if (decltype(full)::value || e < nval) {
+                    T vv[NO];
+#pragma unroll
+                    for (int o = 0; o < NO; ++o) vv[o] = nv[o][r0 + q];
+                    fin.fin(nbase + e, ld[q], vv, red);
+                }
+            }
         }
-    }
+    };
+    if (nval == RN * nthr) run_fin(std::true_type{});   // branch-free, as in k_xfwd
+    else run_fin(std::false_type{});
     if constexpr (F::NRED > 0) {
         __syncthreads();
         double* sm = reinterpret_cast<double*>(smem_raw);
