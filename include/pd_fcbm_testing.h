@@ -23,12 +23,19 @@ extern "C" {
  * Synchronises the stream. */
 pd_status pd_test_conv(pd_plan plan, const void* x, const int* shift, int parity, void* out, void* stream);
 
-/* Kernel selection for A/B tests: generic_only != 0 makes every later call on
- * `plan` (and on its FP32 operator, for PD_PLAN_MIXED plans) use the generic
- * runtime-length last-axis kernel instead of the specialised one (512-point
- * lines, 4 taps).  Both compute the same multiplier; results agree to
- * rounding.  PD_EINVAL for a null plan. */
-pd_status pd_test_set_generic(pd_plan plan, int generic_only);
+/* Last-axis kernel selection for A/B tests (every later call on `plan`, and
+ * on its FP32 operator for PD_PLAN_MIXED plans):
+ *   PD_LASTAXIS_AUTO         direct line correlation when the horizon spans at
+ *                            most 4 spacings along the last axis (default),
+ *                            else the transform form
+ *   PD_LASTAXIS_FFT          transform along the last axis, spectral multiply,
+ *                            inverse transform (specialised kernel for
+ *                            512-point lines with 4 taps, else runtime length)
+ *   PD_LASTAXIS_FFT_GENERIC  transform form, runtime-length kernel only
+ * All compute the same correlation; results agree to rounding.  PD_EINVAL
+ * for a null plan or an unknown mode. */
+enum { PD_LASTAXIS_AUTO = 0, PD_LASTAXIS_FFT = 1, PD_LASTAXIS_FFT_GENERIC = 2 };
+pd_status pd_test_set_lastaxis(pd_plan plan, int mode);
 
 #ifdef __cplusplus
 }

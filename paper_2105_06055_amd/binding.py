@@ -67,7 +67,7 @@ class SolveInfo(C.Structure):
 
 EXPORTS = ["pd_plan_create", "pd_plan_destroy", "pd_plan_query", "pd_force", "pd_force_adjoint",
            "pd_verlet_step", "pd_verlet_adjoint", "pd_static_solve", "pd_damage_index",
-           "pd_status_str", "pd_test_conv", "pd_test_set_generic"]
+           "pd_status_str", "pd_test_conv", "pd_test_set_lastaxis"]
 
 _lib = None
 
@@ -98,7 +98,7 @@ def lib():
     L.pd_status_str.argtypes = [C.c_int]
     L.pd_status_str.restype = C.c_char_p
     L.pd_test_conv.argtypes = [vp, vp, C.POINTER(C.c_int), C.c_int, vp, vp]
-    L.pd_test_set_generic.argtypes = [vp, C.c_int]
+    L.pd_test_set_lastaxis.argtypes = [vp, C.c_int]
     for name in EXPORTS:
         if name not in ("pd_plan_destroy", "pd_status_str"):
             getattr(L, name).restype = C.c_int
@@ -275,9 +275,13 @@ class Plan:
         _check(lib().pd_test_conv(self._h, _ptr(x), sh, int(parity), _ptr(out), _stream()), "pd_test_conv")
         return out
 
-    def set_generic(self, generic_only=True):
-        """Force the generic last-axis kernel (A/B tests of the specialised one)."""
-        _check(lib().pd_test_set_generic(self._h, int(bool(generic_only))), "pd_test_set_generic")
+    LASTAXIS = {"auto": 0, "fft": 1, "fft_generic": 2}
+
+    def set_lastaxis(self, mode="auto"):
+        """Last-axis kernel choice (A/B tests): 'auto' (direct line
+        correlation for short horizons), 'fft' (transform + spectral
+        multiply, specialised where it applies) or 'fft_generic'."""
+        _check(lib().pd_test_set_lastaxis(self._h, self.LASTAXIS[mode]), "pd_test_set_lastaxis")
 
     def close(self):
         if getattr(self, "_h", None):

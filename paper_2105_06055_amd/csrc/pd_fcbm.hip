@@ -38,15 +38,17 @@ constexpr double kPi = 3.14159265358979323846;
 // ---------------------------------------------------------------- plan kernels
 
 // Partial spectra ("taps") of the kernel components, FP64 accumulation:
-//   B_c[t](k') = (t ? 2 : 1) / Nfft * sum_{o in S, o_last = t} K_c(o) prod_{d<last} trig_{p_cd}(2 pi k_d o_d / n_d)
+//   B_c[t](k') = sc_t * sum_{o in S, o_last = t} K_c(o) prod_{d<last} trig_{p_cd}(2 pi k_d o_d / n_d)
 // with trig = cos for even and sin for odd axes (Eq. 56-58: the kernel
 // spectrum as a quadrature sum over the horizon, split along the last axis).
+// Transform convention (spectral multiply): sc_0 = 1/Nfft, sc_t = 2/Nfft;
+// direct convention (line correlation): sc_t = n_last/Nfft for every t.
 // Layout [k' (line)][component][tap]: the taps of one line are contiguous.
 template <class T>
 __global__ void k_taps(int dim, int n1, int n2, int h1, long NP, int ntap, int ns,
                        const int* __restrict__ offs, const double* __restrict__ kval, int kstride,
                        int nct, const uint8_t* __restrict__ par, const double* __restrict__ tw64,
-                       double inv_nfft, T* __restrict__ taps) {
+                       double sc0, double sc1, T* __restrict__ taps) {
     long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= NP * ntap) return;
     const long p = idx % NP;
@@ -79,7 +81,7 @@ __global__ void k_taps(int dim, int n1, int n2, int h1, long NP, int ntap, int n
             acc[c] += kval[(long)s * kstride + c] * f;
         }
     }
-    const double sc = (t ? 2.0 : 1.0) * inv_nfft;
+    const double sc = t ? sc1 : sc0;
     for (int c = 0; c < nct; ++c) taps[((long)p * nct + c) * ntap + t] = T(acc[c] * sc);
 }
 
@@ -242,17 +244,44 @@ pd_status launch_xfwd(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
     return launch_xfwd_lg<T, G, 0>(p, gen, SA, st);
 }
 
-// Last-axis multiply pass over contiguous lines.  Lines of 512 points with
-// 4 taps (horizon of 3 grid spacings along the last axis) take the
-// specialised kernel; everything else the generic one.
+// Last-axis pass over contiguous lines.  Default: direct line correlation
+// (taps_d, horizons up to 4 spacings along the last axis); otherwise the
+// FFT-multiply-FFT form (taps), specialised for 512-point lines with 4 taps
+// or with runtime lengths.
+template <class T, class M, int NT>
+pd_status launch_lastconv(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, const T* taps_d, int nct,
+                          hipStream_t st) {
+    // one wavefront per line, four lines per block; no LDS; line starts must be
+    // 16-point aligned (the pitches of SA and SB are)
+    if ((ln.pitch & 15) || (ln.fstride & 15)) return PD_EINVAL;
+    const int Lw = 4;
+    dim3 grid((unsigned)((ln.nlines + Lw - 1) / Lw)), block(64 * Lw);
+    hipLaunchKernelGGL((k_lastconv<T, M, NT>), grid, block, 0, st, ln, mul, S, taps_d, nct);
+    return PD_OK;
+}
+
 template <class T, class M>
-pd_status launch_lastmul(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, const T* taps, int ntap, int nct,
-                         uint32_t oddmask, hipStream_t st) {
+pd_status launch_lastmul(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, const T* taps, const T* taps_d,
+                         int ntap, int nct, uint32_t oddmask, hipStream_t st) {
     const int Tn = ln.N / 8;
     ProfScope ps(p, st);
-    bool fast = false;
-    if constexpr (!M::RT_ODD) fast = (ln.N == 512 && ntap == 4 && p->fast_lastmul);
-    if (fast) {
+    int path = 2;   // 0 direct, 1 specialised FFT, 2 generic FFT
+    if constexpr (!M::RT_ODD) {
+        if (p->lastaxis == PD_LASTAXIS_AUTO && taps_d && ntap >= 2 && ntap <= 5) path = 0;
+        else if (p->lastaxis != PD_LASTAXIS_FFT_GENERIC && ln.N == 512 && ntap == 4) path = 1;
+    }
+    if (path == 0) {
+        if constexpr (!M::RT_ODD) {
+            pd_status s = PD_OK;
+            switch (ntap) {
+                case 2: s = launch_lastconv<T, M, 2>(p, ln, mul, S, taps_d, nct, st); break;
+                case 3: s = launch_lastconv<T, M, 3>(p, ln, mul, S, taps_d, nct, st); break;
+                case 4: s = launch_lastconv<T, M, 4>(p, ln, mul, S, taps_d, nct, st); break;
+                default: s = launch_lastconv<T, M, 5>(p, ln, mul, S, taps_d, nct, st); break;
+            }
+            PD_TRY(s);
+        }
+    } else if (path == 1) {
         if constexpr (!M::RT_ODD) {
             constexpr int LG = 9, NT = 4;
             const int Lw = 4;
@@ -366,8 +395,10 @@ pd_status run_chain(pd_plan p, const G& gen, const M& mul, const F& fin, hipStre
                     uint32_t oddmask = 0xffffffffu) {
     static_assert(M::NOUT == F::NOUT, "multiplier/epilogue mismatch");
     const Geo& g = p->geo;
+    const T* taps_d = nullptr;   // direct-convention taps (plan tables only)
     if (!taps) {
         taps = reinterpret_cast<const T*>(p->taps);
+        taps_d = reinterpret_cast<const T*>(p->taps_d);
         ntap = p->ntap;
         nct = p->nct;
         oddmask = p->oddmask;
@@ -377,12 +408,12 @@ pd_status run_chain(pd_plan p, const G& gen, const M& mul, const F& fin, hipStre
     if (g.dim == 2) {
         if (G::NIN != M::NIN) return PD_EINVAL;
         Lines ln{(long)g.h1, (long)g.P2, g.saf, g.b2, g.n2, 0};
-        PD_TRY(launch_lastmul<T>(p, ln, mul, SAp<T>(p), taps, ntap, nct, oddmask, st));
+        PD_TRY(launch_lastmul<T>(p, ln, mul, SAp<T>(p), taps, taps_d, ntap, nct, oddmask, st));
     } else {
         if (sb_off + G::NIN > p->sbf_cap || M::NIN > p->sbf_cap || out_off + M::NOUT > p->sbf_cap) return PD_EINVAL;
         PD_TRY((launch_ytrans<T, -1>(p, G::NIN, sb_off, st)));
         Lines ln{(long)g.h1 * g.n2, (long)p->Pz, p->sbf, g.b3, g.n3, out_off};
-        PD_TRY(launch_lastmul<T>(p, ln, mul, SBp<T>(p), taps, ntap, nct, oddmask, st));
+        PD_TRY(launch_lastmul<T>(p, ln, mul, SBp<T>(p), taps, taps_d, ntap, nct, oddmask, st));
         PD_TRY((launch_ytrans<T, 1>(p, M::NOUT, out_off, st)));
     }
     PD_TRY(launch_xinv<T>(p, fin, SAp<T>(p), st));
@@ -544,12 +575,18 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
     const Geo& g = p->geo;
     const long NP = (D == 2) ? (long)g.h1 : (long)g.h1 * g.n2;
     HIP_TRY(hipMalloc(&p->taps, sizeof(T) * NP * p->ntap * nct));
-    p->bytes += sizeof(T) * NP * p->ntap * nct;
+    HIP_TRY(hipMalloc(&p->taps_d, sizeof(T) * NP * p->ntap * nct));
+    p->bytes += 2 * sizeof(T) * NP * p->ntap * nct;
     {
         long n = NP * p->ntap;
+        const double inv = 1.0 / (double)p->nfft, nl = (double)(D == 2 ? g.n2 : g.n3);
         hipLaunchKernelGGL((k_taps<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, D, g.n1, g.n2, g.h1, NP,
                            p->ntap, ns, p->offs_dev, p->kval_dev, ncs, nct, par_dev, p->tw64,
-                           1.0 / (double)p->nfft, reinterpret_cast<T*>(p->taps));
+                           inv, 2.0 * inv, reinterpret_cast<T*>(p->taps));
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL((k_taps<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, D, g.n1, g.n2, g.h1, NP,
+                           p->ntap, ns, p->offs_dev, p->kval_dev, ncs, nct, par_dev, p->tw64,
+                           nl * inv, nl * inv, reinterpret_cast<T*>(p->taps_d));
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipMalloc(&p->stat, sizeof(T) * p->nb * ncs));
@@ -565,7 +602,7 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
 void plan_free(pd_plan p) {
     if (!p) return;
     if (p->stream0) (void)hipStreamSynchronize(p->stream0);
-    void* bufs[] = {p->tw, p->tw64, p->taps, p->stat, p->chiB, p->chiO, p->SA, p->SB, p->theta,
+    void* bufs[] = {p->tw, p->tw64, p->taps, p->taps_d, p->stat, p->chiB, p->chiO, p->SA, p->SB, p->theta,
                     p->vtmp, p->vtmp2, p->partials, p->red, p->offs_dev, p->kval_dev};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -686,7 +723,7 @@ pd_status plan_create_impl(const pd_grid* grid, const pd_horizon* hz, const pd_k
     }
     pd_plan p = new pd_plan_s();
     std::memset(p, 0, sizeof(*p));
-    p->fast_lastmul = true;
+    p->lastaxis = PD_LASTAXIS_AUTO;
     p->dim = D;
     for (int d = 0; d < 3; ++d) {
         p->n[d] = (int)grid->fft_n[d];
@@ -1374,7 +1411,7 @@ pd_status test_conv_impl(pd_plan p, const T* x, const int* sh, int parity, T* ou
         (void)hipMemcpyAsync(pd, par, 3, hipMemcpyHostToDevice, st);
         long nn = NP * ntap;
         hipLaunchKernelGGL((k_taps<T>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, D, g.n1, g.n2, g.h1, NP, ntap,
-                           ns, od, kd, 1, 1, pd, p->tw64, 1.0 / (double)p->nfft, taps);
+                           ns, od, kd, 1, 1, pd, p->tw64, 1.0 / (double)p->nfft, 2.0 / (double)p->nfft, taps);
         s = pdh::check(hipGetLastError());
     }
     if (s == PD_OK) {
@@ -1543,10 +1580,10 @@ pd_status pd_test_conv(pd_plan p, const void* x, const int* shift, int parity, v
     return test_conv_impl<double>(p, (const double*)x, shift, parity, (double*)out, S_(stream));
 }
 
-pd_status pd_test_set_generic(pd_plan p, int generic_only) {
-    if (!p) return PD_EINVAL;
-    p->fast_lastmul = !generic_only;
-    if (p->sub32) p->sub32->fast_lastmul = !generic_only;
+pd_status pd_test_set_lastaxis(pd_plan p, int mode) {
+    if (!p || mode < PD_LASTAXIS_AUTO || mode > PD_LASTAXIS_FFT_GENERIC) return PD_EINVAL;
+    p->lastaxis = mode;
+    if (p->sub32) p->sub32->lastaxis = mode;
     return PD_OK;
 }
 

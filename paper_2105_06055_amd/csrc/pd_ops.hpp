@@ -233,6 +233,16 @@ __device__ __forceinline__ cx<T> kmul(T k, cx<T> a) { return {k * a.r, k * a.i};
 template <class T>
 __device__ __forceinline__ cx<T> kmuli(T k, cx<T> a) { return {-k * a.i, k * a.r}; }
 
+// One term of a multiplier, for the direct last-axis pass: output O takes
+// coef * i^ipow * [ka] * (component c applied to input J).  coef == 0: none.
+struct DTerm {
+    int c, coef, ipow;
+    bool ka;
+};
+__host__ __device__ constexpr bool sym_diag(int D, int c) {
+    return c == 0 || (D == 2 ? c == 2 : (c == 3 || c == 5));
+}
+
 // Bond-based: conv_i = sum_j M[C_ij] U_j; [G_c = M[C_c] Phi]; [E = sum_c m_c M[C_c] F_c]
 // with M[C_ij] = K (i == j) or -K (i != j: two odd axes, i^2 = -1).
 template <class T, int D, bool WPHI, bool ENERGY>
@@ -243,6 +253,15 @@ struct MulBB {
     // components odd along the last axis (y in 2D: C_xy; z in 3D: C_xz, C_yz)
     static constexpr bool RT_ODD = false;
     static constexpr uint32_t ODD = (D == 2) ? (1u << 1) : ((1u << 2) | (1u << 4));
+    __device__ __forceinline__ T ka_value() const { return T(0); }
+    __host__ __device__ static constexpr DTerm dterm(int O, int J) {
+        if (O < D) return J < D ? DTerm{symi(D, O, J), O == J ? 1 : -1, 0, false} : DTerm{0, 0, 0, false};
+        if (WPHI && O < D + nsym(D)) return J == D ? DTerm{O - D, sym_diag(D, O - D) ? 1 : -1, 0, false}
+                                                   : DTerm{0, 0, 0, false};
+        const int ib = D + (WPHI ? 1 : 0);
+        if (J < ib || J >= ib + nsym(D)) return DTerm{0, 0, 0, false};
+        return DTerm{J - ib, sym_diag(D, J - ib) ? 1 : -2, 0, false};
+    }
     // components output O depends on
     template <int O>
     __host__ __device__ static constexpr uint32_t need() {
@@ -322,6 +341,8 @@ struct MulLPSA {
     static constexpr int NIN = 3, NOUT = 1, C0 = 6, NC = 3;
     static constexpr bool RT_ODD = false;
     static constexpr uint32_t ODD = (1u << 2) | (1u << 4) | (1u << 8);
+    __device__ __forceinline__ T ka_value() const { return T(0); }
+    __host__ __device__ static constexpr DTerm dterm(int, int J) { return DTerm{J, 1, 1, false}; }
     template <int O>
     __host__ __device__ static constexpr uint32_t need() { return 7u; }
     template <int O>
@@ -344,6 +365,10 @@ struct MulLPSB {
     static constexpr int NIN = 4, NOUT = 3, C0 = 0, NC = 9;
     static constexpr bool RT_ODD = false;
     static constexpr uint32_t ODD = (1u << 2) | (1u << 4) | (1u << 8);
+    __device__ __forceinline__ T ka_value() const { return ka; }
+    __host__ __device__ static constexpr DTerm dterm(int O, int J) {
+        return J < 3 ? DTerm{symi(3, O, J), O == J ? 1 : -1, 0, false} : DTerm{6 + O, 1, 1, true};
+    }
     T ka;
     template <int O>
     __host__ __device__ static constexpr uint32_t need() {
@@ -379,6 +404,8 @@ struct MulCount {
     static constexpr int NIN = 1, NOUT = 1, C0 = nsym(D), NC = 1;
     static constexpr bool RT_ODD = false;
     static constexpr uint32_t ODD = 0u;
+    __device__ __forceinline__ T ka_value() const { return T(0); }
+    __host__ __device__ static constexpr DTerm dterm(int, int) { return DTerm{0, 1, 0, false}; }
     template <int O>
     __host__ __device__ static constexpr uint32_t need() { return 1u; }
     template <int O>
@@ -397,6 +424,18 @@ struct MulAdj {
     static constexpr int C0 = 0, NC = nsym(D);
     static constexpr bool RT_ODD = false;
     static constexpr uint32_t ODD = (D == 2) ? (1u << 1) : ((1u << 2) | (1u << 4));
+    __device__ __forceinline__ T ka_value() const { return T(0); }
+    __host__ __device__ static constexpr DTerm dterm(int O, int J) {
+        if (O < D) return J < D ? DTerm{symi(D, O, J), O == J ? 1 : -1, 0, false} : DTerm{0, 0, 0, false};
+        if (O < D + nsym(D)) return J == D ? DTerm{O - D, sym_diag(D, O - D) ? 1 : -1, 0, false}
+                                           : DTerm{0, 0, 0, false};
+        if (O < 2 * D + nsym(D)) {
+            const int i = O - D - nsym(D), j = J - (D + 1);
+            return (j >= 0 && j < D) ? DTerm{symi(D, i, j), i == j ? 1 : -1, 0, false} : DTerm{0, 0, 0, false};
+        }
+        const int q = J - (2 * D + 1);
+        return (q >= 0 && q < nsym(D)) ? DTerm{q, sym_diag(D, q) ? 1 : -1, 0, false} : DTerm{0, 0, 0, false};
+    }
     // outputs: conv_i (D) | G_c (nsym) | cg_i (D) | E' (1)
     template <int O>
     __host__ __device__ static constexpr uint32_t need() {
@@ -467,6 +506,7 @@ struct MulTest {
     static constexpr int NIN = 1, NOUT = 1, C0 = 0, NC = 1;
     static constexpr bool RT_ODD = true;   // parity comes with the test kernel
     static constexpr uint32_t ODD = 0u;
+    __device__ __forceinline__ T ka_value() const { return T(0); }
     int P;
     template <int O>
     __host__ __device__ static constexpr uint32_t need() { return 1u; }

@@ -497,6 +497,187 @@ __global__ void __launch_bounds__(256) k_lastmul_f(Lines ln, M mul, cx<T>* S, co
 }
 
 // ----------------------------------------------------------------------------
+// Last-axis pass by direct summation.  After the transforms along the other
+// axes, the multiplier of component c along the last axis is a trigonometric
+// polynomial of degree m (the taps): B_c[0] + sum_{t=1..m} B_c[t] trig(2 pi k t / n).
+// Multiplying by it and transforming back is, exactly, a (2m+1)-point
+// correlation along the line, since the line is zero beyond the body and the
+// box leaves at least m zeros on each side (the periodic wrap only meets
+// zeros):
+//   even c:  w_c[0] g(z) + sum_t w_c[t] (g(z+t) + g(z-t))
+//   odd c:   -i sum_t w_c[t] (g(z+t) - g(z-t))     (the i of i^P_c taken
+//            out of the sine: i sin = (e^{+i} - e^{-i}) / 2)
+// with w_c[t] the taps in the direct convention (1/(n1 n2) instead of the
+// transform normalisation, no factor 2 for t > 0).  Each multiplier lists
+// its terms (DTerm: output, input, component, sign, power of i, k_a).  For
+// m = 3 this is ~170 arithmetic operations per point of the LPS force stage
+// against ~530 for the FFT-multiply-FFT form of the same product.
+//
+// One wavefront per line, four lines per block.  The line is swept in
+// chunks of 256 points, lane j holding the 4 consecutive points 4j .. 4j+3
+// of the chunk in registers (coalesced loads and stores).  The neighbours up
+// to 4 points away come from the lanes on either side by DPP whole-wave
+// shifts.  Beyond the chunk ends: lane 63 loads the next chunk's first 4
+// points (not yet overwritten: the outputs may replace the inputs in
+// place), and lane 0 takes the previous chunk's last 4 input points, which
+// lane 63 left in a small wave-private LDS slot before that chunk's stores.
+// The taps are wave-uniform (scalar loads).
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int DPP_WAVE_SHL1 = 0x130;   // lane i receives lane i+1
+constexpr int DPP_WAVE_SHR1 = 0x138;   // lane i receives lane i-1
+
+template <class T>
+struct alignas(4 * sizeof(T)) cx2 {
+    cx<T> a, b;
+};
+
+template <int N>
+struct IPow {
+    template <class T>
+    __device__ __forceinline__ static cx<T> apply(cx<T> a) {
+        if constexpr ((N & 3) == 0) return a;
+        else if constexpr ((N & 3) == 1) return {-a.i, a.r};
+        else if constexpr ((N & 3) == 2) return {-a.r, -a.i};
+        else return {a.i, -a.r};
+    }
+};
+
+template <class T, class M, int NT>
+__global__ void __launch_bounds__(256) k_lastconv(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps, int nct) {
+    static_assert(!M::RT_ODD && NT >= 2 && NT <= 5, "direct pass: compile-time parities, at most 4 neighbours");
+    constexpr int NI = M::NIN, NO = M::NOUT;
+    const int lane = threadIdx.x & 63;
+    const int l = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long li = (long)blockIdx.x * (blockDim.x >> 6) + l;
+    const bool ok = li < ln.nlines;    // wave-uniform
+    const long lic = ok ? li : 0;
+    const int len = ln.len, nch = (len + 255) >> 8;
+    const T* __restrict__ Bl = taps + (lic * nct + M::C0) * NT;   // wave-uniform
+    const T ka = mul.ka_value();
+    const cx<T> zero = {T(0), T(0)};
+    __shared__ cx<T> halo_s[4 * NI * 4];
+    lds_ptr<cx<T>> halo = as_lds(halo_s) + l * NI * 4;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int z0 = ch * 256 + 4 * lane;
+        cx<T> cur[NI][4];
+#pragma unroll
+        for (int f = 0; f < NI; ++f) {
+            const cx<T>* src = S + f * ln.fstride + lic * ln.pitch + z0;
+            if (ok && z0 + 3 < len) {
+                // 4 consecutive points; line starts are 16-point aligned
+                const cx2<T> p0 = reinterpret_cast<const cx2<T>*>(src)[0];
+                const cx2<T> p1 = reinterpret_cast<const cx2<T>*>(src)[1];
+                cur[f][0] = p0.a; cur[f][1] = p0.b; cur[f][2] = p1.a; cur[f][3] = p1.b;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cur[f][q] = (ok && z0 + q < len) ? src[q] : zero;
+            }
+        }
+        const int e0 = z0 + 4;   // lane 63: the next chunk's first points
+        const bool edge_lane = ok && lane == 63;
+        cx<T> out[NO][4];
+#pragma unroll
+        for (int o = 0; o < NO; ++o)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) out[o][q] = zero;
+#pragma unroll
+        for (int J = 0; J < NI; ++J) {
+            // window of points z0 - 4 .. z0 + 7 of input J; lanes 0 and 63
+            // load the points beyond the chunk ends themselves
+            cx<T> edge[4] = {zero, zero, zero, zero};
+            if (edge_lane) {
+                const cx<T>* src = S + J * ln.fstride + lic * ln.pitch;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (e0 + q < len) edge[q] = src[e0 + q];
+            }
+            if (lane == 0 && ch > 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) edge[q] = halo[J * 4 + q];
+            }
+            cx<T> w[12];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                w[4 + q] = cur[J][q];
+                const cx<T> a = {dpp_mov<DPP_WAVE_SHR1>(cur[J][q].r), dpp_mov<DPP_WAVE_SHR1>(cur[J][q].i)};
+                const cx<T> b = {dpp_mov<DPP_WAVE_SHL1>(cur[J][q].r), dpp_mov<DPP_WAVE_SHL1>(cur[J][q].i)};
+                w[q] = lane == 0 ? edge[q] : a;
+                w[8 + q] = lane == 63 ? edge[q] : b;
+            }
+            // neighbour sums at the 4 points, then every term that reads input J
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const cx<T> ctr = w[4 + q];
+                cx<T> ev[NT], od[NT];
+#pragma unroll
+                for (int t = 1; t < NT; ++t) {
+                    ev[t] = w[4 + q + t] + w[4 + q - t];
+                    od[t] = w[4 + q + t] - w[4 + q - t];
+                }
+                OutLoop<0, NO>::run([&](auto Oc) {
+                    constexpr int O = decltype(Oc)::value;
+                    OutLoop<0, NI>::run([&](auto Jc) {
+                        constexpr int JJ = decltype(Jc)::value;
+                        constexpr DTerm tm = M::dterm(O, JJ);
+                        if constexpr (tm.coef != 0) {
+                            if (JJ == J) {
+                                constexpr bool zo = (M::ODD >> (M::C0 + tm.c)) & 1u;
+                                cx<T> sv;
+                                if constexpr (zo) {
+                                    sv = cscale(od[1], Bl[tm.c * NT + 1]);
+#pragma unroll
+                                    for (int t = 2; t < NT; ++t) sv = sv + cscale(od[t], Bl[tm.c * NT + t]);
+                                } else {
+                                    sv = cscale(ctr, Bl[tm.c * NT]);
+#pragma unroll
+                                    for (int t = 1; t < NT; ++t) sv = sv + cscale(ev[t], Bl[tm.c * NT + t]);
+                                }
+                                // i^ipow of the multiplier, times -i for a component odd along the line
+                                sv = IPow<tm.ipow + (zo ? 3 : 0)>::apply(sv);
+                                if constexpr (tm.ka) sv = cscale(sv, ka);
+                                if constexpr (tm.coef == 1) out[O][q] = out[O][q] + sv;
+                                else if constexpr (tm.coef == -1) out[O][q] = out[O][q] - sv;
+                                else out[O][q] = out[O][q] + cscale(sv, T(tm.coef));
+                            }
+                        }
+                    });
+                });
+            }
+        }
+        if (lane == 63) {
+#pragma unroll
+            for (int f = 0; f < NI; ++f)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) halo[f * 4 + q] = cur[f][q];
+        }
+        if (ok) {
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                cx<T>* dst = S + (ln.out_off + o) * ln.fstride + li * ln.pitch + z0;
+                if (z0 + 3 < len) {
+                    reinterpret_cast<cx2<T>*>(dst)[0] = cx2<T>{out[o][0], out[o][1]};
+                    reinterpret_cast<cx2<T>*>(dst)[1] = cx2<T>{out[o][2], out[o][3]};
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (z0 + q < len) dst[q] = out[o][q];
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
 // 3D y passes with a transpose, so that the z pass reads contiguous lines.
 //   forward: SA [f][z][kx][y<b2]  --FFT along y-->  SB [f][kx][ky][z<Pz]
 //   inverse: SB [f][kx][ky][z]    --iFFT along y--> SA [f][z][kx][y<b2]

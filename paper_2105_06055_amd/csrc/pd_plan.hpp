@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/pd_fcbm.h"
+#include "../../include/pd_fcbm_testing.h"
 #include "pd_passes.hpp"
 
 // One timed kernel launch (profiling mode): events recorded on the launch
@@ -30,7 +31,7 @@ struct pd_plan_s {
     hipStream_t stream0;
     int device;
     int max_lds;                 // bytes of LDS a block may use
-    bool fast_lastmul;           // specialised last-axis kernel where it applies
+    int lastaxis;                // PD_LASTAXIS_* (kernel choice for the last axis)
     pdk::Geo geo;
     long nb, nfft;
     // stencil and kernels
@@ -43,7 +44,8 @@ struct pd_plan_s {
     // device buffers
     void* tw;                    // T twiddles: table for length N at [N, 2N)
     double* tw64;                // FP64 twiddles, same layout
-    void* taps;                  // T [NP][nct][ntap]
+    void* taps;                  // T [NP][nct][ntap], transform convention
+    void* taps_d;                // T [NP][nct][ntap], direct convention
     void* stat;                  // T [ncs][nb]
     uint8_t* chiB;               // [nb]
     uint8_t* chiO;               // [dim][nb]

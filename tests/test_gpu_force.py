@@ -117,9 +117,10 @@ def test_lps3d_ragged_voids(orc, dtype):
 
 
 # Lines of 512 points along the last axis (numpy axis 0) with a horizon of 3
-# spacings take the specialised last-axis kernel: check it against the oracle
-# (ragged body up to the largest body the padding allows) and against the
-# generic kernel on the same plan.
+# spacings: the default direct line correlation, the specialised 512-point
+# transform kernel and the runtime-length transform kernel, each against the
+# oracle (ragged body up to the largest body the padding allows) and against
+# each other on the same plan.
 @pytest.mark.parametrize("dtype", DT)
 @pytest.mark.parametrize("model,body", [("lps", (300, 11, 13)), ("lps", (509, 9, 12)), ("bb", (300, 11, 13)),
                                         ("bb", (509, 9, 12)), ("bb", (300, 41)), ("bb", (509, 17))])
@@ -138,11 +139,12 @@ def test_specialised_lastaxis_512(orc, dtype, model, body):
     else:
         Lo = orc.bb_force(g, orc.bb_alpha(D, 70e9, 3 * dx), chi.astype(float), u)
     _check(L, Lo, u, plan, 2700.0, dtype)
-    plan.set_generic(True)
-    Lg = plan.force(_dev(u, dtype)).cpu().numpy()
-    _check(Lg, Lo, u, plan, 2700.0, dtype)
     tol = 1e-13 if dtype == torch.float64 else 1e-5
-    assert np.linalg.norm(L - Lg) / np.linalg.norm(Lo) <= tol
+    for mode in ("fft", "fft_generic"):
+        plan.set_lastaxis(mode)
+        Lg = plan.force(_dev(u, dtype)).cpu().numpy()
+        _check(Lg, Lo, u, plan, 2700.0, dtype)
+        assert np.linalg.norm(L - Lg) / np.linalg.norm(Lo) <= tol, mode
     plan.close()
 
 
