@@ -1,18 +1,7 @@
-// pd_fcbm.hip -- plan creation, convolution chains and the C entry points of
-// the FCBM-EC peridynamics library for gfx950.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
-#include <cstdio>
-#include <cstdlib>
-#include <cstring>
-#include <type_traits>
-#include <vector>
-
-#include "pd_plan.hpp"
-
-using namespace pdk;
+// pd_fcbm.hip -- the C entry points of the FCBM-EC peridynamics library for
+// gfx950 (plan creation and dispatch by dtype; the per-dtype implementation
+// is compiled in pd_inst.hip).
+#include "pd_impl.hpp"
 
 namespace pdh {
 
@@ -24,1418 +13,30 @@ pd_status check(hipError_t e) {
 
 }  // namespace pdh
 
-#define PD_TRY(...)                                \
-    do {                                           \
-        pd_status s_ = (__VA_ARGS__);              \
-        if (s_ != PD_OK) return s_;                \
-    } while (0)
-#define HIP_TRY(x) PD_TRY(pdh::check(x))
+// instantiated in pd_inst.hip
+namespace pdi {
+#define PD_EXTERN(T)                                                                                               \
+    extern template pd_status plan_alloc<T>(pd_plan, hipStream_t, const uint8_t*, const uint8_t*);                \
+    extern template pd_status build_device_tables<T>(pd_plan, const std::vector<Bond>&, hipStream_t);             \
+    extern template pd_status force_impl<T>(pd_plan, const T*, const void*, T*, T*, hipStream_t);                 \
+    extern template pd_status adjoint_impl<T>(pd_plan, const T*, const T*, const void*, const T*, T*, T*, T, int, \
+                                              hipStream_t);                                                       \
+    extern template pd_status damage_impl<T>(pd_plan, const uint8_t*, T*, hipStream_t);                           \
+    extern template pd_status test_conv_impl<T>(pd_plan, const T*, const int*, int, T*, hipStream_t);             \
+    extern template pd_status verlet_impl<T>(pd_plan, pd_state*, const T*, const T*, double, int, double*,        \
+                                             hipStream_t);                                                        \
+    extern template pd_status verlet_adjoint_impl<T>(pd_plan, const T*, const T*, const T*, T*, T*, T*, double,   \
+                                                     hipStream_t);                                                \
+    extern template pd_status cg_run<T, T>(pd_plan, T*, T*, T*, T*, T*, double, double, int, int*, int*, double*, \
+                                           hipStream_t);                                                          \
+    extern template pd_status lin_apply<T, 3>(pd_plan, const T*, T*, const T*, hipStream_t);
+PD_EXTERN(float)
+PD_EXTERN(double)
+#undef PD_EXTERN
+}  // namespace pdi
+
+using namespace pdi;
 
-namespace {
-
-constexpr double kPi = 3.14159265358979323846;
-
-// ---------------------------------------------------------------- plan kernels
-
-// Partial spectra ("taps") of the kernel components, FP64 accumulation:
-//   B_c[t](k') = sc_t * sum_{o in S, o_last = t} K_c(o) prod_{d<last} trig_{p_cd}(2 pi k_d o_d / n_d)
-// with trig = cos for even and sin for odd axes (Eq. 56-58: the kernel
-// spectrum as a quadrature sum over the horizon, split along the last axis).
-// Transform convention (spectral multiply): sc_0 = 1/Nfft, sc_t = 2/Nfft;
-// direct convention (line correlation): sc_t = n_last/Nfft for every t.
-// Layout [k' (line)][component][tap]: the taps of one line are contiguous.
-template <class T>
-__global__ void k_taps(int dim, int n1, int n2, int h1, long NP, int ntap, int ns,
-                       const int* __restrict__ offs, const double* __restrict__ kval, int kstride,
-                       int nct, const uint8_t* __restrict__ par, const double* __restrict__ tw64,
-                       double sc0, double sc1, T* __restrict__ taps) {
-    long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= NP * ntap) return;
-    const long p = idx % NP;
-    const int t = (int)(idx / NP);
-    int kx, ky = 0;
-    if (dim == 2) kx = (int)p;
-    else { kx = (int)(p / n2); ky = (int)(p % n2); }
-    const int last = dim - 1;
-    double acc[12];
-    for (int c = 0; c < nct; ++c) acc[c] = 0.0;
-    const double* twx = tw64 + 2 * n1;  // complex FP64 table of length n1 at [n1, 2n1)
-    const double* twy = tw64 + 2 * n2;
-    for (int s = 0; s < ns; ++s) {
-        const int ox = offs[3 * s], oy = offs[3 * s + 1], oz = offs[3 * s + 2];
-        const int ol = (last == 1) ? oy : oz;
-        if (ol != t) continue;
-        int ex = (int)(((long)kx * ox) % n1);
-        if (ex < 0) ex += n1;
-        const double cxv = twx[2 * ex], sxv = -twx[2 * ex + 1];
-        double cyv = 1.0, syv = 0.0;
-        if (dim == 3) {
-            int ey = (int)(((long)ky * oy) % n2);
-            if (ey < 0) ey += n2;
-            cyv = twy[2 * ey];
-            syv = -twy[2 * ey + 1];
-        }
-        for (int c = 0; c < nct; ++c) {
-            double f = par[3 * c] ? sxv : cxv;
-            if (dim == 3) f *= par[3 * c + 1] ? syv : cyv;
-            acc[c] += kval[(long)s * kstride + c] * f;
-        }
-    }
-    const double sc = t ? sc1 : sc0;
-    for (int c = 0; c < nct; ++c) taps[((long)p * nct + c) * ntap + t] = T(acc[c] * sc);
-}
-
-// Static embedded-constraint fields by direct quadrature over the horizon
-// (the paper allows P = C (*) 1 either by quadrature or by FFT, Sec. 3.1):
-//   stat_c(x) = sum_{o in S} chi_B(x + o) K_c(o)   on the body box.
-template <class T>
-__global__ void k_static(int b1, int b2, int b3, int ns, const int* __restrict__ offs,
-                         const double* __restrict__ kval, int ncs, const uint8_t* __restrict__ chiB,
-                         T* __restrict__ stat, long nb) {
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nb) return;
-    const int x = (int)(i % b1), y = (int)((i / b1) % b2), z = (int)(i / ((long)b1 * b2));
-    double acc[12];
-    for (int c = 0; c < ncs; ++c) acc[c] = 0.0;
-    for (int s = 0; s < ns; ++s) {
-        const int xx = x + offs[3 * s], yy = y + offs[3 * s + 1], zz = z + offs[3 * s + 2];
-        if (xx < 0 || xx >= b1 || yy < 0 || yy >= b2 || zz < 0 || zz >= b3) continue;
-        if (!chiB[((long)zz * b2 + yy) * b1 + xx]) continue;
-        for (int c = 0; c < ncs; ++c) acc[c] += kval[(long)s * ncs + c];
-    }
-    for (int c = 0; c < ncs; ++c) stat[(long)c * nb + i] = T(acc[c]);
-}
-
-template <class T>
-__global__ void k_fill(T* p, long n, T v) {
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
-}  // namespace
-
-namespace pdk {
-
-__global__ void k_reduce_final(const double* __restrict__ part, long nblk, int NR, double* __restrict__ out) {
-    __shared__ double sm[256];
-    for (int r = 0; r < NR; ++r) {
-        double s = 0;
-        for (long b = threadIdx.x; b < nblk; b += blockDim.x) s += part[b * NR + r];
-        sm[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[r] = sm[0];
-        __syncthreads();
-    }
-}
-
-}  // namespace pdk
-
-namespace {
-
-// ------------------------------------------------------------------ helpers
-
-inline bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
-
-template <class T>
-inline cx<T>* SAp(pd_plan p) { return reinterpret_cast<cx<T>*>(p->SA); }
-template <class T>
-inline cx<T>* SBp(pd_plan p) { return reinterpret_cast<cx<T>*>(p->SB); }
-template <class T>
-inline const cx<T>* TWp(pd_plan p) { return reinterpret_cast<const cx<T>*>(p->tw); }
-
-template <class T>
-NodeCtx<T> ctx(pd_plan p) {
-    NodeCtx<T> c;
-    c.nb = p->nb;
-    c.chiB = p->chiB;
-    c.chiO = p->chiO;
-    c.stat = reinterpret_cast<const T*>(p->stat);
-    return c;
-}
-
-template <class T>
-int rows_per_block(pd_plan p) {
-    const int Tc = p->geo.Nc / 8;
-    int Lt = (sizeof(T) == 4) ? 16 : 8;
-    while (Lt > 1 && Tc * Lt > 512) Lt >>= 1;
-    while (Lt > 1 && ((size_t)Lt * row_pitch(p->geo.Nc) + tw_lds_len(p->geo.n1)) * sizeof(cx<T>) > (size_t)p->max_lds) Lt >>= 1;
-    return Lt;
-}
-
-template <class T>
-int cols_per_block(pd_plan p, int nc_taps) {
-    const int Tn = p->geo.n3 / 8;
-    int Lc = (sizeof(T) == 4) ? 16 : 8;
-    while (Lc > 1 && Tn * Lc > 512) Lc >>= 1;
-    while (Lc > p->geo.n2) Lc >>= 1;
-    auto need = [&](int L) {
-        return (size_t)p->geo.n3 * L * sizeof(cx<T>) + (size_t)L * nc_taps * p->ntap * sizeof(T);
-    };
-    while (Lc > 1 && need(Lc) > (size_t)p->max_lds) Lc >>= 1;
-    return Lc;
-}
-
-template <class K>
-void allow_lds(K kern, size_t bytes) {
-    if (bytes > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
-// Records a pair of events around one launch when timing is enabled.
-struct ProfScope {
-    pd_plan p;
-    hipStream_t st;
-    hipEvent_t a = nullptr;
-    ProfScope(pd_plan p_, hipStream_t st_) : p(p_), st(st_) {
-        if (p->prof && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, st);
-    }
-    void done(const char* name, double bytes) {
-        if (!p->prof || !a) return;
-        hipEvent_t b;
-        if (hipEventCreate(&b) != hipSuccess) return;
-        (void)hipEventRecord(b, st);
-        ProfRec r;
-        std::snprintf(r.name, sizeof(r.name), "%s", name);
-        r.a = a;
-        r.b = b;
-        r.bytes = bytes;
-        p->prof->push_back(r);
-        a = nullptr;
-    }
-};
-
-template <class T>
-long xinv_blocks(pd_plan p) {
-    const int Lt = rows_per_block<T>(p);
-    return (long)((p->geo.b2 + Lt - 1) / Lt) * p->geo.b3;
-}
-
-// Lengths with compile-time specialisations of the x and y passes (the
-// 512^3 box: 256-point complex rows along x, 512-point lines along y); any
-// other length runs the runtime-length kernels (LG = 0).  The specialised x
-// passes also assume a body no longer than half the x box (b1 <= Nc).
-constexpr int kFastLgX = 8, kFastLgY = 9;
-
-// Pass 1
-template <class T, class G, int LG>
-pd_status launch_xfwd_lg(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
-    const Geo& g = p->geo;
-    const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
-    if (LG > 0 && Tc * Lt != xblock_threads<T>()) return PD_EUNSUPPORTED;
-    dim3 grid((g.b2 + Lt - 1) / Lt, g.b3), block(Tc * Lt);
-    size_t lds = ((size_t)Lt * row_pitch(g.Nc) + tw_lds_len(g.n1)) * sizeof(cx<T>);
-    allow_lds(k_xfwd<T, G, LG>, lds);
-    ProfScope ps(p, st);
-    hipLaunchKernelGGL((k_xfwd<T, G, LG>), grid, block, lds, st, g, gen, SA, TWp<T>(p));
-    if (p->prof) {
-        char nm[32];
-        std::snprintf(nm, sizeof nm, "xfwd_%d", G::NIN);
-        ps.done(nm, gen.nbytes() * (double)g.nb + (double)G::NIN * g.b3 * g.h1 * g.b2 * sizeof(cx<T>));
-    }
-    return pdh::check(hipGetLastError());
-}
-template <class T, class G>
-pd_status launch_xfwd(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
-    if (p->geo.Nc == (1 << kFastLgX) && p->geo.b1 <= p->geo.Nc) return launch_xfwd_lg<T, G, kFastLgX>(p, gen, SA, st);
-    return launch_xfwd_lg<T, G, 0>(p, gen, SA, st);
-}
-
-// Last-axis pass over contiguous lines.  Default: direct line correlation
-// (taps_d, horizons up to 4 spacings along the last axis); otherwise the
-// FFT-multiply-FFT form (taps), specialised for 512-point lines with 4 taps
-// or with runtime lengths.
-template <class T, class M, int NT>
-pd_status launch_lastconv(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, const T* taps_d, int nct,
-                          hipStream_t st) {
-    // one wavefront per line, four lines per block; no LDS; line starts must be
-    // 16-point aligned (the pitches of SA and SB are)
-    if ((ln.pitch & 15) || (ln.fstride & 15)) return PD_EINVAL;
-    const int Lw = 4;
-    dim3 grid((unsigned)((ln.nlines + Lw - 1) / Lw)), block(64 * Lw);
-    hipLaunchKernelGGL((k_lastconv<T, M, NT>), grid, block, 0, st, ln, mul, S, taps_d, nct);
-    return PD_OK;
-}
-
-template <class T, class M>
-pd_status launch_lastmul(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, const T* taps, const T* taps_d,
-                         int ntap, int nct, uint32_t oddmask, hipStream_t st) {
-    const int Tn = ln.N / 8;
-    ProfScope ps(p, st);
-    int path = 2;   // 0 direct, 1 specialised FFT, 2 generic FFT
-    if constexpr (!M::RT_ODD) {
-        if (p->lastaxis == PD_LASTAXIS_AUTO && taps_d && ntap >= 2 && ntap <= 5) path = 0;
-        else if (p->lastaxis != PD_LASTAXIS_FFT_GENERIC && ln.N == 512 && ntap == 4) path = 1;
-    }
-    if (path == 0) {
-        if constexpr (!M::RT_ODD) {
-            pd_status s = PD_OK;
-            switch (ntap) {
-                case 2: s = launch_lastconv<T, M, 2>(p, ln, mul, S, taps_d, nct, st); break;
-                case 3: s = launch_lastconv<T, M, 3>(p, ln, mul, S, taps_d, nct, st); break;
-                case 4: s = launch_lastconv<T, M, 4>(p, ln, mul, S, taps_d, nct, st); break;
-                default: s = launch_lastconv<T, M, 5>(p, ln, mul, S, taps_d, nct, st); break;
-            }
-            PD_TRY(s);
-        }
-    } else if (path == 1) {
-        if constexpr (!M::RT_ODD) {
-            constexpr int LG = 9, NT = 4;
-            const int Lw = 4;
-            const size_t lds = ((size_t)Lw * line_pitch(1 << LG) + tw_lds_len(1 << LG)) * sizeof(cx<T>);
-            if (lds > (size_t)p->max_lds) return PD_EUNSUPPORTED;
-            dim3 grid((unsigned)((ln.nlines + Lw - 1) / Lw)), block(Lw * ((1 << LG) / 8));
-            allow_lds(k_lastmul_f<T, M, LG, NT>, lds);
-            hipLaunchKernelGGL((k_lastmul_f<T, M, LG, NT>), grid, block, lds, st, ln, mul, S, taps, nct, TWp<T>(p));
-        }
-    } else {
-        int Lw = std::max(1, 256 / Tn);
-        auto need = [&](int L) {
-            return ((size_t)L * line_pitch(ln.N) + tw_lds_len(ln.N)) * sizeof(cx<T>) +
-                   (size_t)L * M::NC * ntap * sizeof(T);
-        };
-        while (Lw > 1 && need(Lw) > (size_t)p->max_lds) Lw >>= 1;
-        size_t lds = need(Lw);
-        dim3 grid((unsigned)((ln.nlines + Lw - 1) / Lw)), block(Lw * Tn);
-        allow_lds(k_lastmul<T, M>, lds);
-        hipLaunchKernelGGL((k_lastmul<T, M>), grid, block, lds, st, ln, mul, S, taps, ntap, nct, oddmask, TWp<T>(p));
-    }
-    if (p->prof) {
-        char nm[32];
-        std::snprintf(nm, sizeof nm, "lastmul_%dx%d", M::NIN, M::NOUT);
-        ps.done(nm, (double)(M::NIN + M::NOUT) * ln.nlines * ln.len * sizeof(cx<T>) +
-                        (double)M::NC * ntap * ln.nlines * sizeof(T));
-    }
-    return pdh::check(hipGetLastError());
-}
-
-// planes per block of the transposing y passes
-template <class T>
-int planes_per_block(pd_plan p) {
-    const int Tn = p->geo.n2 / 8;
-    int Lz = (sizeof(T) == 4) ? 16 : 8;
-    while (Lz > 1 && Tn * Lz > 1024) Lz >>= 1;
-    while (Lz > 1 && ((size_t)Lz * line_pitch(p->geo.n2) + tw_lds_len(p->geo.n2)) * sizeof(cx<T>) > (size_t)p->max_lds) Lz >>= 1;
-    return Lz;
-}
-
-// 3D y passes with transpose; F fields starting at SA field 0 / SB field fb.
-template <class T, int SIGN, int LG>
-pd_status launch_ytrans_lg(pd_plan p, int F, int fb, hipStream_t st) {
-    const Geo& g = p->geo;
-    const int Tn = g.n2 / 8, Lz = planes_per_block<T>(p);
-    dim3 grid((g.b3 + Lz - 1) / Lz, g.h1, F), block(Lz * Tn);
-    size_t lds = ((size_t)Lz * line_pitch(g.n2) + tw_lds_len(g.n2)) * sizeof(cx<T>);
-    cx<T>* SB = SBp<T>(p) + (long)fb * p->sbf;
-    ProfScope ps(p, st);
-    if (SIGN < 0) {
-        allow_lds(k_ytf<T, LG>, lds);
-        hipLaunchKernelGGL((k_ytf<T, LG>), grid, block, lds, st, g, SAp<T>(p), SB, p->Pz, TWp<T>(p));
-    } else {
-        allow_lds(k_yti<T, LG>, lds);
-        hipLaunchKernelGGL((k_yti<T, LG>), grid, block, lds, st, g, SB, SAp<T>(p), p->Pz, TWp<T>(p));
-    }
-    if (p->prof) {
-        char nm[32];
-        std::snprintf(nm, sizeof nm, "%s_%d", SIGN < 0 ? "ytf" : "yti", g.n2);
-        ps.done(nm, (double)F * g.b3 * g.h1 * (g.b2 + g.n2) * sizeof(cx<T>));
-    }
-    return pdh::check(hipGetLastError());
-}
-template <class T, int SIGN>
-pd_status launch_ytrans(pd_plan p, int F, int fb, hipStream_t st) {
-    if (F <= 0) return PD_OK;
-    if (p->geo.n2 == (1 << kFastLgY)) return launch_ytrans_lg<T, SIGN, kFastLgY>(p, F, fb, st);
-    return launch_ytrans_lg<T, SIGN, 0>(p, F, fb, st);
-}
-
-// Pass 5 (+ deterministic reduction into p->red when F::NRED > 0)
-template <class T, class F, int LG>
-pd_status launch_xinv_lg(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st) {
-    const Geo& g = p->geo;
-    const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
-    if (LG > 0 && Tc * Lt != xblock_threads<T>()) return PD_EUNSUPPORTED;
-    dim3 grid((g.b2 + Lt - 1) / Lt, g.b3), block(Tc * Lt);
-    size_t lds = ((size_t)Lt * row_pitch(g.Nc) + tw_lds_len(g.n1)) * sizeof(cx<T>);
-    size_t red_lds = (size_t)((Tc * Lt + 63) / 64) * 8 * sizeof(double);
-    lds = std::max(lds, red_lds);
-    const long nblk = (long)grid.x * grid.y;
-    if (F::NRED > 0 && nblk * F::NRED > p->partials_cap) return PD_EINVAL;
-    allow_lds(k_xinv<T, F, LG>, lds);
-    ProfScope ps(p, st);
-    hipLaunchKernelGGL((k_xinv<T, F, LG>), grid, block, lds, st, g, fin, SA, p->partials, TWp<T>(p));
-    if (p->prof) {
-        char nm[32];
-        std::snprintf(nm, sizeof nm, "xinv_%d", F::NOUT);
-        ps.done(nm, fin.nbytes() * (double)g.nb + (double)F::NOUT * g.b3 * g.h1 * g.b2 * sizeof(cx<T>));
-    }
-    PD_TRY(pdh::check(hipGetLastError()));
-    if (F::NRED > 0) {
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, p->partials, nblk, F::NRED, p->red);
-        PD_TRY(pdh::check(hipGetLastError()));
-    }
-    return PD_OK;
-}
-template <class T, class F>
-pd_status launch_xinv(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st) {
-    if (p->geo.Nc == (1 << kFastLgX) && p->geo.b1 <= p->geo.Nc) return launch_xinv_lg<T, F, kFastLgX>(p, fin, SA, st);
-    return launch_xinv_lg<T, F, 0>(p, fin, SA, st);
-}
-
-// One full chain.  3D: sb_off is the SB field slot the generator's fields go
-// to; the multiplier reads SB slots [0, M::NIN) and writes slots
-// [out_off, out_off + M::NOUT) (out_off > 0 keeps the input spectra for a
-// later chain, as the LPS dilatation stage does for the force stage).
-template <class T, class G, class M, class F>
-pd_status run_chain(pd_plan p, const G& gen, const M& mul, const F& fin, hipStream_t st, int sb_off = 0,
-                    int out_off = 0, const T* taps = nullptr, int ntap = 0, int nct = 1,
-                    uint32_t oddmask = 0xffffffffu) {
-    static_assert(M::NOUT == F::NOUT, "multiplier/epilogue mismatch");
-    const Geo& g = p->geo;
-    const T* taps_d = nullptr;   // direct-convention taps (plan tables only)
-    if (!taps) {
-        taps = reinterpret_cast<const T*>(p->taps);
-        taps_d = reinterpret_cast<const T*>(p->taps_d);
-        ntap = p->ntap;
-        nct = p->nct;
-        oddmask = p->oddmask;
-    }
-    if (std::max(G::NIN, M::NOUT) > p->saf_cap) return PD_EINVAL;
-    PD_TRY(launch_xfwd<T>(p, gen, SAp<T>(p), st));
-    if (g.dim == 2) {
-        if (G::NIN != M::NIN) return PD_EINVAL;
-        Lines ln{(long)g.h1, (long)g.P2, g.saf, g.b2, g.n2, 0};
-        PD_TRY(launch_lastmul<T>(p, ln, mul, SAp<T>(p), taps, taps_d, ntap, nct, oddmask, st));
-    } else {
-        if (sb_off + G::NIN > p->sbf_cap || M::NIN > p->sbf_cap || out_off + M::NOUT > p->sbf_cap) return PD_EINVAL;
-        PD_TRY((launch_ytrans<T, -1>(p, G::NIN, sb_off, st)));
-        Lines ln{(long)g.h1 * g.n2, (long)p->Pz, p->sbf, g.b3, g.n3, out_off};
-        PD_TRY(launch_lastmul<T>(p, ln, mul, SBp<T>(p), taps, taps_d, ntap, nct, oddmask, st));
-        PD_TRY((launch_ytrans<T, 1>(p, M::NOUT, out_off, st)));
-    }
-    PD_TRY(launch_xinv<T>(p, fin, SAp<T>(p), st));
-    return PD_OK;
-}
-
-// ----------------------------------------------------------------- stencil
-struct Bond {
-    int o[3];
-    double xi[3];
-    double r;
-};
-
-std::vector<Bond> make_stencil(int dim, const double* dx, double delta) {
-    std::vector<Bond> S;
-    int M[3] = {0, 0, 0};
-    for (int d = 0; d < dim; ++d) M[d] = (int)std::floor(delta / dx[d] + 1e-9) + 1;
-    const double lim = delta * delta * (1.0 + 1e-10);
-    for (int oz = -M[2]; oz <= M[2]; ++oz)
-        for (int oy = -M[1]; oy <= M[1]; ++oy)
-            for (int ox = -M[0]; ox <= M[0]; ++ox) {
-                if (!ox && !oy && !oz) continue;
-                Bond b;
-                b.o[0] = ox; b.o[1] = oy; b.o[2] = oz;
-                double r2 = 0;
-                for (int d = 0; d < 3; ++d) {
-                    b.xi[d] = (d < dim) ? b.o[d] * dx[d] : 0.0;
-                    r2 += b.xi[d] * b.xi[d];
-                }
-                if (r2 > lim) continue;
-                b.r = std::sqrt(r2);
-                S.push_back(b);
-            }
-    return S;
-}
-
-// Bond-based micromodulus constant for omega = 1/r (influence 0) or 1:
-// alpha = 2 lambda_target / (A_d * int_0^delta omega r^(d+1) dr), with the
-// isotropic angular moments A_2 = pi/4, A_3 = 4 pi/15 and the Lame constant
-// lambda_target = 3E/8 (2D plane stress, nu = 1/3) or 2E/5 (3D, nu = 1/4);
-// for 2D and omega = 1/r this is the paper's alpha = 9E/(pi delta^3).
-double bb_alpha(int dim, int influence, double E, double delta) {
-    const double I = influence == 0 ? std::pow(delta, dim + 1) / (dim + 1) : std::pow(delta, dim + 2) / (dim + 2);
-    const double A = dim == 2 ? kPi / 4.0 : 4.0 * kPi / 15.0;
-    const double lam = dim == 2 ? 3.0 * E / 8.0 : 2.0 * E / 5.0;
-    return 2.0 * lam / (A * I);
-}
-
-template <class T>
-void twiddles_host(int nmax, std::vector<T>& out) {
-    out.assign((size_t)4 * nmax, T(0));
-    for (int N = 1; N <= nmax; N <<= 1)
-        for (int e = 0; e < N; ++e) {
-            long double a = -2.0L * 3.141592653589793238462643383279502884L * (long double)e / (long double)N;
-            out[2 * (size_t)(N + e)] = (T)cosl(a);
-            out[2 * (size_t)(N + e) + 1] = (T)sinl(a);
-        }
-}
-
-// Largest eigenvalue of the periodic operator's symbol, sampled on a
-// coarse set of wavenumbers (the maximum sits at large |k|), used for the
-// explicit time-step bound dt <= 2/sqrt(lambda_max/rho).
-double symbol_lambda_max(pd_plan p, const std::vector<Bond>& S) {
-    const int D = p->dim;
-    double best = 0;
-    const int nsmp = 16;
-    int lim[3] = {nsmp, nsmp, D == 3 ? nsmp : 0};
-    for (int a = 0; a <= lim[0]; ++a)
-        for (int b = 0; b <= lim[1]; ++b)
-            for (int c = 0; c <= lim[2]; ++c) {
-                double kk[3] = {a * 0.5 / nsmp, b * 0.5 / nsmp, c * 0.5 / nsmp};  // cycles per node
-                double Mx[3][3] = {{0}}, sv[3] = {0, 0, 0};
-                for (const Bond& bd : S) {
-                    double ph = 0;
-                    for (int d = 0; d < D; ++d) ph += 2 * kPi * kk[d] * bd.o[d];
-                    const double om = p->influence == 0 ? 1.0 / bd.r : 1.0;
-                    double coef = (p->kern.model == PD_BB_LINEAR) ? p->alpha : 30.0 * p->mu / p->m0;
-                    coef *= om / (bd.r * bd.r) * p->dV * (1.0 - std::cos(ph));
-                    for (int i = 0; i < D; ++i)
-                        for (int j = 0; j < D; ++j) Mx[i][j] += coef * bd.xi[i] * bd.xi[j];
-                    for (int i = 0; i < D; ++i) sv[i] += om * bd.xi[i] * std::sin(ph) * p->dV;
-                }
-                if (p->kern.model == PD_LPS_LINEAR)
-                    for (int i = 0; i < D; ++i)
-                        for (int j = 0; j < D; ++j) Mx[i][j] += 3.0 * p->ka * sv[i] * sv[j];
-                // Gershgorin bound of the symmetric matrix
-                for (int i = 0; i < D; ++i) {
-                    double r = 0;
-                    for (int j = 0; j < D; ++j) r += std::fabs(Mx[i][j]);
-                    best = std::max(best, r);
-                }
-            }
-    return best;
-}
-
-template <class T>
-pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t st) {
-    const int D = p->dim;
-    // components
-    std::vector<double> kv;          // [ns][ncs]
-    std::vector<uint8_t> par;        // [nct][3]
-    const int ns = (int)S.size();
-    auto om = [&](double r) { return p->influence == 0 ? 1.0 / r : 1.0; };
-    int nct = 0, ncs = 0;
-    if (p->kern.model == PD_BB_LINEAR) {
-        nct = nsym(D) + (p->kern.weight == PD_WEIGHT_INTEGRITY ? 1 : 0);
-        ncs = nct;
-    } else {
-        nct = 9;
-        ncs = 10;
-    }
-    kv.assign((size_t)ns * ncs, 0.0);
-    par.assign((size_t)nct * 3, 0);
-    const double cC = (p->kern.model == PD_BB_LINEAR) ? p->alpha : 30.0 * p->mu / p->m0;
-    for (int s = 0; s < ns; ++s) {
-        const Bond& bd = S[s];
-        const double w = om(bd.r);
-        for (int i = 0; i < D; ++i)
-            for (int j = i; j < D; ++j)
-                kv[(size_t)s * ncs + symi(D, i, j)] = cC * w * bd.xi[i] * bd.xi[j] / (bd.r * bd.r) * p->dV;
-        if (p->kern.model == PD_BB_LINEAR) {
-            if (p->kern.weight == PD_WEIGHT_INTEGRITY) kv[(size_t)s * ncs + nsym(D)] = 1.0;
-        } else {
-            for (int i = 0; i < 3; ++i) kv[(size_t)s * ncs + 6 + i] = w * bd.xi[i] * p->dV;
-            kv[(size_t)s * ncs + 9] = w * bd.r * bd.r * p->dV;
-        }
-    }
-    p->oddmask = 0;
-    for (int i = 0; i < D; ++i)
-        for (int j = i; j < D; ++j) {
-            const int c = symi(D, i, j);
-            for (int d = 0; d < D; ++d) par[3 * c + d] = ((i == d) + (j == d)) & 1;
-        }
-    if (p->kern.model == PD_LPS_LINEAR)
-        for (int i = 0; i < 3; ++i) par[3 * (6 + i) + i] = 1;
-    for (int c = 0; c < nct; ++c)
-        if (par[3 * c + (D - 1)]) p->oddmask |= 1u << c;
-    p->nct = nct;
-    p->ncs = ncs;
-    p->beta_comp = (p->kern.weight == PD_WEIGHT_INTEGRITY && p->kern.model == PD_BB_LINEAR) ? nsym(D) : -1;
-
-    int mlast = 0;
-    std::vector<int> offs((size_t)ns * 3);
-    for (int s = 0; s < ns; ++s) {
-        for (int d = 0; d < 3; ++d) offs[3 * s + d] = S[s].o[d];
-        mlast = std::max(mlast, std::abs(S[s].o[D - 1]));
-    }
-    p->ntap = mlast + 1;
-    if (p->ntap > 9) return PD_EUNSUPPORTED;
-
-    HIP_TRY(hipMalloc(&p->offs_dev, sizeof(int) * offs.size()));
-    HIP_TRY(hipMalloc(&p->kval_dev, sizeof(double) * kv.size()));
-    uint8_t* par_dev = nullptr;
-    HIP_TRY(hipMalloc(&par_dev, par.size()));
-    HIP_TRY(hipMemcpyAsync(p->offs_dev, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(p->kval_dev, kv.data(), sizeof(double) * kv.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(par_dev, par.data(), par.size(), hipMemcpyHostToDevice, st));
-
-    const Geo& g = p->geo;
-    const long NP = (D == 2) ? (long)g.h1 : (long)g.h1 * g.n2;
-    HIP_TRY(hipMalloc(&p->taps, sizeof(T) * NP * p->ntap * nct));
-    HIP_TRY(hipMalloc(&p->taps_d, sizeof(T) * NP * p->ntap * nct));
-    p->bytes += 2 * sizeof(T) * NP * p->ntap * nct;
-    {
-        long n = NP * p->ntap;
-        const double inv = 1.0 / (double)p->nfft, nl = (double)(D == 2 ? g.n2 : g.n3);
-        hipLaunchKernelGGL((k_taps<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, D, g.n1, g.n2, g.h1, NP,
-                           p->ntap, ns, p->offs_dev, p->kval_dev, ncs, nct, par_dev, p->tw64,
-                           inv, 2.0 * inv, reinterpret_cast<T*>(p->taps));
-        HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL((k_taps<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, D, g.n1, g.n2, g.h1, NP,
-                           p->ntap, ns, p->offs_dev, p->kval_dev, ncs, nct, par_dev, p->tw64,
-                           nl * inv, nl * inv, reinterpret_cast<T*>(p->taps_d));
-        HIP_TRY(hipGetLastError());
-    }
-    HIP_TRY(hipMalloc(&p->stat, sizeof(T) * p->nb * ncs));
-    p->bytes += sizeof(T) * p->nb * ncs;
-    hipLaunchKernelGGL((k_static<T>), dim3((unsigned)((p->nb + 255) / 256)), dim3(256), 0, st, g.b1, g.b2, g.b3, ns,
-                       p->offs_dev, p->kval_dev, ncs, p->chiB, reinterpret_cast<T*>(p->stat), p->nb);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(st));
-    (void)hipFree(par_dev);
-    return PD_OK;
-}
-
-void plan_free(pd_plan p) {
-    if (!p) return;
-    if (p->stream0) (void)hipStreamSynchronize(p->stream0);
-    void* bufs[] = {p->tw, p->tw64, p->taps, p->taps_d, p->stat, p->chiB, p->chiO, p->SA, p->SB, p->theta,
-                    p->vtmp, p->vtmp2, p->partials, p->red, p->offs_dev, p->kval_dev};
-    for (void* b : bufs)
-        if (b) (void)hipFree(b);
-    if (p->red_host) (void)hipHostFree(p->red_host);
-    if (p->prof) {
-        for (ProfRec& r : *p->prof) {
-            (void)hipEventDestroy(r.a);
-            (void)hipEventDestroy(r.b);
-        }
-        delete p->prof;
-    }
-    if (p->sub32) plan_free(p->sub32);
-    delete p;
-}
-
-template <class T>
-pd_status plan_alloc(pd_plan p, hipStream_t st, const uint8_t* chiB_h, const uint8_t* chiO_h) {
-    const Geo& g = p->geo;
-    const int D = p->dim;
-    // twiddles
-    int nmax = std::max(std::max(g.n1, g.n2), g.n3);
-    {
-        std::vector<T> tw;
-        twiddles_host<T>(nmax, tw);
-        HIP_TRY(hipMalloc(&p->tw, sizeof(T) * tw.size()));
-        HIP_TRY(hipMemcpyAsync(p->tw, tw.data(), sizeof(T) * tw.size(), hipMemcpyHostToDevice, st));
-        std::vector<double> tw64;
-        twiddles_host<double>(nmax, tw64);
-        HIP_TRY(hipMalloc(&p->tw64, sizeof(double) * tw64.size()));
-        HIP_TRY(hipMemcpyAsync(p->tw64, tw64.data(), sizeof(double) * tw64.size(), hipMemcpyHostToDevice, st));
-        HIP_TRY(hipStreamSynchronize(st));
-    }
-    // masks
-    std::vector<uint8_t> cb((size_t)p->nb, 1), co((size_t)p->nb * D, 1);
-    if (chiB_h)
-        for (long i = 0; i < p->nb; ++i) cb[i] = chiB_h[i] ? 1 : 0;
-    for (int d = 0; d < D; ++d)
-        for (long i = 0; i < p->nb; ++i)
-            co[(size_t)d * p->nb + i] = chiO_h ? (chiO_h[(size_t)d * p->nb + i] ? 1 : 0) : cb[i];
-    // a constrained or unknown component only makes sense on the body
-    for (int d = 0; d < D; ++d)
-        for (long i = 0; i < p->nb; ++i) co[(size_t)d * p->nb + i] &= cb[i];
-    HIP_TRY(hipMalloc(&p->chiB, p->nb));
-    HIP_TRY(hipMalloc(&p->chiO, p->nb * D));
-    HIP_TRY(hipMemcpy(p->chiB, cb.data(), p->nb, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(p->chiO, co.data(), p->nb * D, hipMemcpyHostToDevice));
-    p->bytes += p->nb * (D + 1);
-    // workspaces: field capacities by model
-    int capA, capB = 0, capC = 0;
-    if (D == 2) {
-        // weighted + energy: in D+1+nsym, out D+nsym+1; adjoint: in 2D+1+nsym, out 2D+nsym+1
-        capA = 2 * D + 1 + nsym(D) + 1;
-    } else {
-        capA = (p->kern.model == PD_LPS_LINEAR) ? 4 : (2 * D + 1 + nsym(D) + 1);
-        capB = (p->kern.model == PD_LPS_LINEAR) ? 4 : (2 * D + 1 + nsym(D) + 1);
-        capC = (p->kern.model == PD_LPS_LINEAR) ? 3 : (2 * D + nsym(D) + 1);
-    }
-    if (p->kern.model == PD_BB_LINEAR && p->kern.weight == PD_WEIGHT_NONE) {
-        // unweighted bond-based: force (D) or force+energy (D+1+nsym)
-        capA = std::max(capA, D + 1 + nsym(D));
-    }
-    p->saf_cap = capA;
-    p->sbf_cap = std::max(capB, capC);
-    p->scf_cap = 0;
-    size_t szA = sizeof(cx<T>) * (size_t)g.saf * capA;
-    HIP_TRY(hipMalloc(&p->SA, szA));
-    p->bytes += szA;
-    if (D == 3) {
-        size_t szB = sizeof(cx<T>) * (size_t)p->sbf * std::max(capB, capC);
-        HIP_TRY(hipMalloc(&p->SB, szB));
-        p->bytes += szB;
-    }
-    if (p->kern.model == PD_LPS_LINEAR) {
-        HIP_TRY(hipMalloc(&p->theta, sizeof(T) * p->nb));
-        p->bytes += sizeof(T) * p->nb;
-    }
-    HIP_TRY(hipMalloc(&p->vtmp, 2 * sizeof(T) * p->nb * D));
-    HIP_TRY(hipMalloc(&p->vtmp2, 2 * sizeof(T) * p->nb * D));
-    p->bytes += 4 * sizeof(T) * p->nb * D;
-    {
-        const int Lt = rows_per_block<T>(p);
-        long nblk = (long)((g.b2 + Lt - 1) / Lt) * g.b3;
-        p->partials_cap = std::max(nblk * 8, 4096L);
-        HIP_TRY(hipMalloc(&p->partials, sizeof(double) * p->partials_cap));
-        HIP_TRY(hipMalloc(&p->red, sizeof(double) * 16));
-        HIP_TRY(hipHostMalloc(&p->red_host, sizeof(double) * 16, hipHostMallocDefault));
-    }
-    return PD_OK;
-}
-
-pd_status plan_create_impl(const pd_grid* grid, const pd_horizon* hz, const pd_kernel* kern, const pd_mask* mask,
-                           pd_dtype dtype, int flags, hipStream_t st, pd_plan* out) {
-    if (!grid || !hz || !kern || !out) return PD_EINVAL;
-    *out = nullptr;
-    const int D = grid->dim;
-    if (D != 2 && D != 3) return PD_EINVAL;
-    if (kern->model == PD_LPS_LINEAR && D != 3) return PD_EUNSUPPORTED;
-    if (kern->model != PD_BB_LINEAR && kern->model != PD_LPS_LINEAR) return PD_EINVAL;
-    if (kern->model == PD_LPS_LINEAR && kern->weight != PD_WEIGHT_NONE) return PD_EUNSUPPORTED;
-    if (dtype != PD_F32 && dtype != PD_F64) return PD_EINVAL;
-    if (!(hz->delta > 0) || (hz->influence != 0 && hz->influence != 1)) return PD_EINVAL;
-    if (!(kern->E > 0)) return PD_EINVAL;
-    if (kern->model == PD_LPS_LINEAR && !(kern->nu > -1.0 && kern->nu < 0.5)) return PD_EINVAL;
-    for (int d = 0; d < 3; ++d) {
-        const bool active = d < D;
-        const long n = grid->fft_n[d], b = grid->body_n[d];
-        if (!active) {
-            if (n != 1 || b != 1) return PD_EINVAL;
-            continue;
-        }
-        if (!(grid->dx[d] > 0)) return PD_EINVAL;
-        if (b < 1 || n < 1) return PD_EINVAL;
-        if (!is_pow2(n)) return PD_EUNSUPPORTED;
-        const long lo = 16, hi = (d == 0) ? 2048 : 1024;
-        if (n < lo || n > hi) return PD_EUNSUPPORTED;
-        const long m = (long)std::ceil(hz->delta / grid->dx[d] * (1.0 - 1e-12));
-        if (n - b < m) return PD_EINVAL;  // a bond would wrap around the periodic box
-    }
-    pd_plan p = new pd_plan_s();
-    std::memset(p, 0, sizeof(*p));
-    p->lastaxis = PD_LASTAXIS_AUTO;
-    p->dim = D;
-    for (int d = 0; d < 3; ++d) {
-        p->n[d] = (int)grid->fft_n[d];
-        p->b[d] = (int)grid->body_n[d];
-        p->dx[d] = d < D ? grid->dx[d] : 1.0;
-    }
-    p->delta = hz->delta;
-    p->influence = hz->influence;
-    p->kern = *kern;
-    p->dtype = dtype;
-    p->flags = flags;
-    p->stream0 = st;
-    (void)hipGetDevice(&p->device);
-    int maxsm = 65536;
-    if (hipDeviceGetAttribute(&maxsm, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess) maxsm = 65536;
-    p->max_lds = std::max(32768, maxsm);
-    Geo& g = p->geo;
-    g.dim = D;
-    g.n1 = p->n[0]; g.n2 = p->n[1]; g.n3 = p->n[2];
-    g.b1 = p->b[0]; g.b2 = p->b[1]; g.b3 = p->b[2];
-    g.Nc = g.n1 / 2;
-    g.h1 = g.Nc + 1;
-    g.P2 = ((g.b2 + 15) / 16) * 16;
-    g.nb = (long)g.b1 * g.b2 * g.b3;
-    g.saf = (long)g.b3 * g.h1 * g.P2;
-    g.sbf = (long)g.b3 * g.h1 * g.n2;
-    p->Pz = ((g.b3 + 15) / 16) * 16;
-    p->sbf = (long)g.h1 * g.n2 * p->Pz;
-    p->nb = g.nb;
-    p->nfft = (long)g.n1 * g.n2 * g.n3;
-    p->dV = p->dx[0] * p->dx[1] * (D == 3 ? p->dx[2] : 1.0);
-
-    std::vector<Bond> S = make_stencil(D, p->dx, p->delta);
-    p->ns = (int)S.size();
-    if (p->ns == 0) { delete p; return PD_EINVAL; }
-    p->m0 = 0;
-    for (const Bond& bd : S) p->m0 += (p->influence == 0 ? 1.0 / bd.r : 1.0) * bd.r * bd.r * p->dV;
-    p->alpha = bb_alpha(D, p->influence, kern->E, p->delta);
-    if (kern->model == PD_LPS_LINEAR) {
-        p->kappa = kern->E / (3.0 * (1.0 - 2.0 * kern->nu));
-        p->mu = kern->E / (2.0 * (1.0 + kern->nu));
-        p->ka = (3.0 * p->kappa - 5.0 * p->mu) / p->m0;
-    }
-    p->Wc = (kern->weight == PD_WEIGHT_INTEGRITY && kern->G0 > 0) ? kern->G0 / p->delta : 0.0;
-    const double lmax = symbol_lambda_max(p, S);
-    p->dt_max = (lmax > 0 && kern->rho > 0) ? 2.0 / std::sqrt(lmax / kern->rho) : 0.0;
-
-    pd_status s = (dtype == PD_F32) ? plan_alloc<float>(p, st, mask ? mask->chi_B : nullptr, mask ? mask->chi_Omega : nullptr)
-                                    : plan_alloc<double>(p, st, mask ? mask->chi_B : nullptr, mask ? mask->chi_Omega : nullptr);
-    if (s == PD_OK)
-        s = (dtype == PD_F32) ? build_device_tables<float>(p, S, st) : build_device_tables<double>(p, S, st);
-    if (s == PD_OK && (flags & PD_PLAN_MIXED)) {
-        if (dtype != PD_F64) s = PD_EINVAL;
-        else s = plan_create_impl(grid, hz, kern, mask, PD_F32, 0, st, &p->sub32);
-        if (s == PD_OK) p->sub32->parent = p;
-    }
-    if (s != PD_OK) {
-        plan_free(p);
-        return s;
-    }
-    *out = p;
-    return PD_OK;
-}
-
-// ------------------------------------------------------------------ force
-template <class T>
-pd_status force_impl(pd_plan p, const T* u, const void* weight, T* L, T* W, hipStream_t st) {
-    const int D = p->dim;
-    const pd_weight_kind wk = p->kern.weight;
-    if (wk != PD_WEIGHT_NONE && !weight) return PD_EINVAL;
-    if (p->kern.model == PD_LPS_LINEAR) {
-        if (W) return PD_EUNSUPPORTED;
-        // stage A: dilatation
-        GenU<T, 3, WK_NONE, false, false, false> gA{};
-        gA.c = ctx<T>(p);
-        gA.u = const_cast<T*>(u);
-        FinTheta<T> fA{};
-        fA.c = ctx<T>(p);
-        fA.u = u;
-        fA.theta = reinterpret_cast<T*>(p->theta);
-        PD_TRY(run_chain<T>(p, gA, MulLPSA<T>{}, fA, st, 0, 3));
-        // stage B: force
-        GenTheta<T> gB{};
-        gB.c = ctx<T>(p);
-        gB.theta = reinterpret_cast<const T*>(p->theta);
-        MulLPSB<T> mB{};
-        mB.ka = T(p->ka);
-        FinLin<T, 3, 0, false, true> fB{};
-        fB.c = ctx<T>(p);
-        fB.ka = T(p->ka);
-        fB.u = u;
-        fB.theta = reinterpret_cast<const T*>(p->theta);
-        fB.L = L;
-        return run_chain<T>(p, gB, mB, fB, st, 3);
-    }
-    // bond-based
-    auto go = [&](auto Dc) -> pd_status {
-        constexpr int DD = decltype(Dc)::value;
-        if (wk == PD_WEIGHT_NONE && !W) {
-            GenU<T, DD, WK_NONE, false, false, false> gg{};
-            gg.c = ctx<T>(p);
-            gg.u = const_cast<T*>(u);
-            FinLin<T, DD, 0, false, false> ff{};
-            ff.c = ctx<T>(p);
-            ff.u = u;
-            ff.L = L;
-            return run_chain<T>(p, gg, MulBB<T, DD, false, false>{}, ff, st);
-        }
-        if constexpr (DD == 3) {
-            return PD_EUNSUPPORTED;  // weighted bond-based chains are built for 2D plates
-        } else {
-        auto weighted = [&](auto WKc) -> pd_status {
-            constexpr int WK = decltype(WKc)::value;
-            const uint8_t* lam = (WK == WK_LAMBDA) ? reinterpret_cast<const uint8_t*>(weight) : nullptr;
-            const T* s = (WK == WK_SCALE) ? reinterpret_cast<const T*>(weight) : nullptr;
-            if (W) {
-                GenU<T, DD, WK, true, true, false> gg{};
-                gg.c = ctx<T>(p);
-                gg.u = const_cast<T*>(u);
-                gg.lam_in = lam;
-                gg.s = s;
-                FinBB<T, DD, WK, true, true, false, false> ff{};
-                ff.c = ctx<T>(p);
-                ff.u = u; ff.lam = lam; ff.s = s; ff.L = L; ff.Wout = W;
-                return run_chain<T>(p, gg, MulBB<T, DD, true, true>{}, ff, st);
-            } else {
-                GenU<T, DD, WK, true, false, false> gg{};
-                gg.c = ctx<T>(p);
-                gg.u = const_cast<T*>(u);
-                gg.lam_in = lam;
-                gg.s = s;
-                FinBB<T, DD, WK, true, false, false, false> ff{};
-                ff.c = ctx<T>(p);
-                ff.u = u; ff.lam = lam; ff.s = s; ff.L = L;
-                return run_chain<T>(p, gg, MulBB<T, DD, true, false>{}, ff, st);
-            }
-        };
-        if (wk == PD_WEIGHT_INTEGRITY) return weighted(std::integral_constant<int, WK_LAMBDA>{});
-        if (wk == PD_WEIGHT_SCALE) return weighted(std::integral_constant<int, WK_SCALE>{});
-        return weighted(std::integral_constant<int, WK_NONE>{});
-        }
-    };
-    return D == 2 ? go(std::integral_constant<int, 2>{}) : go(std::integral_constant<int, 3>{});
-}
-
-}  // namespace
-
-// ------------------------------------------------------- elementwise kernels
-namespace {
-
-constexpr int EW_THREADS = 256;
-
-// grid-stride elementwise kernels use at most 2048 blocks (partials capacity)
-inline unsigned ew_blocks(long n) { return (unsigned)std::max<long>(1, std::min<long>((n + EW_THREADS - 1) / EW_THREADS, 2048L)); }
-
-// y[k] += x[k]  (k < n)
-template <class T>
-__global__ void k_add(T* __restrict__ y, const T* __restrict__ x, long n) {
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) y[k] += x[k];
-}
-
-// u = chi_O u + (1 - chi_O) w   and   t = (1 - chi_O) w
-template <class T>
-__global__ void k_constrain(T* __restrict__ u, T* __restrict__ t, const T* __restrict__ w,
-                            const uint8_t* __restrict__ chiO, long n) {
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        const T wk = w ? w[k] : T(0);
-        if (u) u[k] = chiO[k] ? u[k] : wk;
-        if (t) t[k] = chiO[k] ? T(0) : wk;
-    }
-}
-
-// Block partial sums of NR FP64 accumulators, written to part[blockIdx*NR].
-template <int NR>
-__device__ __forceinline__ void ew_block_reduce(double (&acc)[NR], double* part) {
-    __shared__ double sm[(EW_THREADS / 64) * 4];
-    block_reduce_store<NR>(acc, part + (long)blockIdx.x * NR, sm);
-}
-
-// CG update: x += a p; r -= a Ap; partial |r|^2.   (types may differ: x is
-// the iterate precision, r/p/Ap the operator precision)
-template <class TX, class T>
-__global__ void k_cg_update(TX* __restrict__ x, const T* __restrict__ p, T* __restrict__ r, const T* __restrict__ Ap,
-                            const double* __restrict__ coef, long n, double* __restrict__ part) {
-    const double a = coef[0];
-    double acc[1] = {0.0};
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        x[k] = TX(double(x[k]) + a * double(p[k]));
-        T rk = T(double(r[k]) - a * double(Ap[k]));
-        r[k] = rk;
-        acc[0] += double(rk) * double(rk);
-    }
-    ew_block_reduce<1>(acc, part);
-}
-
-// p = r + b p
-template <class T>
-__global__ void k_cg_dir(T* __restrict__ p, const T* __restrict__ r, const double* __restrict__ coef, long n) {
-    const double b = coef[0];
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
-        p[k] = T(double(r[k]) + b * double(p[k]));
-}
-
-// r32 = scale * r64;  p32 = r32;  d32 = 0; partial |r32|^2
-__global__ void k_ir_start(const double* __restrict__ r64, double scale, float* __restrict__ r32, float* __restrict__ p32,
-                           float* __restrict__ d32, long n, double* __restrict__ part) {
-    double acc[1] = {0.0};
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        float v = float(r64[k] * scale);
-        r32[k] = v;
-        p32[k] = v;
-        d32[k] = 0.0f;
-        acc[0] += double(v) * double(v);
-    }
-    ew_block_reduce<1>(acc, part);
-}
-
-// x64 += d32 / scale
-__global__ void k_ir_update(double* __restrict__ x, const float* __restrict__ d, double inv_scale, long n) {
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
-        x[k] += double(d[k]) * inv_scale;
-}
-
-// Verlet adjoint helpers
-template <class T>
-__global__ void k_mask_copy(T* __restrict__ a, const T* __restrict__ vb, const uint8_t* __restrict__ chiO, long n) {
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
-        a[k] = chiO[k] ? vb[k] : T(0);
-}
-// ut = chi_O (ub + c1 La)
-template <class T>
-__global__ void k_vva_ut(T* __restrict__ ut, const T* __restrict__ ub, const T* __restrict__ La, T c1,
-                         const uint8_t* __restrict__ chiO, long n) {
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
-        ut[k] = chiO[k] ? ub[k] + c1 * La[k] : T(0);
-}
-// ub = c1 La + ut + c2 Lut;  vb = a + dt ut
-template <class T>
-__global__ void k_vva_final(T* __restrict__ ub, T* __restrict__ vb, const T* __restrict__ a, const T* __restrict__ ut,
-                            const T* __restrict__ La, const T* __restrict__ Lut, T c1, T c2, T dt, long n) {
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        ub[k] = c1 * La[k] + ut[k] + c2 * Lut[k];
-        vb[k] = a[k] + dt * ut[k];
-    }
-}
-
-// single-thread scalar ops on device values (alpha = num/den etc.)
-__global__ void k_ratio(const double* __restrict__ num, const double* __restrict__ den, double* __restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = (den[0] != 0.0) ? num[0] / den[0] : 0.0;
-}
-
-template <int NR>
-pd_status ew_finish(pd_plan p, unsigned nblk, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, p->partials, (long)nblk, NR, out);
-    return pdh::check(hipGetLastError());
-}
-
-pd_status fetch_red(pd_plan p, int n, hipStream_t st, double* dst) {
-    HIP_TRY(hipMemcpyAsync(p->red_host, p->red, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    for (int i = 0; i < n; ++i) dst[i] = p->red_host[i];
-    return PD_OK;
-}
-
-// ------------------------------------------------------------ operator kinds
-// Apply one linear chain with a FinLin epilogue: MODE 0 force, 2 CG operator
-// Ap = -chi_O L(x), 3 residual chi_O (L(x) + b).  Unweighted plans only.
-template <class T, int MODE>
-pd_status lin_apply(pd_plan p, const T* x, T* out, const T* b, hipStream_t st) {
-    const int D = p->dim;
-    if (p->kern.model == PD_LPS_LINEAR) {
-        GenU<T, 3, WK_NONE, false, false, false> gA{};
-        gA.c = ctx<T>(p);
-        gA.u = const_cast<T*>(x);
-        FinTheta<T> fA{};
-        fA.c = ctx<T>(p);
-        fA.u = x;
-        fA.theta = reinterpret_cast<T*>(p->theta);
-        PD_TRY(run_chain<T>(p, gA, MulLPSA<T>{}, fA, st, 0, 3));
-        GenTheta<T> gB{};
-        gB.c = ctx<T>(p);
-        gB.theta = reinterpret_cast<const T*>(p->theta);
-        MulLPSB<T> mB{};
-        mB.ka = T(p->ka);
-        FinLin<T, 3, MODE, false, true> fB{};
-        fB.c = ctx<T>(p);
-        fB.ka = T(p->ka);
-        fB.u = x;
-        fB.theta = reinterpret_cast<const T*>(p->theta);
-        fB.L = out;
-        fB.b = b;
-        return run_chain<T>(p, gB, mB, fB, st, 3);
-    }
-    auto go = [&](auto Dc) -> pd_status {
-        constexpr int DD = decltype(Dc)::value;
-        GenU<T, DD, WK_NONE, false, false, false> gg{};
-        gg.c = ctx<T>(p);
-        gg.u = const_cast<T*>(x);
-        FinLin<T, DD, MODE, false, false> ff{};
-        ff.c = ctx<T>(p);
-        ff.u = x;
-        ff.L = out;
-        ff.b = b;
-        return run_chain<T>(p, gg, MulBB<T, DD, false, false>{}, ff, st);
-    };
-    return D == 2 ? go(std::integral_constant<int, 2>{}) : go(std::integral_constant<int, 3>{});
-}
-
-// --------------------------------------------------------------- Verlet
-template <class T, bool ENRED>
-pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, hipStream_t st) {
-    const int D = p->dim;
-    const T rho = T(p->kern.rho);
-    const T c1 = dt / (T(2) * rho), c2 = dt * dt / (T(2) * rho);
-    T* u = reinterpret_cast<T*>(S->u);
-    T* v = reinterpret_cast<T*>(S->v);
-    T* F = reinterpret_cast<T*>(S->F);
-    if (p->kern.model == PD_LPS_LINEAR) {
-        GenU<T, 3, WK_NONE, false, false, true> gA{};
-        gA.c = ctx<T>(p);
-        gA.u = u; gA.v = v; gA.F = F; gA.w = w; gA.dt = dt; gA.c2 = c2;
-        FinTheta<T> fA{};
-        fA.c = ctx<T>(p);
-        fA.u = u;
-        fA.theta = reinterpret_cast<T*>(p->theta);
-        PD_TRY(run_chain<T>(p, gA, MulLPSA<T>{}, fA, st, 0, 3));
-        GenTheta<T> gB{};
-        gB.c = ctx<T>(p);
-        gB.theta = reinterpret_cast<const T*>(p->theta);
-        MulLPSB<T> mB{};
-        mB.ka = T(p->ka);
-        FinLin<T, 3, 1, ENRED, true> fB{};
-        fB.c = ctx<T>(p);
-        fB.ka = T(p->ka); fB.u = u; fB.theta = reinterpret_cast<const T*>(p->theta);
-        fB.v = v; fB.F = F; fB.b = b; fB.c1 = c1; fB.rho = rho;
-        return run_chain<T>(p, gB, mB, fB, st, 3);
-    }
-    auto go = [&](auto Dc) -> pd_status {
-        constexpr int DD = decltype(Dc)::value;
-        const pd_weight_kind wk = p->kern.weight;
-        if (wk == PD_WEIGHT_NONE) {
-            GenU<T, DD, WK_NONE, false, false, true> gg{};
-            gg.c = ctx<T>(p);
-            gg.u = u; gg.v = v; gg.F = F; gg.w = w; gg.dt = dt; gg.c2 = c2;
-            FinLin<T, DD, 1, ENRED, false> ff{};
-            ff.c = ctx<T>(p);
-            ff.u = u; ff.v = v; ff.F = F; ff.b = b; ff.c1 = c1; ff.rho = rho;
-            return run_chain<T>(p, gg, MulBB<T, DD, false, false>{}, ff, st);
-        }
-        if constexpr (DD == 3) {
-            return PD_EUNSUPPORTED;
-        } else {
-        auto weighted = [&](auto WKc, auto Ec) -> pd_status {
-            constexpr int WK = decltype(WKc)::value;
-            constexpr bool E = decltype(Ec)::value;
-            GenU<T, DD, WK, true, E, true> gg{};
-            gg.c = ctx<T>(p);
-            gg.u = u; gg.v = v; gg.F = F; gg.w = w; gg.dt = dt; gg.c2 = c2;
-            gg.lam_in = S->lambda; gg.lam_out = S->lambda; gg.s = reinterpret_cast<const T*>(S->s);
-            gg.W = reinterpret_cast<const T*>(S->W); gg.Wc = T(p->Wc); gg.fail = (E && p->Wc > 0) ? 1 : 0;
-            FinBB<T, DD, WK, true, E, true, ENRED> ff{};
-            ff.c = ctx<T>(p);
-            ff.u = u; ff.lam = S->lambda; ff.s = reinterpret_cast<const T*>(S->s); ff.Wout = reinterpret_cast<T*>(S->W);
-            ff.v = v; ff.F = F; ff.b = b; ff.c1 = c1; ff.rho = rho;
-            return run_chain<T>(p, gg, MulBB<T, DD, true, E>{}, ff, st);
-        };
-        if (wk == PD_WEIGHT_INTEGRITY) {
-            if (S->W) return weighted(std::integral_constant<int, WK_LAMBDA>{}, std::true_type{});
-            return weighted(std::integral_constant<int, WK_LAMBDA>{}, std::false_type{});
-        }
-        return weighted(std::integral_constant<int, WK_SCALE>{}, std::false_type{});
-        }
-    };
-    return D == 2 ? go(std::integral_constant<int, 2>{}) : go(std::integral_constant<int, 3>{});
-}
-
-template <class T>
-pd_status force_impl_any(pd_plan p, const T* u, const void* weight, T* L, T* W, hipStream_t st);
-
-template <class T>
-pd_status verlet_impl(pd_plan p, pd_state* S, const T* b, const T* w, double dt, int nsteps, double* energy,
-                      hipStream_t st) {
-    if (!S || !S->u || !S->v || !S->F) return PD_EINVAL;
-    if (!(dt > 0) || nsteps < 0) return PD_EINVAL;
-    if (p->dt_max > 0 && dt > p->dt_max) return PD_EINVAL;
-    if (p->kern.weight == PD_WEIGHT_INTEGRITY && !S->lambda) return PD_EINVAL;
-    if (p->kern.weight == PD_WEIGHT_SCALE && !S->s) return PD_EINVAL;
-    if (p->kern.weight == PD_WEIGHT_INTEGRITY && p->Wc > 0 && !S->W) return PD_EINVAL;
-    const long n = p->nb * p->dim;
-    if (S->step == 0) {
-        const void* wgt = (p->kern.weight == PD_WEIGHT_INTEGRITY) ? (const void*)S->lambda
-                          : (p->kern.weight == PD_WEIGHT_SCALE) ? (const void*)S->s : nullptr;
-        T* Wp = (p->kern.weight == PD_WEIGHT_INTEGRITY && S->W) ? reinterpret_cast<T*>(S->W) : nullptr;
-        PD_TRY(force_impl_any<T>(p, reinterpret_cast<const T*>(S->u), wgt, reinterpret_cast<T*>(S->F), Wp, st));
-        if (b) {
-            hipLaunchKernelGGL(k_add<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, st, reinterpret_cast<T*>(S->F), b, n);
-            HIP_TRY(hipGetLastError());
-        }
-    }
-    for (int k = 0; k < nsteps; ++k) {
-        if (energy) {
-            PD_TRY((verlet_one<T, true>(p, S, b, w, T(dt), st)));
-            double r[4];
-            PD_TRY(fetch_red(p, 4, st, r));
-            const double dV = p->dV;
-            energy[4 * k + 0] = r[0] * dV;
-            energy[4 * k + 1] = r[1] * dV;
-            energy[4 * k + 2] = r[2] * dV;
-            energy[4 * k + 3] = (r[0] + r[1] + r[2]) * dV - dt * dt / (8.0 * p->kern.rho) * r[3] * dV;
-            for (int q = 0; q < 4; ++q)
-                if (!std::isfinite(energy[4 * k + q])) return PD_ENUMERIC;
-        } else {
-            PD_TRY((verlet_one<T, false>(p, S, b, w, T(dt), st)));
-        }
-        S->step += 1;
-    }
-    return PD_OK;
-}
-
-// -------------------------------------------------------------- force
-template <class T>
-pd_status force_impl_any(pd_plan p, const T* u, const void* weight, T* L, T* W, hipStream_t st) {
-    return force_impl<T>(p, u, weight, L, W, st);
-}
-
-// ------------------------------------------------------------- adjoint
-template <class T>
-pd_status adjoint_impl(pd_plan p, const T* u, const T* u2, const void* weight, const T* g, T* ubar, T* wbar,
-                       T wscale, int accumulate, hipStream_t st) {
-    if (!wbar) {
-        if (!ubar) return PD_OK;
-        if (p->kern.weight == PD_WEIGHT_NONE) return lin_apply<T, 0>(p, g, ubar, nullptr, st);
-        return force_impl<T>(p, g, weight, ubar, nullptr, st);
-    }
-    if (p->kern.weight != PD_WEIGHT_SCALE || p->kern.model != PD_BB_LINEAR) return PD_EUNSUPPORTED;
-    if (!weight) return PD_EINVAL;
-    if (p->dim != 2) return PD_EUNSUPPORTED;
-    auto go = [&](auto Dc) -> pd_status {
-        constexpr int DD = decltype(Dc)::value;
-        GenAdj<T, DD, WK_SCALE> gg{};
-        gg.c = ctx<T>(p);
-        gg.u = u; gg.u2 = u2; gg.g = g; gg.s = reinterpret_cast<const T*>(weight);
-        FinAdj<T, DD, WK_SCALE> ff{};
-        ff.c = ctx<T>(p);
-        ff.u = u; ff.u2 = u2; ff.g = g; ff.s = reinterpret_cast<const T*>(weight);
-        ff.ubar = ubar; ff.wbar = wbar; ff.wscale = wscale; ff.accumulate = accumulate;
-        return run_chain<T>(p, gg, MulAdj<T, DD>{}, ff, st);
-    };
-    return go(std::integral_constant<int, 2>{});
-}
-
-template <class T>
-pd_status verlet_adjoint_impl(pd_plan p, const T* un, const T* unp1, const T* s, T* ub, T* vb, T* sb, double dt,
-                              hipStream_t st) {
-    if (!un || !unp1 || !ub || !vb) return PD_EINVAL;
-    if (p->kern.weight == PD_WEIGHT_INTEGRITY) return PD_EUNSUPPORTED;
-    if (p->kern.weight == PD_WEIGHT_SCALE && !s) return PD_EINVAL;
-    const long n = p->nb * p->dim;
-    // scratch: a, La, ut, Lut  (4 vector fields of T)
-    T* a = reinterpret_cast<T*>(p->vtmp);
-    T* La = a + n;            // vtmp and vtmp2 each hold two vector fields
-    T* ut = reinterpret_cast<T*>(p->vtmp2);
-    T* Lut = ut + n;
-    const T rho = T(p->kern.rho), c1 = T(dt / (2.0 * p->kern.rho)), c2 = T(dt * dt / (2.0 * p->kern.rho));
-    (void)rho;
-    const void* wgt = (p->kern.weight == PD_WEIGHT_SCALE) ? (const void*)s : nullptr;
-    hipLaunchKernelGGL(k_mask_copy<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, st, a, (const T*)vb, p->chiO, n);
-    HIP_TRY(hipGetLastError());
-    PD_TRY(adjoint_impl<T>(p, un, unp1, wgt, a, La, sb, c1, 1, st));
-    hipLaunchKernelGGL(k_vva_ut<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, st, ut, (const T*)ub, (const T*)La, c1,
-                       p->chiO, n);
-    HIP_TRY(hipGetLastError());
-    PD_TRY(adjoint_impl<T>(p, un, nullptr, wgt, ut, Lut, sb, c2, 1, st));
-    hipLaunchKernelGGL(k_vva_final<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, st, ub, vb, (const T*)a, (const T*)ut,
-                       (const T*)La, (const T*)Lut, c1, c2, T(dt), n);
-    return pdh::check(hipGetLastError());
-}
-
-// --------------------------------------------------------- static solve
-// Plain CG in the plan precision on A = -chi_O L chi_O; x holds the full
-// displacement (constrained components already = w).  Vectors r, pp, Ap of
-// type T.  Returns the number of operator applications used.
-template <class T, class TX>
-pd_status cg_run(pd_plan p, TX* x_unused, T* xT, T* r, T* pp, T* Ap, double rr0, double stop2, int maxit, int* its,
-                 int* applies, double* rr_out, hipStream_t st) {
-    (void)x_unused;
-    const long n = p->nb * p->dim;
-    double rr = rr0;
-    int it = 0;
-    HIP_TRY(hipMemcpyAsync(pp, r, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
-    double* dev = p->red;      // [0] pAp, [1] alpha, [2] rr_new, [3] beta, [4] rr
-    while (it < maxit && rr > stop2) {
-        PD_TRY((lin_apply<T, 2>(p, pp, Ap, nullptr, st)));   // red[0] = p.Ap
-        // alpha = rr / pAp  (rr kept on the host, pushed to red[4])
-        p->red_host[4] = rr;
-        HIP_TRY(hipMemcpyAsync(dev + 4, p->red_host + 4, sizeof(double), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, st, dev + 4, dev + 0, dev + 1);
-        const unsigned nb = ew_blocks(n);
-        hipLaunchKernelGGL((k_cg_update<T, T>), dim3(nb), dim3(EW_THREADS), 0, st, xT, (const T*)pp, r, (const T*)Ap,
-                           (const double*)(dev + 1), n, p->partials);
-        PD_TRY(ew_finish<1>(p, nb, dev + 2, st));
-        double v[3];
-        PD_TRY(fetch_red(p, 3, st, v));
-        const double rr_new = v[2];
-        ++it;
-        if (!std::isfinite(rr_new)) return PD_ENUMERIC;
-        if (rr_new <= stop2) { rr = rr_new; break; }
-        p->red_host[3] = rr_new / rr;
-        HIP_TRY(hipMemcpyAsync(dev + 3, p->red_host + 3, sizeof(double), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_cg_dir<T>, dim3(nb), dim3(EW_THREADS), 0, st, pp, (const T*)r, (const double*)(dev + 3), n);
-        HIP_TRY(hipGetLastError());
-        rr = rr_new;
-    }
-    *its = it;
-    *applies = it;
-    *rr_out = rr;
-    return PD_OK;
-}
-
-pd_status static_solve_impl(pd_plan p, const double* b, const double* w, double* u, double rtol, int maxit, int mixed,
-                            pd_solve_info* info, hipStream_t st) {
-    if (p->dtype != PD_F64) return PD_EINVAL;
-    if (p->kern.weight != PD_WEIGHT_NONE) return PD_EUNSUPPORTED;
-    if (!b || !u || !(rtol > 0) || maxit <= 0) return PD_EINVAL;
-    if (mixed && !p->sub32) return PD_EINVAL;
-    const long n = p->nb * p->dim;
-    pd_solve_info inf{};
-    double *r = nullptr, *pp = nullptr, *Ap = nullptr, *t = nullptr;
-    float *r32 = nullptr, *p32 = nullptr, *Ap32 = nullptr, *d32 = nullptr;
-    auto cleanup = [&]() {
-        void* bufs[] = {r, pp, Ap, t, r32, p32, Ap32, d32};
-        for (void* q : bufs)
-            if (q) (void)hipFree(q);
-    };
-    auto fail = [&](pd_status s) { cleanup(); return s; };
-#define SOLVE_TRY(x)                       \
-    do {                                   \
-        pd_status s2_ = (x);               \
-        if (s2_ != PD_OK) return fail(s2_); \
-    } while (0)
-    SOLVE_TRY(pdh::check(hipMalloc(&r, sizeof(double) * n)));
-    SOLVE_TRY(pdh::check(hipMalloc(&t, sizeof(double) * n)));
-    // x = chi_O u + (1 - chi_O) w ; t = (1 - chi_O) w
-    hipLaunchKernelGGL(k_constrain<double>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, st, u, t, w, p->chiO, n);
-    SOLVE_TRY(pdh::check(hipGetLastError()));
-    // |rhs|^2 = |chi_O (L((1 - chi_O) w) + b)|^2
-    SOLVE_TRY((lin_apply<double, 3>(p, t, r, b, st)));
-    double v[1];
-    SOLVE_TRY(fetch_red(p, 1, st, v));
-    inf.applies_fp64 += 1;
-    double bn2 = v[0] > 0 ? v[0] : 1.0;
-    const double stop2 = rtol * rtol * bn2;
-    // r = chi_O (L(x) + b)
-    SOLVE_TRY((lin_apply<double, 3>(p, u, r, b, st)));
-    SOLVE_TRY(fetch_red(p, 1, st, v));
-    inf.applies_fp64 += 1;
-    double rr = v[0];
-    pd_status result = PD_OK;
-    if (!mixed) {
-        SOLVE_TRY(pdh::check(hipMalloc(&pp, sizeof(double) * n)));
-        SOLVE_TRY(pdh::check(hipMalloc(&Ap, sizeof(double) * n)));
-        int its = 0, app = 0;
-        double rr_end = rr;
-        SOLVE_TRY((cg_run<double, double>(p, u, u, r, pp, Ap, rr, stop2, maxit, &its, &app, &rr_end, st)));
-        inf.iters_fp64 = its;
-        inf.applies_fp64 += app;
-    } else {
-        pd_plan q = p->sub32;
-        SOLVE_TRY(pdh::check(hipMalloc(&r32, sizeof(float) * n)));
-        SOLVE_TRY(pdh::check(hipMalloc(&p32, sizeof(float) * n)));
-        SOLVE_TRY(pdh::check(hipMalloc(&Ap32, sizeof(float) * n)));
-        SOLVE_TRY(pdh::check(hipMalloc(&d32, sizeof(float) * n)));
-        int budget = maxit;
-        while (rr > stop2 && budget > 0) {
-            // inner FP32 CG on A d = r (normalised), FP64 inner products
-            const double scale = 1.0 / std::sqrt(rr);
-            const unsigned nb = ew_blocks(n);
-            hipLaunchKernelGGL(k_ir_start, dim3(nb), dim3(EW_THREADS), 0, st, (const double*)r, scale, r32, p32, d32, n,
-                               q->partials);
-            SOLVE_TRY(pdh::check(hipGetLastError()));
-            SOLVE_TRY(ew_finish<1>(q, nb, q->red, st));
-            SOLVE_TRY(fetch_red(q, 1, st, v));
-            const double rr32 = v[0];
-            // inner target: the remaining reduction, but no tighter than FP32 allows
-            const double need = std::sqrt(stop2 / rr);
-            const double tol_in = std::max(need * 0.5, 1e-5);
-            int its = 0, app = 0;
-            double rr_end = 0;
-            // p32 is re-initialised inside cg_run from r32
-            SOLVE_TRY((cg_run<float, float>(q, d32, d32, r32, p32, Ap32, rr32, tol_in * tol_in * rr32, budget, &its,
-                                            &app, &rr_end, st)));
-            inf.iters_fp32 += its;
-            inf.applies_fp32 += app;
-            budget -= std::max(its, 1);
-            hipLaunchKernelGGL(k_ir_update, dim3(nb), dim3(EW_THREADS), 0, st, u, (const float*)d32, 1.0 / scale, n);
-            SOLVE_TRY(pdh::check(hipGetLastError()));
-            // FP64 residual
-            SOLVE_TRY((lin_apply<double, 3>(p, u, r, b, st)));
-            SOLVE_TRY(fetch_red(p, 1, st, v));
-            inf.applies_fp64 += 1;
-            inf.iters_fp64 += 1;
-            if (!std::isfinite(v[0])) return fail(PD_ENUMERIC);
-            rr = v[0];
-        }
-    }
-    // true FP64 residual of the returned iterate
-    SOLVE_TRY((lin_apply<double, 3>(p, u, r, b, st)));
-    SOLVE_TRY(fetch_red(p, 1, st, v));
-    inf.applies_fp64 += 1;
-    inf.rel_res = std::sqrt(v[0] / bn2);
-    if (!(inf.rel_res <= rtol)) result = std::isfinite(inf.rel_res) ? PD_ENOTCONV : PD_ENUMERIC;
-    if (info) *info = inf;
-    cleanup();
-#undef SOLVE_TRY
-    return result;
-}
-
-// ---------------------------------------------------------- damage index
-template <class T>
-pd_status damage_impl(pd_plan p, const uint8_t* lam, T* d, hipStream_t st) {
-    if (p->kern.model != PD_BB_LINEAR || p->kern.weight != PD_WEIGHT_INTEGRITY) return PD_EUNSUPPORTED;
-    if (!lam || !d) return PD_EINVAL;
-    auto go = [&](auto Dc) -> pd_status {
-        constexpr int DD = decltype(Dc)::value;
-        GenPhi<T> gg{};
-        gg.c = ctx<T>(p);
-        gg.lam = lam;
-        FinCount<T> ff{};
-        ff.c = ctx<T>(p);
-        ff.beta_comp = p->beta_comp;
-        ff.lam = lam;
-        ff.d = d;
-        return run_chain<T>(p, gg, MulCount<T, DD>{}, ff, st);
-    };
-    if (p->dim != 2) return PD_EUNSUPPORTED;
-    return go(std::integral_constant<int, 2>{});
-}
-
-// ------------------------------------------------------------ test chain
-// Correlation with the separable kernel K(o) = prod_d k_d(o_d), k_d(o) =
-// [o = s_d] + (-1)^{p_d} [o = -s_d] (s_d > 0) or [o = 0] (s_d = 0).
-template <class T>
-pd_status test_conv_impl(pd_plan p, const T* x, const int* sh, int parity, T* out, hipStream_t st) {
-    const int D = p->dim;
-    std::vector<int> offs;
-    std::vector<double> kv;
-    int P = 0;
-    for (int d = 0; d < D; ++d) {
-        if (sh[d] < 0) return PD_EINVAL;
-        if (((parity >> d) & 1) && sh[d] == 0) return PD_EINVAL;
-        P += (parity >> d) & 1;
-    }
-    int cnt[3] = {1, 1, 1};
-    for (int d = 0; d < D; ++d) cnt[d] = sh[d] ? 2 : 1;
-    for (int a = 0; a < cnt[0]; ++a)
-        for (int bq = 0; bq < cnt[1]; ++bq)
-            for (int c = 0; c < cnt[2]; ++c) {
-                int sg[3] = {a ? -1 : 1, bq ? -1 : 1, c ? -1 : 1};
-                double val = 1.0;
-                for (int d = 0; d < D; ++d)
-                    if (((parity >> d) & 1) && sg[d] < 0) val = -val;
-                offs.push_back(sg[0] * sh[0]);
-                offs.push_back(sg[1] * sh[1]);
-                offs.push_back(D == 3 ? sg[2] * sh[2] : 0);
-                kv.push_back(val);
-            }
-    const int ns = (int)kv.size();
-    const int ntap = sh[D - 1] + 1;
-    if (ntap > 9) return PD_EUNSUPPORTED;
-    uint8_t par[3] = {(uint8_t)(parity & 1), (uint8_t)((parity >> 1) & 1), (uint8_t)((parity >> 2) & 1)};
-    const Geo& g = p->geo;
-    const long NP = (D == 2) ? (long)g.h1 : (long)g.h1 * g.n2;
-    int* od = nullptr;
-    double* kd = nullptr;
-    uint8_t* pd = nullptr;
-    T* taps = nullptr;
-    pd_status s = PD_OK;
-    s = pdh::check(hipMalloc(&od, sizeof(int) * offs.size()));
-    if (s == PD_OK) s = pdh::check(hipMalloc(&kd, sizeof(double) * kv.size()));
-    if (s == PD_OK) s = pdh::check(hipMalloc(&pd, 3));
-    if (s == PD_OK) s = pdh::check(hipMalloc(&taps, sizeof(T) * NP * ntap));
-    if (s == PD_OK) {
-        (void)hipMemcpyAsync(od, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice, st);
-        (void)hipMemcpyAsync(kd, kv.data(), sizeof(double) * kv.size(), hipMemcpyHostToDevice, st);
-        (void)hipMemcpyAsync(pd, par, 3, hipMemcpyHostToDevice, st);
-        long nn = NP * ntap;
-        hipLaunchKernelGGL((k_taps<T>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, D, g.n1, g.n2, g.h1, NP, ntap,
-                           ns, od, kd, 1, 1, pd, p->tw64, 1.0 / (double)p->nfft, 2.0 / (double)p->nfft, taps);
-        s = pdh::check(hipGetLastError());
-    }
-    if (s == PD_OK) {
-        GenScalar<T> gg{};
-        gg.x = x;
-        MulTest<T> mm{};
-        mm.P = P;
-        FinScalar<T> ff{};
-        ff.out = out;
-        s = run_chain<T>(p, gg, mm, ff, st, 0, 0, taps, ntap, 1, (uint32_t)par[D - 1]);
-    }
-    (void)hipStreamSynchronize(st);
-    if (od) (void)hipFree(od);
-    if (kd) (void)hipFree(kd);
-    if (pd) (void)hipFree(pd);
-    if (taps) (void)hipFree(taps);
-    return s;
-}
-
-inline hipStream_t S_(void* s) { return reinterpret_cast<hipStream_t>(s); }
-
-}  // namespace
-
-// ===================================================================== C ABI
 extern "C" {
 
 pd_status pd_plan_create(const pd_grid* grid, const pd_horizon* horizon, const pd_kernel* kernel, const pd_mask* mask,

@@ -889,6 +889,6 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
 
 // Deterministic final sum of per-block partials: out[r] = sum_b part[b*NR + r]
 // (one block, fixed order tree).
-__global__ void k_reduce_final(const double* __restrict__ part, long nblk, int NR, double* __restrict__ out);
+static __global__ void k_reduce_final(const double* __restrict__ part, long nblk, int NR, double* __restrict__ out);
 
 }  // namespace pdk
