@@ -198,8 +198,9 @@ pd_status pd_verlet_adjoint(pd_plan plan, const void* u_n, const void* u_np1, co
                             void* u_bar, void* v_bar, void* s_bar, double dt, void* stream);
 
 typedef struct {
-    int iters_fp64;        /* FP64 CG iterations (plain solve) or outer refinements (mixed) */
-    int iters_fp32;        /* inner FP32 CG iterations (mixed) */
+    int iters_fp64;        /* FP64 CG iterations (plain solve) or FP64 residual
+                              replacements (mixed) */
+    int iters_fp32;        /* CG iterations with the FP32 operator (mixed) */
     int applies_fp64;      /* FP64 operator applications */
     int applies_fp32;      /* FP32 operator applications */
     double rel_res;        /* final |chi_O (L(u) + b)|_2 / |rhs|_2 in FP64 */
@@ -210,10 +211,13 @@ typedef struct {
  * relative residual rtol.  b, w, u_inout are FP64 DEVICE buffers
  * [dim][body] regardless of the plan dtype; u_inout holds the initial guess
  * on entry and the solution (u = w on constrained components) on exit.
- * mixed = 0: plain FP64 CG (PD_F64 plan).  mixed = 1: iterative refinement
- * with an FP64 residual, FP64 inner products and FP64 updates around FP32
- * operator CG iterations (PD_F64 plan created with PD_PLAN_MIXED).
- * PD_ENOTCONV when maxit operator applications did not reach rtol. */
+ * mixed = 0: plain FP64 CG (PD_F64 plan).  mixed = 1 (PD_F64 plan created
+ * with PD_PLAN_MIXED): CG iterations that apply the operator in FP32 to an
+ * FP32 copy of the search direction, with the iterate, residual and
+ * direction updated and every inner product accumulated in FP64, and the
+ * residual replaced by the FP64 residual chi_O (L(u) + b) each time it has
+ * dropped tenfold and at convergence (refinement against the FP64 operator).
+ * PD_ENOTCONV when maxit CG iterations did not reach rtol. */
 pd_status pd_static_solve(pd_plan plan, const void* b, const void* w, void* u_inout, double rtol,
                           int maxit, int mixed, pd_solve_info* info, void* stream);
 
@@ -229,7 +233,7 @@ pd_status pd_damage_index(pd_plan plan, const uint8_t* lambda, void* d_out, void
  * recorded on the launch stream, together with the pass's algorithmic HBM
  * bytes (what the pass must read and write: its spectral slabs, kernel
  * partial spectra and per-node fields, each once).  pd_profile_read waits
- * for the recorded events, aggregates them by pass name (e.g. "zmul_4x3":
+ * for the recorded events, aggregates them by pass name (e.g. "lastmul_4x3":
  * last-axis pass with 4 input and 3 output fields), writes up to cap
  * records, sets *n_out to the number of distinct passes and clears the
  * record list.  Enabling adds two event records per launch. */

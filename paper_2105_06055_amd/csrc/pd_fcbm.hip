@@ -29,7 +29,8 @@ namespace pdi {
                                                      hipStream_t);                                                \
     extern template pd_status cg_run<T, T>(pd_plan, T*, T*, T*, T*, T*, double, double, int, int*, int*, double*, \
                                            hipStream_t);                                                          \
-    extern template pd_status lin_apply<T, 3>(pd_plan, const T*, T*, const T*, hipStream_t);
+    extern template pd_status lin_apply<T, 3>(pd_plan, const T*, T*, const T*, hipStream_t);                      \
+    extern template pd_status lin_apply<T, 2>(pd_plan, const T*, T*, const T*, hipStream_t);
 PD_EXTERN(float)
 PD_EXTERN(double)
 #undef PD_EXTERN

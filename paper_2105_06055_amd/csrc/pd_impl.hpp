@@ -922,24 +922,39 @@ __global__ void k_cg_dir(T* __restrict__ p, const T* __restrict__ r, const doubl
         p[k] = T(double(r[k]) + b * double(p[k]));
 }
 
-// r32 = scale * r64;  p32 = r32;  d32 = 0; partial |r32|^2
-static __global__ void k_ir_start(const double* __restrict__ r64, double scale, float* __restrict__ r32, float* __restrict__ p32,
-                           float* __restrict__ d32, long n, double* __restrict__ part) {
+// Mixed-precision CG vectors: the iterate, residual and direction in FP64,
+// the operator applied in FP32 to an FP32 copy of the direction.
+// p = r;  p32 = (float) r
+static __global__ void k_cgm_start(double* __restrict__ p, float* __restrict__ p32, const double* __restrict__ r, long n) {
+    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        p[k] = r[k];
+        p32[k] = float(r[k]);
+    }
+}
+// x += a p32;  r -= a Ap32  (FP64 accumulation of the FP32 operator output);
+// partial |r|^2
+static __global__ void k_cgm_update(double* __restrict__ x, const float* __restrict__ p32, double* __restrict__ r,
+                                    const float* __restrict__ Ap32, const double* __restrict__ coef, long n,
+                                    double* __restrict__ part) {
+    const double a = coef[0];
     double acc[1] = {0.0};
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        float v = float(r64[k] * scale);
-        r32[k] = v;
-        p32[k] = v;
-        d32[k] = 0.0f;
-        acc[0] += double(v) * double(v);
+        x[k] += a * double(p32[k]);
+        const double rk = r[k] - a * double(Ap32[k]);
+        r[k] = rk;
+        acc[0] += rk * rk;
     }
     ew_block_reduce<1>(acc, part);
 }
-
-// x64 += d32 / scale
-static __global__ void k_ir_update(double* __restrict__ x, const float* __restrict__ d, double inv_scale, long n) {
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
-        x[k] += double(d[k]) * inv_scale;
+// p = r + b p;  p32 = (float) p
+static __global__ void k_cgm_dir(double* __restrict__ p, float* __restrict__ p32, const double* __restrict__ r,
+                                 const double* __restrict__ coef, long n) {
+    const double b = coef[0];
+    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        const double v = r[k] + b * p[k];
+        p[k] = v;
+        p32[k] = float(v);
+    }
 }
 
 // Verlet adjoint helpers
@@ -1247,9 +1262,9 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
     const long n = p->nb * p->dim;
     pd_solve_info inf{};
     double *r = nullptr, *pp = nullptr, *Ap = nullptr, *t = nullptr;
-    float *r32 = nullptr, *p32 = nullptr, *Ap32 = nullptr, *d32 = nullptr;
+    float *p32 = nullptr, *Ap32 = nullptr;
     auto cleanup = [&]() {
-        void* bufs[] = {r, pp, Ap, t, r32, p32, Ap32, d32};
+        void* bufs[] = {r, pp, Ap, t, p32, Ap32};
         for (void* q : bufs)
             if (q) (void)hipFree(q);
     };
@@ -1286,42 +1301,55 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
         inf.iters_fp64 = its;
         inf.applies_fp64 += app;
     } else {
+        // CG with the operator applied in FP32 (sub32 plan) and every vector
+        // update and inner product in FP64; the recursively updated residual
+        // is replaced by the FP64 residual chi_O (L x + b) whenever it has
+        // dropped by a factor 10 since the last replacement and at the end
+        // (residual replacement keeps the FP32 operator's errors from
+        // accumulating in r), so the returned iterate meets rtol in FP64.
         pd_plan q = p->sub32;
-        SOLVE_TRY(pdh::check(hipMalloc(&r32, sizeof(float) * n)));
+        SOLVE_TRY(pdh::check(hipMalloc(&pp, sizeof(double) * n)));
         SOLVE_TRY(pdh::check(hipMalloc(&p32, sizeof(float) * n)));
         SOLVE_TRY(pdh::check(hipMalloc(&Ap32, sizeof(float) * n)));
-        SOLVE_TRY(pdh::check(hipMalloc(&d32, sizeof(float) * n)));
-        int budget = maxit;
-        while (rr > stop2 && budget > 0) {
-            // inner FP32 CG on A d = r (normalised), FP64 inner products
-            const double scale = 1.0 / std::sqrt(rr);
-            const unsigned nb = ew_blocks(n);
-            hipLaunchKernelGGL(k_ir_start, dim3(nb), dim3(EW_THREADS), 0, st, (const double*)r, scale, r32, p32, d32, n,
-                               q->partials);
+        const unsigned nb = ew_blocks(n);
+        double* dev = q->red;   // [0] pAp, [1] alpha, [3] beta, [4] rr (device copies)
+        hipLaunchKernelGGL(k_cgm_start, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const double*)r, n);
+        SOLVE_TRY(pdh::check(hipGetLastError()));
+        double rr_rep = rr;   // |r|^2 at the last replacement
+        int it = 0;
+        while (rr > stop2 && it < maxit) {
+            SOLVE_TRY((lin_apply<float, 2>(q, p32, Ap32, nullptr, st)));   // q->red[0] = p32 . Ap32
+            inf.applies_fp32 += 1;
+            q->red_host[4] = rr;
+            SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + 4, q->red_host + 4, sizeof(double), hipMemcpyHostToDevice, st)));
+            hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, st, dev + 4, dev + 0, dev + 1);
+            hipLaunchKernelGGL(k_cgm_update, dim3(nb), dim3(EW_THREADS), 0, st, u, (const float*)p32, r,
+                               (const float*)Ap32, (const double*)(dev + 1), n, q->partials);
             SOLVE_TRY(pdh::check(hipGetLastError()));
-            SOLVE_TRY(ew_finish<1>(q, nb, q->red, st));
-            SOLVE_TRY(fetch_red(q, 1, st, v));
-            const double rr32 = v[0];
-            // inner target: the remaining reduction, but no tighter than FP32 allows
-            const double need = std::sqrt(stop2 / rr);
-            const double tol_in = std::max(need * 0.5, 1e-5);
-            int its = 0, app = 0;
-            double rr_end = 0;
-            // p32 is re-initialised inside cg_run from r32
-            SOLVE_TRY((cg_run<float, float>(q, d32, d32, r32, p32, Ap32, rr32, tol_in * tol_in * rr32, budget, &its,
-                                            &app, &rr_end, st)));
-            inf.iters_fp32 += its;
-            inf.applies_fp32 += app;
-            budget -= std::max(its, 1);
-            hipLaunchKernelGGL(k_ir_update, dim3(nb), dim3(EW_THREADS), 0, st, u, (const float*)d32, 1.0 / scale, n);
+            SOLVE_TRY(ew_finish<1>(q, nb, dev + 2, st));
+            double w3[3];
+            SOLVE_TRY(fetch_red(q, 3, st, w3));
+            double rr_new = w3[2];
+            ++it;
+            inf.iters_fp32 += 1;
+            if (!std::isfinite(rr_new)) return fail(PD_ENUMERIC);
+            if (rr_new <= stop2 || rr_new <= 1e-2 * rr_rep) {
+                // residual replacement in FP64
+                SOLVE_TRY((lin_apply<double, 3>(p, u, r, b, st)));
+                SOLVE_TRY(fetch_red(p, 1, st, v));
+                inf.applies_fp64 += 1;
+                inf.iters_fp64 += 1;
+                if (!std::isfinite(v[0])) return fail(PD_ENUMERIC);
+                rr_new = v[0];
+                rr_rep = rr_new;
+                if (rr_new <= stop2) { rr = rr_new; break; }
+            }
+            q->red_host[3] = rr_new / rr;
+            SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + 3, q->red_host + 3, sizeof(double), hipMemcpyHostToDevice, st)));
+            hipLaunchKernelGGL(k_cgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const double*)r,
+                               (const double*)(dev + 3), n);
             SOLVE_TRY(pdh::check(hipGetLastError()));
-            // FP64 residual
-            SOLVE_TRY((lin_apply<double, 3>(p, u, r, b, st)));
-            SOLVE_TRY(fetch_red(p, 1, st, v));
-            inf.applies_fp64 += 1;
-            inf.iters_fp64 += 1;
-            if (!std::isfinite(v[0])) return fail(PD_ENUMERIC);
-            rr = v[0];
+            rr = rr_new;
         }
     }
     // true FP64 residual of the returned iterate

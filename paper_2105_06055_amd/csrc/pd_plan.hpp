@@ -6,8 +6,8 @@
 #include <cstdint>
 #include <vector>
 
-#include "../../include/pd_fcbm.h"
-#include "../../include/pd_fcbm_testing.h"
+#include "pd_fcbm.h"
+#include "pd_fcbm_testing.h"
 #include "pd_passes.hpp"
 
 // One timed kernel launch (profiling mode): events recorded on the launch
