@@ -552,8 +552,11 @@ struct IPow {
     }
 };
 
+// FP64: at least two waves per SIMD (<= 256 registers) keeps enough loads in
+// flight; FP32 needs no bound.
 template <class T, class M, int NT>
-__global__ void __launch_bounds__(256) k_lastconv(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps, int nct) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 1 : 2)))
+k_lastconv(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps, int nct) {
     static_assert(!M::RT_ODD && NT >= 2 && NT <= 5, "direct pass: compile-time parities, at most 4 neighbours");
     constexpr int NI = M::NIN, NO = M::NOUT;
     const int lane = threadIdx.x & 63;
@@ -564,11 +567,11 @@ __global__ void __launch_bounds__(256) k_lastconv(Lines ln, M mul, cx<T>* S, con
     const int len = ln.len, nch = (len + 255) >> 8;
     const T* __restrict__ Bl = taps + (lic * nct + M::C0) * NT;   // wave-uniform
     const T ka = mul.ka_value();
-    const cx<T> zero = {T(0), T(0)};
     __shared__ cx<T> halo_s[4 * NI * 4];
     lds_ptr<cx<T>> halo = as_lds(halo_s) + l * NI * 4;
     for (int ch = 0; ch < nch; ++ch) {
         const int z0 = ch * 256 + 4 * lane;
+        // this lane's 4 points of every input field, all loads issued together
         cx<T> cur[NI][4];
 #pragma unroll
         for (int f = 0; f < NI; ++f) {
@@ -580,7 +583,10 @@ __global__ void __launch_bounds__(256) k_lastconv(Lines ln, M mul, cx<T>* S, con
                 cur[f][0] = p0.a; cur[f][1] = p0.b; cur[f][2] = p1.a; cur[f][3] = p1.b;
             } else {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) cur[f][q] = (ok && z0 + q < len) ? src[q] : zero;
+                for (int q = 0; q < 4; ++q) {
+                    cur[f][q] = cx<T>{T(0), T(0)};
+                    if (ok && z0 + q < len) cur[f][q] = src[q];
+                }
             }
         }
         const int e0 = z0 + 4;   // lane 63: the next chunk's first points
@@ -589,12 +595,14 @@ __global__ void __launch_bounds__(256) k_lastconv(Lines ln, M mul, cx<T>* S, con
 #pragma unroll
         for (int o = 0; o < NO; ++o)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) out[o][q] = zero;
+            for (int q = 0; q < 4; ++q) out[o][q] = cx<T>{T(0), T(0)};
 #pragma unroll
         for (int J = 0; J < NI; ++J) {
             // window of points z0 - 4 .. z0 + 7 of input J; lanes 0 and 63
             // load the points beyond the chunk ends themselves
-            cx<T> edge[4] = {zero, zero, zero, zero};
+            cx<T> edge[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) edge[q] = cx<T>{T(0), T(0)};
             if (edge_lane) {
                 const cx<T>* src = S + J * ln.fstride + lic * ln.pitch;
 #pragma unroll
@@ -605,14 +613,21 @@ __global__ void __launch_bounds__(256) k_lastconv(Lines ln, M mul, cx<T>* S, con
 #pragma unroll
                 for (int q = 0; q < 4; ++q) edge[q] = halo[J * 4 + q];
             }
+            const cx<T>(&cj)[4] = cur[J];
             cx<T> w[12];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                w[4 + q] = cur[J][q];
-                const cx<T> a = {dpp_mov<DPP_WAVE_SHR1>(cur[J][q].r), dpp_mov<DPP_WAVE_SHR1>(cur[J][q].i)};
-                const cx<T> b = {dpp_mov<DPP_WAVE_SHL1>(cur[J][q].r), dpp_mov<DPP_WAVE_SHL1>(cur[J][q].i)};
+                w[4 + q] = cj[q];
+                const cx<T> a = {dpp_mov<DPP_WAVE_SHR1>(cj[q].r), dpp_mov<DPP_WAVE_SHR1>(cj[q].i)};
+                const cx<T> b = {dpp_mov<DPP_WAVE_SHL1>(cj[q].r), dpp_mov<DPP_WAVE_SHL1>(cj[q].i)};
                 w[q] = lane == 0 ? edge[q] : a;
                 w[8 + q] = lane == 63 ? edge[q] : b;
+            }
+            // lane 63's input points are the next chunk's left neighbours (read
+            // by lane 0 above, in program order, before this write)
+            if (lane == 63) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) halo[J * 4 + q] = cj[q];
             }
             // neighbour sums at the 4 points, then every term that reads input J
 #pragma unroll
@@ -653,12 +668,6 @@ __global__ void __launch_bounds__(256) k_lastconv(Lines ln, M mul, cx<T>* S, con
                     });
                 });
             }
-        }
-        if (lane == 63) {
-#pragma unroll
-            for (int f = 0; f < NI; ++f)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) halo[f * 4 + q] = cur[f][q];
         }
         if (ok) {
 #pragma unroll
