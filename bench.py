@@ -9,12 +9,15 @@ the two-stage LPS force (dilatation convolution, then force convolutions;
 forward real FFTs, spectral multiply, inverse FFTs, assembly) and the
 velocity update.  value = body nodes x steps / time (Gnode/s).
 
-Also reported: the same step in FP64, pd_force alone in FP32 and FP64,
-per-pass HIP-event timings with algorithmic bytes (roofline of the
-dominant pass), the elastostatic CG time to a 1e-10 relative residual on
-the 128^3-node / 256^3-grid static cube (plain FP64 vs FP32-inner FP64
-refinement), and the FP64 direct-summation oracle timed on host cores on a
-bounded slab of the same workload.
+Also reported: the same step in FP64 and in FP32 with transforms along all
+three axes (the last axis otherwise uses the equivalent direct line
+correlation), pd_force alone, per-pass HIP-event timings over the timed
+steps with algorithmic bytes (roofline of the dominant pass; its HBM traffic
+from the committed rocprofv3 counter summary when the sources match), the
+elastostatic CG time to a 1e-10 relative residual on the 128^3-node /
+256^3-grid static cube (plain FP64 vs mixed FP32-operator / FP64 CG), and
+the FP64 direct-summation oracle timed on host cores on a bounded slab of
+the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -35,52 +38,96 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def profile_passes(plan, fn, reps):
-    import ctypes as C
+class ProfileSession:
+    """Per-launch HIP-event timing of a plan (pd_profile_enable / read)."""
 
-    from paper_2105_06055_amd import binding
+    def __init__(self, plan):
+        import ctypes as C
 
-    class PassTime(C.Structure):
-        _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double),
-                    ("bytes", C.c_double)]
+        from paper_2105_06055_amd import binding
 
-    L = binding.lib()
-    L.pd_profile_enable.argtypes = [C.c_void_p, C.c_int]
-    L.pd_profile_read.argtypes = [C.c_void_p, C.POINTER(PassTime), C.c_int, C.POINTER(C.c_int)]
-    assert L.pd_profile_enable(plan._h, 1) == 0
-    for _ in range(reps):
-        fn()
-    buf = (PassTime * 64)()
-    n = C.c_int(0)
-    assert L.pd_profile_read(plan._h, buf, 64, C.byref(n)) == 0
-    L.pd_profile_enable(plan._h, 0)
-    out = []
-    for i in range(min(n.value, 64)):
-        r = buf[i]
-        out.append({"name": r.name.decode(), "launches": int(r.launches), "total_ms": r.total_ms,
-                    "avg_ms": r.total_ms / max(1, r.launches),
-                    "bytes_per_launch": r.bytes / max(1, r.launches),
-                    "GBps": (r.bytes / 1e9) / (r.total_ms / 1e3) if r.total_ms > 0 else 0.0})
-    return out
+        class PassTime(C.Structure):
+            _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double),
+                        ("bytes", C.c_double)]
+
+        self.C, self.PassTime, self.plan = C, PassTime, plan
+        self.L = binding.lib()
+        self.L.pd_profile_enable.argtypes = [C.c_void_p, C.c_int]
+        self.L.pd_profile_read.argtypes = [C.c_void_p, C.POINTER(PassTime), C.c_int, C.POINTER(C.c_int)]
+        assert self.L.pd_profile_enable(plan._h, 1) == 0
+
+    def read(self):
+        C = self.C
+        buf = (self.PassTime * 64)()
+        n = C.c_int(0)
+        assert self.L.pd_profile_read(self.plan._h, buf, 64, C.byref(n)) == 0
+        self.L.pd_profile_enable(self.plan._h, 0)
+        out = []
+        for i in range(min(n.value, 64)):
+            r = buf[i]
+            out.append({"name": r.name.decode(), "launches": int(r.launches), "total_ms": r.total_ms,
+                        "avg_ms": r.total_ms / max(1, r.launches),
+                        "bytes_per_launch": r.bytes / max(1, r.launches),
+                        "GBps": (r.bytes / 1e9) / (r.total_ms / 1e3) if r.total_ms > 0 else 0.0})
+        return out
 
 
-def run_dynamics(wl, dtype, steps, warmup, with_profile):
+def kernel_source_hash():
+    """Hash of the HIP sources: HBM counter results taken for other sources
+    are not reported."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2105_06055_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(pass_name):
+    """HBM bytes per launch of a pass from the committed rocprofv3 counter
+    summary (FETCH_SIZE, WRITE_SIZE, scaled by the 1 GiB copy calibration),
+    or None if there is none for these sources."""
+    p = os.path.join(ROOT, "profiles", "hbm_traffic_lps256_fp32_step.json")
+    try:
+        with open(p) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    k = t.get("passes", {}).get(pass_name)
+    return None if k is None else float(k["hbm_bytes_per_launch"])
+
+
+def run_dynamics(wl, dtype, steps, warmup, with_profile, lastaxis="auto"):
+    """Warm up, then time exactly `steps` Verlet steps between two device
+    synchronisations; with_profile records HIP events around every launch
+    of those same steps (on the launch stream) for the per-pass timings."""
     import torch
 
     from paper_2105_06055_amd import binding
     plan = binding.Plan.from_workload(wl, dtype=dtype)
+    if lastaxis != "auto":
+        plan.set_lastaxis(lastaxis)
     dev = lambda a: torch.tensor(a, dtype=dtype, device="cuda").contiguous()
     st = {"u": dev(wl.u0), "v": dev(wl.v0), "F": torch.zeros((wl.dim,) + wl.body, dtype=dtype, device="cuda"),
           "step": 0}
     dt = wl.dt
     for _ in range(max(1, warmup)):
         plan.verlet(st, dt, 1)
+    prof = None
     torch.cuda.synchronize()
+    if with_profile:
+        prof = ProfileSession(plan)
     t0 = time.perf_counter()
     for _ in range(steps):
         plan.verlet(st, dt, 1)
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t0) / steps
+    if with_profile:
+        prof = prof.read()
     # pd_force alone
     L = torch.empty_like(st["u"])
     for _ in range(2):
@@ -91,9 +138,6 @@ def run_dynamics(wl, dtype, steps, warmup, with_profile):
         plan.force(st["u"], out=L)
     torch.cuda.synchronize()
     t_force = (time.perf_counter() - t0) / steps
-    prof = None
-    if with_profile:
-        prof = profile_passes(plan, lambda: plan.verlet(st, dt, 1), steps)
     finite = bool(torch.isfinite(st["u"]).all().item())
     info = plan.info
     plan.close()
@@ -158,7 +202,7 @@ def cpu_baseline(wl, budget_s=10.0):
     nz = int(min(nb[0], max(4, nz * budget_s / max(t, 1e-3))))
     t = step(nz)
     nodes = nz * nb[1] * nb[2]
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = orc.threads()
     return {"value": nodes / t / 1e9, "unit": "Gnode/s", "cores": threads, "kind": "oracle",
             "sample": f"one EC velocity-Verlet step (one LPS direct-sum force, FP64) on a {nz}x{nb[1]}x{nb[2]} "
                       f"z-slab of the 256^3 block-with-voids workload ({nodes} nodes, {t:.1f} s)"}
@@ -174,6 +218,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fft-variant", action="store_true",
+                    help="skip the step timing with FFTs along all three axes")
     ap.add_argument("--cg-size", type=int, default=128)
     ap.add_argument("--cg-fft", type=int, default=256)
     ap.add_argument("--copy-calib", action="store_true",
@@ -205,6 +251,11 @@ def main():
     if not args.no_fp64:
         r64 = run_dynamics(wl, torch.float64, args.steps, args.warmup, with_profile=True)
         log(f"[bench] fp64 step {r64['s_per_step'] * 1e3:.3f} ms, force {r64['s_per_force'] * 1e3:.3f} ms")
+    r32f = None
+    if not args.no_fft_variant:
+        # the same step with the transform form along the last axis as well
+        r32f = run_dynamics(wl, torch.float32, args.steps, args.warmup, with_profile=True, lastaxis="fft")
+        log(f"[bench] fp32 step, FFT on all three axes: {r32f['s_per_step'] * 1e3:.3f} ms")
     passes = r32["passes"]
     dom = max(passes, key=lambda p: p["total_ms"])
     achieved = dom["bytes_per_launch"] / 1e9 / (dom["avg_ms"] / 1e3)
@@ -237,8 +288,9 @@ def main():
                                f"voids) on a {args.fft}^3 FFT grid, delta=3dx, E=70GPa, nu=0.25",
                    "body_nodes": nodes, "fft_grid": args.fft ** 3, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom["name"],
-                     "kernel_avg_ms": dom["avg_ms"], "kernel_bytes": dom["bytes_per_launch"]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom["name"]),
+                     "kernel": dom["name"], "kernel_avg_ms": dom["avg_ms"],
+                     "kernel_bytes": dom["bytes_per_launch"]},
         "cpu_baseline": cpu,
         "detail": {
             "fp32": {"step_Gnode_s": nodes / r32["s_per_step"] / 1e9,
@@ -252,6 +304,10 @@ def main():
                 "step_Gnode_s": nodes / r64["s_per_step"] / 1e9, "ms_per_step": r64["s_per_step"] * 1e3,
                 "force_Gnode_s": nodes / r64["s_per_force"] / 1e9, "force_ms": r64["s_per_force"] * 1e3,
                 "finite": r64["finite"], "passes": r64["passes"]},
+            "fp32_fft_all_axes": None if r32f is None else {
+                "step_Gnode_s": nodes / r32f["s_per_step"] / 1e9, "ms_per_step": r32f["s_per_step"] * 1e3,
+                "force_Gnode_s": nodes / r32f["s_per_force"] / 1e9, "force_ms": r32f["s_per_force"] * 1e3,
+                "finite": r32f["finite"], "passes": r32f["passes"]},
             "cg_time_to_1e-10": cg,
         },
     }

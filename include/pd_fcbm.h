@@ -233,8 +233,10 @@ pd_status pd_damage_index(pd_plan plan, const uint8_t* lambda, void* d_out, void
  * recorded on the launch stream, together with the pass's algorithmic HBM
  * bytes (what the pass must read and write: its spectral slabs, kernel
  * partial spectra and per-node fields, each once).  pd_profile_read waits
- * for the recorded events, aggregates them by pass name (e.g. "lastmul_4x3":
- * last-axis pass with 4 input and 3 output fields), writes up to cap
+ * for the recorded events, aggregates them by pass name (e.g. "lastconv_4x3":
+ * last-axis pass with 4 input and 3 output fields by direct correlation,
+ * "lastmul_4x3" in the transform form; "xfwd_3", "ytf_512", "yti_512",
+ * "xinv_3": the x and y transform passes), writes up to cap
  * records, sets *n_out to the number of distinct passes and clears the
  * record list.  Enabling adds two event records per launch. */
 typedef struct {

@@ -55,6 +55,7 @@ def lib():
         up = C.POINTER(C.c_uint8)
         gp = C.POINTER(Geom)
         mp = C.POINTER(Model)
+        _lib.orc_threads.restype = C.c_int
         _lib.orc_stencil.argtypes = [gp, C.POINTER(C.c_int), C.c_int]
         _lib.orc_stencil.restype = C.c_int
         _lib.orc_bb_alpha.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double]
@@ -73,6 +74,11 @@ def lib():
         _lib.orc_verlet_adjoint.argtypes = [gp, C.c_double, C.c_double, up, dp, dp, dp, dp,
                                             C.c_double, C.c_int, dp, dp, dp]
     return _lib
+
+
+def threads() -> int:
+    """Host threads the oracle's parallel loops use."""
+    return int(lib().orc_threads())
 
 
 def _d(a):

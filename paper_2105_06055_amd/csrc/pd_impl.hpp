@@ -300,7 +300,7 @@ pd_status launch_lastmul(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, con
     }
     if (p->prof) {
         char nm[32];
-        std::snprintf(nm, sizeof nm, "lastmul_%dx%d", M::NIN, M::NOUT);
+        std::snprintf(nm, sizeof nm, "%s_%dx%d", path == 0 ? "lastconv" : "lastmul", M::NIN, M::NOUT);
         ps.done(nm, (double)(M::NIN + M::NOUT) * ln.nlines * ln.len * sizeof(cx<T>) +
                         (double)M::NC * ntap * ln.nlines * sizeof(T));
     }
