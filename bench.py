@@ -27,6 +27,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -178,6 +180,69 @@ def run_cg(nb, nfft, maxit):
     return res
 
 
+def run_force_rate(wl, dtype, reps, warmup):
+    """pd_force alone: mean time over `reps` calls after `warmup`."""
+    import torch
+
+    from paper_2105_06055_amd import binding
+    plan = binding.Plan.from_workload(wl, dtype=dtype)
+    u = torch.tensor(np.random.default_rng(7).normal(0.0, 1e-6, size=(wl.dim,) + wl.body), dtype=dtype,
+                     device="cuda")
+    L = torch.empty_like(u)
+    for _ in range(max(1, warmup)):
+        plan.force(u, out=L)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.force(u, out=L)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    plan.close()
+    del u, L
+    torch.cuda.empty_cache()
+    return t
+
+
+def run_energy(wl, dtype, nsteps):
+    """nsteps EC Verlet steps from the workload's initial state with FP64
+    energy accounting every step; returns the energy histories."""
+    import torch
+
+    from paper_2105_06055_amd import binding
+    plan = binding.Plan.from_workload(wl, dtype=dtype)
+    dev = lambda a: torch.tensor(a, dtype=dtype, device="cuda").contiguous()
+    st = {"u": dev(wl.u0), "v": dev(wl.v0), "F": torch.zeros((wl.dim,) + wl.body, dtype=dtype, device="cuda"),
+          "step": 0}
+    t0 = time.perf_counter()
+    en = plan.verlet(st, wl.dt, nsteps, energy=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    plan.close()
+    del st
+    torch.cuda.empty_cache()
+    return en, t
+
+
+def energy_report(wl, nsteps):
+    """C5: energy drift of FP32 and FP64 runs of nsteps steps (E = KE + PE +
+    EXT, and the Verlet shadow energy), and the FP32 run against FP64."""
+    import torch
+    out = {"steps": nsteps}
+    hist = {}
+    for name, dt_ in (("fp32", torch.float32), ("fp64", torch.float64)):
+        en, t = run_energy(wl, dt_, nsteps)
+        E = en[:, 0] + en[:, 1] + en[:, 2]
+        hist[name] = (E, en[:, 3])
+        out[name] = {"E0_J": float(E[0]), "E_end_J": float(E[-1]),
+                     "drift_rel": float((E[-1] - E[0]) / E[0]),
+                     "max_abs_drift_rel": float(np.max(np.abs(E - E[0])) / abs(E[0])),
+                     "shadow_drift_rel": float((en[-1, 3] - en[0, 3]) / en[0, 3]),
+                     "seconds": t}
+    E32, E64 = hist["fp32"][0], hist["fp64"][0]
+    out["fp32_vs_fp64_max_rel"] = float(np.max(np.abs(E32 - E64)) / abs(E64[0]))
+    return out
+
+
 def cpu_baseline(wl, budget_s=10.0):
     """FP64 direct-summation oracle, one EC Verlet step (one LPS force) on a
     z-slab of the same workload, slab sized for ~budget_s seconds."""
@@ -220,6 +285,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fft-variant", action="store_true",
                     help="skip the step timing with FFTs along all three axes")
+    ap.add_argument("--no-energy", action="store_true", help="skip the 1000-step energy-drift runs")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 128^3/256^3 force rates")
+    ap.add_argument("--energy-steps", type=int, default=1000)
     ap.add_argument("--cg-size", type=int, default=128)
     ap.add_argument("--cg-fft", type=int, default=256)
     ap.add_argument("--copy-calib", action="store_true",
@@ -261,6 +329,22 @@ def main():
     achieved = dom["bytes_per_launch"] / 1e9 / (dom["avg_ms"] / 1e3)
     step_bytes = sum(p["bytes_per_launch"] * p["launches"] for p in passes) / args.steps
     step_kernel_ms = sum(p["total_ms"] for p in passes) / args.steps
+    c2 = None
+    if not args.no_c2:
+        w2 = workloads.cube_void_static()
+        t32 = run_force_rate(w2, torch.float32, args.steps, args.warmup)
+        t64 = run_force_rate(w2, torch.float64, args.steps, args.warmup)
+        c2 = {"workload": "LPS cube 128^3 nodes with spherical void, 256^3 FFT grid (pd_force alone)",
+              "fp32_force_ms": t32 * 1e3, "fp32_Gnode_s": w2.nodes / t32 / 1e9,
+              "fp32_fft_grid_Gpoint_s": 256 ** 3 / t32 / 1e9,
+              "fp64_force_ms": t64 * 1e3, "fp64_Gnode_s": w2.nodes / t64 / 1e9,
+              "fp64_fft_grid_Gpoint_s": 256 ** 3 / t64 / 1e9}
+        log(f"[bench] c2 {json.dumps(c2)}")
+    energy = None
+    if not args.no_energy:
+        log(f"[bench] energy drift over {args.energy_steps} steps (FP32 and FP64)")
+        energy = energy_report(wl, args.energy_steps)
+        log(f"[bench] energy {json.dumps(energy)}")
     cg = None
     if not args.no_cg:
         log("[bench] CG time-to-1e-10 (static cube)")
@@ -309,6 +393,8 @@ def main():
                 "force_Gnode_s": nodes / r32f["s_per_force"] / 1e9, "force_ms": r32f["s_per_force"] * 1e3,
                 "finite": r32f["finite"], "passes": r32f["passes"]},
             "cg_time_to_1e-10": cg,
+            "c2_force": c2,
+            "energy_drift": energy,
         },
     }
     print(json.dumps(out), flush=True)
