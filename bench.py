@@ -157,23 +157,26 @@ def run_cg(nb, nfft, maxit):
     plan = binding.Plan.from_workload(wl, dtype=torch.float64, mixed=True)
     b = torch.tensor(wl.b, dtype=torch.float64, device="cuda").contiguous()
     res = {}
-    for mixed in (False, True):
-        # one untimed solve with a loose tolerance warms caches and code paths
-        plan.static_solve(b, rtol=1e-2, maxit=maxit, mixed=mixed, check=False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        u, info = plan.static_solve(b, rtol=1e-10, maxit=maxit, mixed=mixed, check=False)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        key = "mixed_fp32_fp64" if mixed else "fp64"
-        res[key] = {"seconds": dt, "rel_res": info["rel_res"], "status": info["status"],
-                    "iters_fp64": info["iters_fp64"], "iters_fp32": info["iters_fp32"],
-                    "applies_fp64": info["applies_fp64"], "applies_fp32": info["applies_fp32"]}
-        if mixed:
-            res["solution_rel_diff_vs_fp64"] = float(torch.linalg.vector_norm(u - u_plain) /
-                                                     torch.linalg.vector_norm(u_plain))
-        else:
-            u_plain = u
+    u_plain = None
+    for precond in (False, True):
+        for mixed in (False, True):
+            # one untimed solve with a loose tolerance warms caches and code paths
+            plan.static_solve(b, rtol=1e-2, maxit=maxit, mixed=mixed, precond=precond, check=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, info = plan.static_solve(b, rtol=1e-10, maxit=maxit, mixed=mixed, precond=precond, check=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            key = ("mixed_fp32_fp64" if mixed else "fp64") + ("_precond" if precond else "")
+            res[key] = {"seconds": dt, "rel_res": info["rel_res"], "status": info["status"],
+                        "iters_fp64": info["iters_fp64"], "iters_fp32": info["iters_fp32"],
+                        "applies_fp64": info["applies_fp64"], "applies_fp32": info["applies_fp32"],
+                        "precond_applies": info["precond_applies"]}
+            if u_plain is None:
+                u_plain = u
+            else:
+                res[key]["solution_rel_diff_vs_fp64_cg"] = float(torch.linalg.vector_norm(u - u_plain) /
+                                                                 torch.linalg.vector_norm(u_plain))
     plan.close()
     torch.cuda.empty_cache()
     res["workload"] = f"LPS cube {nb}^3 nodes with spherical void, {nfft}^3 FFT grid, clamped 3-delta layer"

@@ -198,28 +198,42 @@ pd_status pd_verlet_adjoint(pd_plan plan, const void* u_n, const void* u_np1, co
                             void* u_bar, void* v_bar, void* s_bar, double dt, void* stream);
 
 typedef struct {
-    int iters_fp64;        /* FP64 CG iterations (plain solve) or FP64 residual
+    int iters_fp64;        /* FP64 CG iterations (FP64 solves) or FP64 residual
                               replacements (mixed) */
     int iters_fp32;        /* CG iterations with the FP32 operator (mixed) */
     int applies_fp64;      /* FP64 operator applications */
     int applies_fp32;      /* FP32 operator applications */
     double rel_res;        /* final |chi_O (L(u) + b)|_2 / |rhs|_2 in FP64 */
+    int precond_applies;   /* preconditioner applications (PD_SOLVE_PRECOND) */
 } pd_solve_info;
+
+/* pd_static_solve options (bit flags) */
+#define PD_SOLVE_MIXED 1     /* FP32 operator, FP64 vectors / inner products /
+                                residual replacement (plan built with PD_PLAN_MIXED) */
+#define PD_SOLVE_PRECOND 2   /* spectral preconditioner */
 
 /* Embedded-constraint statics (Eq. 85-89) by conjugate gradients on
  * A = -chi_O L chi_O (symmetric positive definite on the unknowns), to the
  * relative residual rtol.  b, w, u_inout are FP64 DEVICE buffers
  * [dim][body] regardless of the plan dtype; u_inout holds the initial guess
  * on entry and the solution (u = w on constrained components) on exit.
- * mixed = 0: plain FP64 CG (PD_F64 plan).  mixed = 1 (PD_F64 plan created
- * with PD_PLAN_MIXED): CG iterations that apply the operator in FP32 to an
- * FP32 copy of the search direction, with the iterate, residual and
- * direction updated and every inner product accumulated in FP64, and the
- * residual replaced by the FP64 residual chi_O (L(u) + b) each time it has
- * dropped tenfold and at convergence (refinement against the FP64 operator).
- * PD_ENOTCONV when maxit CG iterations did not reach rtol. */
+ * options = 0: plain FP64 CG (PD_F64 plan).
+ * PD_SOLVE_MIXED (PD_F64 plan created with PD_PLAN_MIXED): CG iterations that
+ *   apply the operator in FP32 to an FP32 copy of the search direction, with
+ *   the iterate, residual and direction updated and every inner product
+ *   accumulated in FP64, and the residual replaced by the FP64 residual
+ *   chi_O (L(u) + b) each time it has dropped tenfold and at convergence
+ *   (refinement against the FP64 operator).
+ * PD_SOLVE_PRECOND: preconditioned CG with z = chi_O M^-1 chi_O r, M the
+ *   bond-based operator of the same kernel on the full periodic box without
+ *   masks (its symbol Ĉ(0) - Ĉ(k), shifted by a quarter of its mean diagonal
+ *   at the first nonzero wavenumber along x so that k = 0 is invertible),
+ *   applied by transforms; in FP32 when combined with PD_SOLVE_MIXED.  Not a
+ *   method of the paper: an option for the solve only.
+ * PD_ENOTCONV when maxit CG iterations did not reach rtol; PD_EINVAL for
+ * unknown option bits. */
 pd_status pd_static_solve(pd_plan plan, const void* b, const void* w, void* u_inout, double rtol,
-                          int maxit, int mixed, pd_solve_info* info, void* stream);
+                          int maxit, int options, pd_solve_info* info, void* stream);
 
 /* Damage index (Eq. 12 as Eq. 49/65): d = 1 - chi_B lambda cnt / beta with
  * cnt the number of intact partners within the horizon including the node

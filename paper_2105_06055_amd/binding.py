@@ -62,7 +62,10 @@ class State(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters_fp64", C.c_int), ("iters_fp32", C.c_int), ("applies_fp64", C.c_int),
-                ("applies_fp32", C.c_int), ("rel_res", C.c_double)]
+                ("applies_fp32", C.c_int), ("rel_res", C.c_double), ("precond_applies", C.c_int)]
+
+
+SOLVE_MIXED, SOLVE_PRECOND = 1, 2
 
 
 EXPORTS = ["pd_plan_create", "pd_plan_destroy", "pd_plan_query", "pd_force", "pd_force_adjoint",
@@ -249,13 +252,15 @@ class Plan:
                                        _ptr(self._vec(v_bar, "v_bar")), _ptr(self._sca(s_bar, "s_bar")),
                                        float(dt), _stream()), "pd_verlet_adjoint")
 
-    def static_solve(self, b, w=None, u0=None, rtol=1e-10, maxit=100000, mixed=False, check=True):
+    def static_solve(self, b, w=None, u0=None, rtol=1e-10, maxit=100000, mixed=False, precond=False,
+                     check=True):
         b = self._vec(b, "b", torch.float64)
         w = self._vec(w, "w", torch.float64)
         u = torch.zeros_like(b) if u0 is None else self._vec(u0, "u0", torch.float64).clone()
         inf = SolveInfo()
+        opts = (SOLVE_MIXED if mixed else 0) | (SOLVE_PRECOND if precond else 0)
         s = lib().pd_static_solve(self._h, _ptr(b), _ptr(w), _ptr(u), float(rtol), int(maxit),
-                                  1 if mixed else 0, C.byref(inf), _stream())
+                                  opts, C.byref(inf), _stream())
         if check:
             _check(s, "pd_static_solve")
         info = {f: getattr(inf, f) for f, _ in SolveInfo._fields_}

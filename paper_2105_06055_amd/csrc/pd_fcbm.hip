@@ -30,7 +30,8 @@ namespace pdi {
     extern template pd_status cg_run<T, T>(pd_plan, T*, T*, T*, T*, T*, double, double, int, int*, int*, double*, \
                                            hipStream_t);                                                          \
     extern template pd_status lin_apply<T, 3>(pd_plan, const T*, T*, const T*, hipStream_t);                      \
-    extern template pd_status lin_apply<T, 2>(pd_plan, const T*, T*, const T*, hipStream_t);
+    extern template pd_status lin_apply<T, 2>(pd_plan, const T*, T*, const T*, hipStream_t);                      \
+    extern template pd_status precond_apply<T, double, T>(pd_plan, const double*, T*, hipStream_t);
 PD_EXTERN(float)
 PD_EXTERN(double)
 #undef PD_EXTERN
@@ -101,10 +102,10 @@ pd_status pd_verlet_adjoint(pd_plan p, const void* u_n, const void* u_np1, const
                                        (double*)v_bar, (double*)s_bar, dt, S_(stream));
 }
 
-pd_status pd_static_solve(pd_plan p, const void* b, const void* w, void* u_inout, double rtol, int maxit, int mixed,
+pd_status pd_static_solve(pd_plan p, const void* b, const void* w, void* u_inout, double rtol, int maxit, int options,
                           pd_solve_info* info, void* stream) {
     if (!p) return PD_EINVAL;
-    return static_solve_impl(p, (const double*)b, (const double*)w, (double*)u_inout, rtol, maxit, mixed, info,
+    return static_solve_impl(p, (const double*)b, (const double*)w, (double*)u_inout, rtol, maxit, options, info,
                              S_(stream));
 }
 

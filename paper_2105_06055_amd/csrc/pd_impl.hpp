@@ -255,18 +255,28 @@ pd_status launch_lastconv(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, co
     return PD_OK;
 }
 
+// Multipliers that are not trigonometric polynomials of the taps along the
+// last axis (the preconditioner) declare NONLOCAL and take a transform form.
+template <class M, class = void>
+struct is_nonlocal : std::false_type {};
+template <class M>
+struct is_nonlocal<M, std::void_t<decltype(M::NONLOCAL)>> : std::integral_constant<bool, M::NONLOCAL> {};
+
 template <class T, class M>
 pd_status launch_lastmul(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, const T* taps, const T* taps_d,
                          int ntap, int nct, uint32_t oddmask, hipStream_t st) {
     const int Tn = ln.N / 8;
     ProfScope ps(p, st);
+    constexpr bool direct_ok = !M::RT_ODD && !is_nonlocal<M>::value;
     int path = 2;   // 0 direct, 1 specialised FFT, 2 generic FFT
-    if constexpr (!M::RT_ODD) {
+    if constexpr (direct_ok) {
         if (p->lastaxis == PD_LASTAXIS_AUTO && taps_d && ntap >= 2 && ntap <= 5) path = 0;
-        else if (p->lastaxis != PD_LASTAXIS_FFT_GENERIC && ln.N == 512 && ntap == 4) path = 1;
+    }
+    if constexpr (!M::RT_ODD) {
+        if (path != 0 && p->lastaxis != PD_LASTAXIS_FFT_GENERIC && ln.N == 512 && ntap == 4) path = 1;
     }
     if (path == 0) {
-        if constexpr (!M::RT_ODD) {
+        if constexpr (direct_ok) {
             pd_status s = PD_OK;
             switch (ntap) {
                 case 2: s = launch_lastconv<T, M, 2>(p, ln, mul, S, taps_d, nct, st); break;
@@ -558,6 +568,25 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
     }
     p->ntap = mlast + 1;
     if (p->ntap > 9) return PD_EUNSUPPORTED;
+    {
+        // preconditioner constants: Ĉ(0)_ii = sum_o C_ii(o) dV; the shift is a
+        // quarter of the mean diagonal of the symbol at the first nonzero
+        // wavenumber along x, sum_o C_ii(o) (1 - cos(2 pi o_x / n1)) dV
+        const double nf = (double)p->nfft;
+        double sh = 0.0;
+        for (int i = 0; i < 3; ++i) p->pre_k0[i] = 0.0;
+        for (int s = 0; s < ns; ++s) {
+            const double cx1 = 1.0 - std::cos(2.0 * kPi * S[s].o[0] / p->geo.n1);
+            for (int i = 0; i < D; ++i) {
+                const double c = kv[(size_t)s * ncs + symi(D, i, i)];
+                p->pre_k0[i] += c;
+                sh += c * cx1;
+            }
+        }
+        p->pre_shift = 0.25 * sh / D / nf;
+        for (int i = 0; i < 3; ++i) p->pre_k0[i] /= nf;
+        p->pre_s0 = p->pre_k0[0] > 0 ? p->pre_k0[0] : 1.0;
+    }
 
     HIP_TRY(hipMalloc(&p->offs_dev, sizeof(int) * offs.size()));
     HIP_TRY(hipMalloc(&p->kval_dev, sizeof(double) * kv.size()));
@@ -957,6 +986,32 @@ static __global__ void k_cgm_dir(double* __restrict__ p, float* __restrict__ p32
     }
 }
 
+// Preconditioned CG directions: p = z + b p
+template <class T>
+__global__ void k_pcg_dir(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ coef, long n) {
+    const double b = coef[0];
+    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+        p[k] = T(double(z[k]) + b * double(p[k]));
+}
+// mixed, first direction: p = z32 (FP64);  p32 = z32
+static __global__ void k_pcgm_start(double* __restrict__ p, float* __restrict__ p32, const float* __restrict__ z32,
+                                    long n) {
+    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        p[k] = double(z32[k]);
+        p32[k] = z32[k];
+    }
+}
+// mixed: p = z32 + b p (FP64);  p32 = (float) p
+static __global__ void k_pcgm_dir(double* __restrict__ p, float* __restrict__ p32, const float* __restrict__ z32,
+                                  const double* __restrict__ coef, long n) {
+    const double b = coef[0];
+    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        const double v = double(z32[k]) + b * p[k];
+        p[k] = v;
+        p32[k] = float(v);
+    }
+}
+
 // Verlet adjoint helpers
 template <class T>
 __global__ void k_mask_copy(T* __restrict__ a, const T* __restrict__ vb, const uint8_t* __restrict__ chiO, long n) {
@@ -1043,6 +1098,30 @@ pd_status lin_apply(pd_plan p, const T* x, T* out, const T* b, hipStream_t st) {
 }
 
 // --------------------------------------------------------------- Verlet
+// Spectral preconditioner z = chi_O M^-1 chi_O r (M: periodic unmasked
+// bond-based symbol, see MulPre); p->red[0] = r . z.  T is the chain
+// precision, r is read as TR and z stored as TZ.
+template <class T, class TR, class TZ>
+pd_status precond_apply(pd_plan p, const TR* r, TZ* z, hipStream_t st) {
+    auto go = [&](auto Dc) -> pd_status {
+        constexpr int DD = decltype(Dc)::value;
+        GenMasked<T, DD, TR> gg{};
+        gg.c = ctx<T>(p);
+        gg.r = r;
+        MulPre<T, DD> mm{};
+        const double s0 = p->pre_s0;
+        for (int i = 0; i < 3; ++i) mm.k0n[i] = T((p->pre_k0[i] + p->pre_shift) / s0);
+        mm.kscale = T(1.0 / s0);
+        mm.outscale = T(1.0 / ((double)p->nfft * (double)p->nfft * s0));
+        FinPre<T, DD, TR, TZ> ff{};
+        ff.c = ctx<T>(p);
+        ff.r = r;
+        ff.z = z;
+        return run_chain<T>(p, gg, mm, ff, st);
+    };
+    return p->dim == 2 ? go(std::integral_constant<int, 2>{}) : go(std::integral_constant<int, 3>{});
+}
+
 template <class T, bool ENRED>
 pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, hipStream_t st) {
     const int D = p->dim;
@@ -1253,18 +1332,20 @@ pd_status cg_run(pd_plan p, TX* x_unused, T* xT, T* r, T* pp, T* Ap, double rr0,
     return PD_OK;
 }
 
-inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, double* u, double rtol, int maxit, int mixed,
-                            pd_solve_info* info, hipStream_t st) {
+inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, double* u, double rtol, int maxit,
+                                   int options, pd_solve_info* info, hipStream_t st) {
+    const bool mixed = (options & PD_SOLVE_MIXED) != 0, pre = (options & PD_SOLVE_PRECOND) != 0;
+    if (options & ~(PD_SOLVE_MIXED | PD_SOLVE_PRECOND)) return PD_EINVAL;
     if (p->dtype != PD_F64) return PD_EINVAL;
     if (p->kern.weight != PD_WEIGHT_NONE) return PD_EUNSUPPORTED;
     if (!b || !u || !(rtol > 0) || maxit <= 0) return PD_EINVAL;
     if (mixed && !p->sub32) return PD_EINVAL;
     const long n = p->nb * p->dim;
     pd_solve_info inf{};
-    double *r = nullptr, *pp = nullptr, *Ap = nullptr, *t = nullptr;
-    float *p32 = nullptr, *Ap32 = nullptr;
+    double *r = nullptr, *pp = nullptr, *Ap = nullptr, *t = nullptr, *z = nullptr;
+    float *p32 = nullptr, *Ap32 = nullptr, *z32 = nullptr;
     auto cleanup = [&]() {
-        void* bufs[] = {r, pp, Ap, t, p32, Ap32};
+        void* bufs[] = {r, pp, Ap, t, z, p32, Ap32, z32};
         for (void* q : bufs)
             if (q) (void)hipFree(q);
     };
@@ -1281,7 +1362,7 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
     SOLVE_TRY(pdh::check(hipGetLastError()));
     // |rhs|^2 = |chi_O (L((1 - chi_O) w) + b)|^2
     SOLVE_TRY((lin_apply<double, 3>(p, t, r, b, st)));
-    double v[1];
+    double v[3];
     SOLVE_TRY(fetch_red(p, 1, st, v));
     inf.applies_fp64 += 1;
     double bn2 = v[0] > 0 ? v[0] : 1.0;
@@ -1292,7 +1373,8 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
     inf.applies_fp64 += 1;
     double rr = v[0];
     pd_status result = PD_OK;
-    if (!mixed) {
+    const unsigned nb = ew_blocks(n);
+    if (!mixed && !pre) {
         SOLVE_TRY(pdh::check(hipMalloc(&pp, sizeof(double) * n)));
         SOLVE_TRY(pdh::check(hipMalloc(&Ap, sizeof(double) * n)));
         int its = 0, app = 0;
@@ -1300,36 +1382,92 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
         SOLVE_TRY((cg_run<double, double>(p, u, u, r, pp, Ap, rr, stop2, maxit, &its, &app, &rr_end, st)));
         inf.iters_fp64 = its;
         inf.applies_fp64 += app;
+    } else if (!mixed) {
+        // preconditioned CG in FP64
+        SOLVE_TRY(pdh::check(hipMalloc(&pp, sizeof(double) * n)));
+        SOLVE_TRY(pdh::check(hipMalloc(&Ap, sizeof(double) * n)));
+        SOLVE_TRY(pdh::check(hipMalloc(&z, sizeof(double) * n)));
+        double* dev = p->red;   // [0] pAp or rz, [1] alpha, [2] rr, [3] beta, [4] rz (device copies)
+        int it = 0;
+        if (rr > stop2) {
+            SOLVE_TRY((precond_apply<double, double, double>(p, r, z, st)));
+            SOLVE_TRY(fetch_red(p, 1, st, v));
+            inf.precond_applies += 1;
+            double rz = v[0];
+            SOLVE_TRY(pdh::check(hipMemcpyAsync(pp, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st)));
+            while (it < maxit) {
+                SOLVE_TRY((lin_apply<double, 2>(p, pp, Ap, nullptr, st)));   // red[0] = p.Ap
+                inf.applies_fp64 += 1;
+                p->red_host[4] = rz;
+                SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + 4, p->red_host + 4, sizeof(double), hipMemcpyHostToDevice, st)));
+                hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, st, dev + 4, dev + 0, dev + 1);
+                hipLaunchKernelGGL((k_cg_update<double, double>), dim3(nb), dim3(EW_THREADS), 0, st, u, (const double*)pp,
+                                   r, (const double*)Ap, (const double*)(dev + 1), n, p->partials);
+                SOLVE_TRY(pdh::check(hipGetLastError()));
+                SOLVE_TRY(ew_finish<1>(p, nb, dev + 2, st));
+                SOLVE_TRY(fetch_red(p, 3, st, v));
+                ++it;
+                rr = v[2];
+                if (!std::isfinite(rr)) return fail(PD_ENUMERIC);
+                if (rr <= stop2) break;
+                SOLVE_TRY((precond_apply<double, double, double>(p, r, z, st)));   // red[0] = r.z
+                inf.precond_applies += 1;
+                SOLVE_TRY(fetch_red(p, 1, st, v));
+                const double rz_new = v[0];
+                p->red_host[3] = rz_new / rz;
+                SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + 3, p->red_host + 3, sizeof(double), hipMemcpyHostToDevice, st)));
+                hipLaunchKernelGGL(k_pcg_dir<double>, dim3(nb), dim3(EW_THREADS), 0, st, pp, (const double*)z,
+                                   (const double*)(dev + 3), n);
+                SOLVE_TRY(pdh::check(hipGetLastError()));
+                rz = rz_new;
+            }
+        }
+        inf.iters_fp64 = it;
     } else {
-        // CG with the operator applied in FP32 (sub32 plan) and every vector
-        // update and inner product in FP64; the recursively updated residual
-        // is replaced by the FP64 residual chi_O (L x + b) whenever it has
-        // dropped by a factor 10 since the last replacement and at the end
-        // (residual replacement keeps the FP32 operator's errors from
-        // accumulating in r), so the returned iterate meets rtol in FP64.
+        // CG with the operator (and the preconditioner, if any) applied in
+        // FP32 (sub32 plan) to FP32 copies, with the iterate, residual and
+        // direction updated and every inner product accumulated in FP64; the
+        // recursively updated residual is replaced by the FP64 residual
+        // chi_O (L x + b) whenever it has dropped by a factor 10 since the
+        // last replacement and at the end (residual replacement keeps the
+        // FP32 operator's errors from accumulating in r), so the returned
+        // iterate meets rtol in FP64.
         pd_plan q = p->sub32;
         SOLVE_TRY(pdh::check(hipMalloc(&pp, sizeof(double) * n)));
         SOLVE_TRY(pdh::check(hipMalloc(&p32, sizeof(float) * n)));
         SOLVE_TRY(pdh::check(hipMalloc(&Ap32, sizeof(float) * n)));
-        const unsigned nb = ew_blocks(n);
-        double* dev = q->red;   // [0] pAp, [1] alpha, [3] beta, [4] rr (device copies)
-        hipLaunchKernelGGL(k_cgm_start, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const double*)r, n);
+        if (pre) SOLVE_TRY(pdh::check(hipMalloc(&z32, sizeof(float) * n)));
+        double* dev = q->red;   // [0] pAp / r.z, [1] alpha, [2] rr, [3] beta, [4] rho (device copies)
+        // rho = r.z (preconditioned) or r.r; the direction starts from z or r
+        auto precond = [&](double* rz) -> pd_status {
+            PD_TRY((precond_apply<float, double, float>(q, r, z32, st)));
+            inf.precond_applies += 1;
+            PD_TRY(fetch_red(q, 1, st, v));
+            *rz = v[0];
+            return PD_OK;
+        };
+        double rho = rr;
+        if (pre) {
+            if (rr > stop2) SOLVE_TRY(precond(&rho));
+            hipLaunchKernelGGL(k_pcgm_start, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const float*)z32, n);
+        } else {
+            hipLaunchKernelGGL(k_cgm_start, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const double*)r, n);
+        }
         SOLVE_TRY(pdh::check(hipGetLastError()));
         double rr_rep = rr;   // |r|^2 at the last replacement
         int it = 0;
         while (rr > stop2 && it < maxit) {
             SOLVE_TRY((lin_apply<float, 2>(q, p32, Ap32, nullptr, st)));   // q->red[0] = p32 . Ap32
             inf.applies_fp32 += 1;
-            q->red_host[4] = rr;
+            q->red_host[4] = rho;
             SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + 4, q->red_host + 4, sizeof(double), hipMemcpyHostToDevice, st)));
             hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, st, dev + 4, dev + 0, dev + 1);
             hipLaunchKernelGGL(k_cgm_update, dim3(nb), dim3(EW_THREADS), 0, st, u, (const float*)p32, r,
                                (const float*)Ap32, (const double*)(dev + 1), n, q->partials);
             SOLVE_TRY(pdh::check(hipGetLastError()));
             SOLVE_TRY(ew_finish<1>(q, nb, dev + 2, st));
-            double w3[3];
-            SOLVE_TRY(fetch_red(q, 3, st, w3));
-            double rr_new = w3[2];
+            SOLVE_TRY(fetch_red(q, 3, st, v));
+            double rr_new = v[2];
             ++it;
             inf.iters_fp32 += 1;
             if (!std::isfinite(rr_new)) return fail(PD_ENUMERIC);
@@ -1344,12 +1482,19 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
                 rr_rep = rr_new;
                 if (rr_new <= stop2) { rr = rr_new; break; }
             }
-            q->red_host[3] = rr_new / rr;
-            SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + 3, q->red_host + 3, sizeof(double), hipMemcpyHostToDevice, st)));
-            hipLaunchKernelGGL(k_cgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const double*)r,
-                               (const double*)(dev + 3), n);
-            SOLVE_TRY(pdh::check(hipGetLastError()));
             rr = rr_new;
+            double rho_new = rr_new;
+            if (pre) SOLVE_TRY(precond(&rho_new));
+            q->red_host[3] = rho_new / rho;
+            SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + 3, q->red_host + 3, sizeof(double), hipMemcpyHostToDevice, st)));
+            if (pre)
+                hipLaunchKernelGGL(k_pcgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const float*)z32,
+                                   (const double*)(dev + 3), n);
+            else
+                hipLaunchKernelGGL(k_cgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const double*)r,
+                                   (const double*)(dev + 3), n);
+            SOLVE_TRY(pdh::check(hipGetLastError()));
+            rho = rho_new;
         }
     }
     // true FP64 residual of the returned iterate

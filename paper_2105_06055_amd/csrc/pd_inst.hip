@@ -23,6 +23,7 @@ template pd_status cg_run<PD_INST_T, PD_INST_T>(pd_plan, PD_INST_T*, PD_INST_T*,
                                                 double, double, int, int*, int*, double*, hipStream_t);
 template pd_status lin_apply<PD_INST_T, 3>(pd_plan, const PD_INST_T*, PD_INST_T*, const PD_INST_T*, hipStream_t);
 template pd_status lin_apply<PD_INST_T, 2>(pd_plan, const PD_INST_T*, PD_INST_T*, const PD_INST_T*, hipStream_t);
+template pd_status precond_apply<PD_INST_T, double, PD_INST_T>(pd_plan, const double*, PD_INST_T*, hipStream_t);
 #else
 template pd_status plan_alloc<PD_INST_T>(pd_plan, hipStream_t, const uint8_t*, const uint8_t*);
 template pd_status build_device_tables<PD_INST_T>(pd_plan, const std::vector<Bond>&, hipStream_t);

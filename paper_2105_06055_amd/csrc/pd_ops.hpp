@@ -500,6 +500,75 @@ struct MulAdj {
     }
 };
 
+// Spectral preconditioner of the static solve: the inverse of the periodic,
+// unmasked bond-based symbol (Ĉ(0) - M[C](k), the operator -L of the same
+// kernel on the full periodic box, shifted by a multiple of the identity so
+// that k = 0 is invertible), applied per wavenumber.  It is nonlocal along
+// the last axis, so only the transform form of the last-axis pass applies.
+// In tap units (Ĉ/Nfft), normalised by s0: out = (S')^-1 in * outscale with
+// S' = k0n - kscale M[C](k), k0n = (Ĉ(0) + shift)/ (Nfft s0).
+template <class T, int D>
+struct MulPre {
+    static constexpr int NIN = D, NOUT = D, C0 = 0, NC = nsym(D);
+    static constexpr bool RT_ODD = false, NONLOCAL = true;
+    static constexpr uint32_t ODD = (D == 2) ? (1u << 1) : ((1u << 2) | (1u << 4));
+    T k0n[3];
+    T kscale, outscale;
+    __device__ __forceinline__ T ka_value() const { return T(0); }
+    __host__ __device__ static constexpr DTerm dterm(int, int) { return DTerm{0, 0, 0, false}; }
+    template <int O>
+    __host__ __device__ static constexpr uint32_t need() { return (1u << nsym(D)) - 1u; }
+    template <int O>
+    __device__ __forceinline__ cx<T> one(const T* K, const cx<T>* in) const {
+        // S'_ij = k0n_i [i == j] - kscale * (i == j ? K : -K)_ij  (symmetric)
+        auto Sij = [&](int i, int j) {
+            const T m = (i == j) ? K[symi(D, i, j)] : -K[symi(D, i, j)];
+            return (i == j ? k0n[i] : T(0)) - kscale * m;
+        };
+        if constexpr (D == 2) {
+            const T a = Sij(0, 0), b = Sij(1, 1), d = Sij(0, 1);
+            const T inv = outscale / (a * b - d * d);
+            const T r0 = (O == 0) ? b : -d, r1 = (O == 0) ? -d : a;
+            return cscale(kmul(r0, in[0]) + kmul(r1, in[1]), inv);
+        } else {
+            const T a = Sij(0, 0), b = Sij(1, 1), c = Sij(2, 2);
+            const T d = Sij(0, 1), e = Sij(0, 2), f = Sij(1, 2);
+            // cofactors of the symmetric matrix [[a d e] [d b f] [e f c]]
+            const T A00 = b * c - f * f, A01 = e * f - d * c, A02 = d * f - e * b;
+            const T A11 = a * c - e * e, A12 = d * e - a * f, A22 = a * b - d * d;
+            const T inv = outscale / (a * A00 + d * A01 + e * A02);
+            T r0, r1, r2;
+            if constexpr (O == 0) { r0 = A00; r1 = A01; r2 = A02; }
+            else if constexpr (O == 1) { r0 = A01; r1 = A11; r2 = A12; }
+            else { r0 = A02; r1 = A12; r2 = A22; }
+            return cscale(kmul(r0, in[0]) + kmul(r1, in[1]) + kmul(r2, in[2]), inv);
+        }
+    }
+};
+
+// Preconditioner input: chi_O r (r in TR, converted to the chain type).
+template <class T, int D, class TR>
+struct GenMasked {
+    static constexpr int NIN = D;
+    NodeCtx<T> c;
+    const TR* r;
+    __host__ double nbytes() const { return D * (sizeof(TR) + 1.0); }
+    struct Ld { TR r[D]; uint8_t o[D]; };
+    __device__ __forceinline__ Ld load(long i) const {
+        Ld L;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            L.r[d] = r[d * c.nb + i];
+            L.o[d] = c.chiO[d * c.nb + i];
+        }
+        return L;
+    }
+    __device__ __forceinline__ void gen(long, const Ld& L, T (&in)[D]) const {
+#pragma unroll
+        for (int d = 0; d < D; ++d) in[d] = L.o[d] ? T(L.r[d]) : T(0);
+    }
+};
+
 // Test multiplier: a single kernel component odd in P axes, i^P K.
 template <class T>
 struct MulTest {
@@ -829,6 +898,35 @@ struct FinAdj {
         if (wbar) {
             T add = Q.chiB ? wscale * pb : T(0);
             wbar[i] = accumulate ? Q.wb + add : add;
+        }
+    }
+};
+
+// Preconditioner output z = chi_O (M^-1 chi_O r), stored as TZ, with the
+// partial sum r . z (FP64) for the preconditioned CG.
+template <class T, int D, class TR, class TZ>
+struct FinPre {
+    static constexpr int NOUT = D, NRED = 1;
+    NodeCtx<T> c;
+    const TR* r;
+    TZ* z;
+    __host__ double nbytes() const { return D * (sizeof(TR) + sizeof(TZ) + 1.0); }
+    struct Ld { TR r[D]; uint8_t o[D]; };
+    __device__ __forceinline__ Ld load(long i) const {
+        Ld Q;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            Q.r[d] = r[d * c.nb + i];
+            Q.o[d] = c.chiO[d * c.nb + i];
+        }
+        return Q;
+    }
+    __device__ __forceinline__ void fin(long i, const Ld& Q, const T (&val)[D], double* red) const {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const TZ zd = Q.o[d] ? TZ(val[d]) : TZ(0);
+            z[d * c.nb + i] = zd;
+            red[0] += double(Q.r[d]) * double(zd);
         }
     }
 };

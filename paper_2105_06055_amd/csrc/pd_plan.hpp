@@ -40,6 +40,9 @@ struct pd_plan_s {
     int nct, ncs;                // taps components, static components
     uint32_t oddmask;            // last-axis parity of each taps component
     double alpha, m0, kappa, mu, ka, Wc, dt_max, dV;
+    // spectral preconditioner of the static solve, in tap units (Ĉ/Nfft):
+    // diagonal of Ĉ(0), identity shift, normalisation s0 = Ĉ(0)_xx/Nfft
+    double pre_k0[3], pre_shift, pre_s0;
     int beta_comp;               // static component holding the omega_0 bond count
     // device buffers
     void* tw;                    // T twiddles: table for length N at [N, 2N)
