@@ -83,22 +83,27 @@ __global__ void k_taps(int dim, int n1, int n2, int h1, long NP, int ntap, int n
 // Static embedded-constraint fields by direct quadrature over the horizon
 // (the paper allows P = C (*) 1 either by quadrature or by FFT, Sec. 3.1):
 //   stat_c(x) = sum_{o in S} chi_B(x + o) K_c(o)   on the body box.
+// Also flags[i] = chiB[i] | 2 when the node's whole horizon lies in the body
+// (then stat equals the interior sums: every bond counted, same order).
 template <class T>
 __global__ void k_static(int b1, int b2, int b3, int ns, const int* __restrict__ offs,
                          const double* __restrict__ kval, int ncs, const uint8_t* __restrict__ chiB,
-                         T* __restrict__ stat, long nb) {
+                         T* __restrict__ stat, uint8_t* __restrict__ flags, long nb) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb) return;
     const int x = (int)(i % b1), y = (int)((i / b1) % b2), z = (int)(i / ((long)b1 * b2));
     double acc[12];
     for (int c = 0; c < ncs; ++c) acc[c] = 0.0;
+    int inside = 0;
     for (int s = 0; s < ns; ++s) {
         const int xx = x + offs[3 * s], yy = y + offs[3 * s + 1], zz = z + offs[3 * s + 2];
         if (xx < 0 || xx >= b1 || yy < 0 || yy >= b2 || zz < 0 || zz >= b3) continue;
         if (!chiB[((long)zz * b2 + yy) * b1 + xx]) continue;
+        ++inside;
         for (int c = 0; c < ncs; ++c) acc[c] += kval[(long)s * ncs + c];
     }
     for (int c = 0; c < ncs; ++c) stat[(long)c * nb + i] = T(acc[c]);
+    flags[i] = (uint8_t)(chiB[i] ? (inside == ns ? 3 : 1) : 0);
 }
 
 template <class T>
@@ -149,6 +154,8 @@ NodeCtx<T> ctx(pd_plan p) {
     c.chiB = p->chiB;
     c.chiO = p->chiO;
     c.stat = reinterpret_cast<const T*>(p->stat);
+    c.stat_int = reinterpret_cast<const T*>(p->stat_int);
+    c.edge_frac = p->nb > 0 ? (double)p->n_edge / (double)p->nb : 0.0;
     return c;
 }
 
@@ -615,9 +622,36 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
     }
     HIP_TRY(hipMalloc(&p->stat, sizeof(T) * p->nb * ncs));
     p->bytes += sizeof(T) * p->nb * ncs;
+    uint8_t* flags = nullptr;
+    HIP_TRY(hipMalloc(&flags, p->nb));
     hipLaunchKernelGGL((k_static<T>), dim3((unsigned)((p->nb + 255) / 256)), dim3(256), 0, st, g.b1, g.b2, g.b3, ns,
-                       p->offs_dev, p->kval_dev, ncs, p->chiB, reinterpret_cast<T*>(p->stat), p->nb);
-    HIP_TRY(hipGetLastError());
+                       p->offs_dev, p->kval_dev, ncs, p->chiB, reinterpret_cast<T*>(p->stat), flags, p->nb);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipFree(flags);
+        return PD_EDEVICE;
+    }
+    (void)hipFree(p->chiB);
+    p->chiB = flags;   // body | interior << 1
+    {
+        // nodes that read per-node static fields (everything not interior),
+        // for the byte accounting of the passes
+        std::vector<uint8_t> fh((size_t)p->nb);
+        HIP_TRY(hipMemcpy(fh.data(), flags, p->nb, hipMemcpyDeviceToHost));
+        long ne = 0;
+        for (long i = 0; i < p->nb; ++i) ne += (fh[(size_t)i] & 2) ? 0 : 1;
+        p->n_edge = ne;
+    }
+    {
+        // interior values: every bond counted, summed in the same order as k_static
+        std::vector<T> si((size_t)ncs);
+        for (int c = 0; c < ncs; ++c) {
+            double acc = 0.0;
+            for (int s = 0; s < ns; ++s) acc += kv[(size_t)s * ncs + c];
+            si[(size_t)c] = T(acc);
+        }
+        HIP_TRY(hipMalloc(&p->stat_int, sizeof(T) * ncs));
+        HIP_TRY(hipMemcpy(p->stat_int, si.data(), sizeof(T) * ncs, hipMemcpyHostToDevice));
+    }
     HIP_TRY(hipStreamSynchronize(st));
     (void)hipFree(par_dev);
     return PD_OK;
@@ -626,7 +660,7 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
 inline void plan_free(pd_plan p) {
     if (!p) return;
     if (p->stream0) (void)hipStreamSynchronize(p->stream0);
-    void* bufs[] = {p->tw, p->tw64, p->taps, p->taps_d, p->stat, p->chiB, p->chiO, p->SA, p->SB, p->theta,
+    void* bufs[] = {p->tw, p->tw64, p->taps, p->taps_d, p->stat, p->stat_int, p->chiB, p->chiO, p->SA, p->SB, p->theta,
                     p->vtmp, p->vtmp2, p->partials, p->red, p->offs_dev, p->kval_dev};
     for (void* b : bufs)
         if (b) (void)hipFree(b);

@@ -35,12 +35,27 @@ enum { WK_NONE = 0, WK_LAMBDA = 1, WK_SCALE = 2 };
 
 // ----------------------------------------------------------------------------
 // Node context shared by generators and epilogues.
+//
+// chiB[i] bit 0: the node is in the body; bit 1 (set only with bit 0): the
+// node's whole horizon lies in the body ("interior"), so its static fields
+// equal the constants stat_int (the same sums, in the same order) and are
+// read from that small cached table instead of the per-node arrays.  The
+// passes load chiB[i] ahead of the node's other loads and hand it to the
+// generators' and epilogues' load steps.
 template <class T>
 struct NodeCtx {
     long nb;                   // body nodes
-    const uint8_t* chiB;       // [nb]
+    const uint8_t* chiB;       // [nb] body | interior << 1
     const uint8_t* chiO;       // [D][nb]
     const T* stat;             // static fields [ncs][nb]
+    const T* stat_int;         // [ncs] values at interior nodes
+    double edge_frac;          // host bookkeeping: fraction of body-box nodes that
+                               // read per-node static fields (not interior)
+    // static field q at node i with flags cb (a select of addresses, no branch)
+    __device__ __forceinline__ T st(int q, long i, uint8_t cb) const {
+        const T* a = (cb & 2) ? stat_int + q : stat + (long)q * nb + i;
+        return *a;
+    }
 };
 
 // ============================================================================
@@ -86,7 +101,7 @@ struct GenU {
         uint8_t chiB, lam;
         T s, W;
     };
-    __device__ __forceinline__ Ld load(long i) const {
+    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
         Ld L;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -99,7 +114,7 @@ struct GenU {
                 L.o[d] = c.chiO[k];
             }
         }
-        L.chiB = c.chiB[i];
+        L.chiB = cb;
         L.lam = (WK == WK_LAMBDA) ? lam_in[i] : uint8_t(1);
         L.s = (WK == WK_SCALE) ? s[i] : T(1);
         L.W = (VV && WK == WK_LAMBDA) ? W[i] : T(0);
@@ -147,7 +162,7 @@ struct GenTheta {
     const T* theta;
     __host__ double nbytes() const { return sizeof(T) + 1.0; }
     struct Ld { T th; uint8_t chiB; };
-    __device__ __forceinline__ Ld load(long i) const { return {theta[i], c.chiB[i]}; }
+    __device__ __forceinline__ Ld load(long i, uint8_t cb) const { return {theta[i], cb}; }
     __device__ __forceinline__ void gen(long, const Ld& L, T (&in)[1]) const { in[0] = L.chiB ? L.th : T(0); }
 };
 
@@ -159,7 +174,7 @@ struct GenPhi {
     const uint8_t* lam;
     __host__ double nbytes() const { return 2.0; }
     struct Ld { uint8_t chiB, lam; };
-    __device__ __forceinline__ Ld load(long i) const { return {c.chiB[i], lam[i]}; }
+    __device__ __forceinline__ Ld load(long i, uint8_t cb) const { return {cb, lam[i]}; }
     __device__ __forceinline__ void gen(long, const Ld& L, T (&in)[1]) const {
         in[0] = (L.chiB && L.lam) ? T(1) : T(0);
     }
@@ -177,7 +192,7 @@ struct GenAdj {
         return (2 * D + (u2 ? D : 0)) * t + 1 + (WK == WK_SCALE ? t : 0.0) + (WK == WK_LAMBDA ? 1.0 : 0.0);
     }
     struct Ld { T u[D], u2[D], g[D]; uint8_t chiB, lam; T s; };
-    __device__ __forceinline__ Ld load(long i) const {
+    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
         Ld L;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -185,7 +200,7 @@ struct GenAdj {
             L.u2[d] = (u2 ? u2 : u)[d * c.nb + i];
             L.g[d] = g[d * c.nb + i];
         }
-        L.chiB = c.chiB[i];
+        L.chiB = cb;
         L.lam = (WK == WK_LAMBDA) ? lam[i] : uint8_t(1);
         L.s = (WK == WK_SCALE) ? s[i] : T(1);
         return L;
@@ -216,9 +231,10 @@ template <class T>
 struct GenScalar {
     static constexpr int NIN = 1;
     const T* x;
+    __device__ __forceinline__ uint8_t flags(long) const { return 0; }
     __host__ double nbytes() const { return sizeof(T); }
     struct Ld { T x; };
-    __device__ __forceinline__ Ld load(long i) const { return {x[i]}; }
+    __device__ __forceinline__ Ld load(long i, uint8_t cb) const { return {x[i]}; }
     __device__ __forceinline__ void gen(long, const Ld& L, T (&in)[1]) const { in[0] = L.x; }
 };
 
@@ -554,7 +570,7 @@ struct GenMasked {
     const TR* r;
     __host__ double nbytes() const { return D * (sizeof(TR) + 1.0); }
     struct Ld { TR r[D]; uint8_t o[D]; };
-    __device__ __forceinline__ Ld load(long i) const {
+    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
         Ld L;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -614,7 +630,7 @@ struct FinBB {
     __host__ double nbytes() const {
         const double t = sizeof(T);
         double r = D * t + 1 + (WK == WK_LAMBDA ? 1.0 : 0.0) + (WK == WK_SCALE ? t : 0.0);
-        if (!WPHI) r += nsym(D) * t;
+        if (!WPHI) r += nsym(D) * t * c.edge_frac;
         if (ENERGY) r += t;
         if (VV) r += D * (4 * t + 1) + (b ? D * t : 0.0);
         else r += D * t;
@@ -627,13 +643,13 @@ struct FinBB {
         uint8_t chiB, lam;
         T s;
     };
-    __device__ __forceinline__ Ld load(long i) const {
+    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
         Ld Q;
 #pragma unroll
         for (int d = 0; d < D; ++d) Q.u[d] = u[d * c.nb + i];
         if constexpr (!WPHI) {
 #pragma unroll
-            for (int q = 0; q < nsym(D); ++q) Q.G[q] = c.stat[q * c.nb + i];
+            for (int q = 0; q < nsym(D); ++q) Q.G[q] = c.st(q, i, cb);
         }
         if constexpr (VV) {
 #pragma unroll
@@ -645,7 +661,7 @@ struct FinBB {
                 Q.o[d] = c.chiO[k];
             }
         }
-        Q.chiB = c.chiB[i];
+        Q.chiB = cb;
         Q.lam = (WK == WK_LAMBDA) ? lam[i] : uint8_t(1);
         Q.s = (WK == WK_SCALE) ? s[i] : T(1);
         return Q;
@@ -704,17 +720,17 @@ struct FinTheta {
     static constexpr int NOUT = 1, NRED = 0;
     NodeCtx<T> c;
     const T* u; T* theta;
-    __host__ double nbytes() const { return 8.0 * sizeof(T) + 1.0; }
+    __host__ double nbytes() const { return 4.0 * sizeof(T) + 4.0 * sizeof(T) * c.edge_frac + 1.0; }
     struct Ld { T m, g[3], u[3]; uint8_t chiB; };
-    __device__ __forceinline__ Ld load(long i) const {
+    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
         Ld Q;
-        Q.m = c.stat[9 * c.nb + i];
+        Q.m = c.st(9, i, cb);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            Q.g[d] = c.stat[(6 + d) * c.nb + i];
+            Q.g[d] = c.st(6 + d, i, cb);
             Q.u[d] = u[d * c.nb + i];
         }
-        Q.chiB = c.chiB[i];
+        Q.chiB = cb;
         return Q;
     }
     __device__ __forceinline__ void fin(long i, const Ld& Q, const T (&val)[1], double*) const {
@@ -743,7 +759,7 @@ struct FinLin {
     T c1, rho;
     __host__ double nbytes() const {
         const double t = sizeof(T);
-        double r = D * t + 1 + nsym(D) * t + (LPS ? (1 + D) * t : 0.0);
+        double r = D * t + 1 + nsym(D) * t * c.edge_frac + (LPS ? t + D * t * c.edge_frac : 0.0);
         if (MODE == 0) r += D * t;
         else if (MODE == 1) r += D * (4 * t + 1) + (b ? D * t : 0.0);
         else if (MODE == 2) r += D * (t + 1);
@@ -757,18 +773,18 @@ struct FinLin {
         uint8_t o[HAS_O ? D : 1];
         uint8_t chiB;
     };
-    __device__ __forceinline__ Ld load(long i) const {
+    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
         Ld Q;
-        Q.chiB = c.chiB[i];
+        Q.chiB = cb;
 #pragma unroll
         for (int d = 0; d < D; ++d) Q.u[d] = u[d * c.nb + i];
 #pragma unroll
-        for (int q = 0; q < nsym(D); ++q) Q.G[q] = c.stat[q * c.nb + i];
+        for (int q = 0; q < nsym(D); ++q) Q.G[q] = c.st(q, i, cb);
         Q.th = T(0);
         if constexpr (LPS) {
             Q.th = theta[i];
 #pragma unroll
-            for (int d = 0; d < D; ++d) Q.g[d] = c.stat[(6 + d) * c.nb + i];
+            for (int d = 0; d < D; ++d) Q.g[d] = c.st(6 + d, i, cb);
         }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -828,9 +844,9 @@ struct FinCount {
     NodeCtx<T> c;
     int beta_comp;
     const uint8_t* lam; T* d;
-    __host__ double nbytes() const { return 2.0 + 2.0 * sizeof(T); }
+    __host__ double nbytes() const { return 2.0 + sizeof(T) + sizeof(T) * c.edge_frac; }
     struct Ld { T st; uint8_t chiB, lam; };
-    __device__ __forceinline__ Ld load(long i) const { return {c.stat[beta_comp * c.nb + i], c.chiB[i], lam[i]}; }
+    __device__ __forceinline__ Ld load(long i, uint8_t cb) const { return {c.st(beta_comp, i, cb), cb, lam[i]}; }
     __device__ __forceinline__ void fin(long i, const Ld& Q, const T (&val)[1], double*) const {
         int phi = (Q.chiB && Q.lam) ? 1 : 0;
         long cnt = (long)rint(val[0]) + phi;
@@ -858,7 +874,7 @@ struct FinAdj {
                (wbar ? (accumulate ? 2 : 1) * t : 0.0);
     }
     struct Ld { T u[D], u2[D], g[D]; uint8_t chiB, lam; T s, wb; };
-    __device__ __forceinline__ Ld load(long i) const {
+    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
         Ld Q;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -866,7 +882,7 @@ struct FinAdj {
             Q.u2[d] = (u2 ? u2 : u)[d * c.nb + i];
             Q.g[d] = g[d * c.nb + i];
         }
-        Q.chiB = c.chiB[i];
+        Q.chiB = cb;
         Q.lam = (WK == WK_LAMBDA) ? lam[i] : uint8_t(1);
         Q.s = (WK == WK_SCALE) ? s[i] : T(1);
         Q.wb = (wbar && accumulate) ? wbar[i] : T(0);
@@ -912,7 +928,7 @@ struct FinPre {
     TZ* z;
     __host__ double nbytes() const { return D * (sizeof(TR) + sizeof(TZ) + 1.0); }
     struct Ld { TR r[D]; uint8_t o[D]; };
-    __device__ __forceinline__ Ld load(long i) const {
+    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
         Ld Q;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -936,9 +952,10 @@ template <class T>
 struct FinScalar {
     static constexpr int NOUT = 1, NRED = 0;
     T* out;
+    __device__ __forceinline__ uint8_t flags(long) const { return 0; }
     __host__ double nbytes() const { return sizeof(T); }
     struct Ld {};
-    __device__ __forceinline__ Ld load(long) const { return {}; }
+    __device__ __forceinline__ Ld load(long, uint8_t) const { return {}; }
     __device__ __forceinline__ void fin(long i, const Ld&, const T (&val)[1], double*) const { out[i] = val[0]; }
 };
 

@@ -45,6 +45,18 @@ __host__ __device__ constexpr int xblock_threads() { return sizeof(T) == 4 ? 512
 // Body nodes whose loads the x passes issue together (see k_xfwd).
 constexpr int NODE_GROUP = 4;
 
+// Node flags (body | interior << 1) of node i for a generator or epilogue:
+// from its node context where it has one.
+template <class G, class = void>
+struct has_ctx : std::false_type {};
+template <class G>
+struct has_ctx<G, std::void_t<decltype(std::declval<G>().c.chiB)>> : std::true_type {};
+template <class G>
+__device__ __forceinline__ uint8_t node_flags(const G& g, long i) {
+    if constexpr (has_ctx<G>::value) return g.c.chiB[i];
+    else return g.flags(i);
+}
+
 struct Geo {
     int dim;
     int n1, n2, n3;     // FFT grid
@@ -116,13 +128,19 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
     // read-modify-write generator would otherwise wait out one memory latency
     // per slot).  A full block takes a branch-free path.
     auto run_gen = [&](auto full) {
+        uint8_t cbv[RN];
+#pragma unroll
+        for (int r = 0; r < RN; ++r) {
+            const int e = tid + nthr * r;
+            cbv[r] = (decltype(full)::value || e < nval) ? node_flags(gen, nbase + e) : uint8_t(0);
+        }
 #pragma unroll
         for (int r0 = 0; r0 < RN; r0 += NODE_GROUP) {
             typename G::Ld ld[NODE_GROUP];
 #pragma unroll
             for (int q = 0; q < NODE_GROUP; ++q) {
                 const int e = tid + nthr * (r0 + q);
-                if (decltype(full)::value || e < nval) ld[q] = gen.load(nbase + e);
+                if (decltype(full)::value || e < nval) ld[q] = gen.load(nbase + e, cbv[r0 + q]);
             }
 #pragma unroll
             for (int q = 0; q < NODE_GROUP; ++q) {
@@ -807,6 +825,17 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
         pre[8] = (okr && kk == 0) ? src[(long)Nc * g.P2] : cx<T>{T(0), T(0)};
     };
     fetch(0);
+    // flags of this thread's epilogue nodes, loaded ahead of the transforms
+    // (the epilogue's static-field addresses depend on them)
+    constexpr int RN = LG > 0 ? 8 : 16;
+    const long nbase = ((long)z * g.b2 + y0) * g.b1;
+    const int nval = min(Lt, g.b2 - y0) * g.b1;
+    uint8_t cbv[RN];
+#pragma unroll
+    for (int r = 0; r < RN; ++r) {
+        const int e = tid + nthr * r;
+        cbv[r] = e < nval ? node_flags(fin, nbase + e) : uint8_t(0);
+    }
     T val[NO][16];
     lds_ptr<cx<T>> rowv = as_lds(row);
     lds_ptr<cx<T>> ldsv = as_lds(lds);
@@ -839,9 +868,6 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     // epilogue over the block's run of body nodes with consecutive threads on
     // consecutive nodes, the values passing through a flat [Lt][b1] staging
     // area over the row buffers (node slots per thread as in k_xfwd)
-    constexpr int RN = LG > 0 ? 8 : 16;
-    const long nbase = ((long)z * g.b2 + y0) * g.b1;
-    const int nval = min(Lt, g.b2 - y0) * g.b1;
     lds_ptr<T> flat = as_lds(reinterpret_cast<T*>(lds));
     T nv[NO][RN];
 #pragma unroll
@@ -873,7 +899,7 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
 #pragma unroll
             for (int q = 0; q < NODE_GROUP; ++q) {
                 const int e = tid + nthr * (r0 + q);
-                if (decltype(full)::value || e < nval) ld[q] = fin.load(nbase + e);
+                if (decltype(full)::value || e < nval) ld[q] = fin.load(nbase + e, cbv[r0 + q]);
             }
 #pragma unroll
             for (int q = 0; q < NODE_GROUP; ++q) {

@@ -50,7 +50,9 @@ struct pd_plan_s {
     void* taps;                  // T [NP][nct][ntap], transform convention
     void* taps_d;                // T [NP][nct][ntap], direct convention
     void* stat;                  // T [ncs][nb]
-    uint8_t* chiB;               // [nb]
+    void* stat_int;              // T [ncs]: the static fields at interior nodes
+    long n_edge;                 // body-box nodes that are not interior
+    uint8_t* chiB;               // [nb] body | interior << 1 (interior: whole horizon in the body)
     uint8_t* chiO;               // [dim][nb]
     void* SA;                    // complex T workspaces (see pd_passes.hpp)
     void* SB;
