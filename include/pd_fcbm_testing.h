@@ -23,18 +23,26 @@ extern "C" {
  * Synchronises the stream. */
 pd_status pd_test_conv(pd_plan plan, const void* x, const int* shift, int parity, void* out, void* stream);
 
-/* Last-axis kernel selection for A/B tests (every later call on `plan`, and
- * on its FP32 operator for PD_PLAN_MIXED plans):
- *   PD_LASTAXIS_AUTO         direct line correlation when the horizon spans at
- *                            most 4 spacings along the last axis (default),
- *                            else the transform form
- *   PD_LASTAXIS_FFT          transform along the last axis, spectral multiply,
- *                            inverse transform (specialised kernel for
- *                            512-point lines with 4 taps, else runtime length)
+/* Kernel selection after the x transform, for A/B tests (every later call
+ * on `plan`, and on its FP32 operator for PD_PLAN_MIXED plans):
+ *   PD_LASTAXIS_AUTO         3D: direct 2D correlation over (y, z) per
+ *                            x-wavenumber when the horizon's (y, z) footprint
+ *                            is a disc of radius 2 or 3 spacings, for the LPS
+ *                            and unweighted bond-based chains; otherwise as
+ *                            PD_LASTAXIS_YFFT.
+ *                            2D: as PD_LASTAXIS_YFFT (default)
+ *   PD_LASTAXIS_YFFT         transform along y (3D), then the direct line
+ *                            correlation along the last axis when the horizon
+ *                            spans at most 4 spacings there, else the
+ *                            transform form
+ *   PD_LASTAXIS_FFT          transforms along every axis: along the last one
+ *                            transform, spectral multiply, inverse transform
+ *                            (specialised kernel for 512-point lines with 4
+ *                            taps, else runtime length)
  *   PD_LASTAXIS_FFT_GENERIC  transform form, runtime-length kernel only
  * All compute the same correlation; results agree to rounding.  PD_EINVAL
  * for a null plan or an unknown mode. */
-enum { PD_LASTAXIS_AUTO = 0, PD_LASTAXIS_FFT = 1, PD_LASTAXIS_FFT_GENERIC = 2 };
+enum { PD_LASTAXIS_AUTO = 0, PD_LASTAXIS_FFT = 1, PD_LASTAXIS_FFT_GENERIC = 2, PD_LASTAXIS_YFFT = 3 };
 pd_status pd_test_set_lastaxis(pd_plan plan, int mode);
 
 #ifdef __cplusplus

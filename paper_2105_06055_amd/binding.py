@@ -280,12 +280,14 @@ class Plan:
         _check(lib().pd_test_conv(self._h, _ptr(x), sh, int(parity), _ptr(out), _stream()), "pd_test_conv")
         return out
 
-    LASTAXIS = {"auto": 0, "fft": 1, "fft_generic": 2}
+    LASTAXIS = {"auto": 0, "fft": 1, "fft_generic": 2, "yfft": 3}
 
     def set_lastaxis(self, mode="auto"):
-        """Last-axis kernel choice (A/B tests): 'auto' (direct line
-        correlation for short horizons), 'fft' (transform + spectral
-        multiply, specialised where it applies) or 'fft_generic'."""
+        """Kernel choice after the x transform (A/B tests): 'auto' (3D: the
+        direct (y, z) correlation where it applies), 'yfft' (transform along
+        y, direct line correlation along the last axis), 'fft' (transforms on
+        every axis, spectral multiply, specialised where it applies) or
+        'fft_generic'."""
         _check(lib().pd_test_set_lastaxis(self._h, self.LASTAXIS[mode]), "pd_test_set_lastaxis")
 
     def close(self):

@@ -13,29 +13,6 @@ pd_status check(hipError_t e) {
 
 }  // namespace pdh
 
-// instantiated in pd_inst.hip
-namespace pdi {
-#define PD_EXTERN(T)                                                                                               \
-    extern template pd_status plan_alloc<T>(pd_plan, hipStream_t, const uint8_t*, const uint8_t*);                \
-    extern template pd_status build_device_tables<T>(pd_plan, const std::vector<Bond>&, hipStream_t);             \
-    extern template pd_status force_impl<T>(pd_plan, const T*, const void*, T*, T*, hipStream_t);                 \
-    extern template pd_status adjoint_impl<T>(pd_plan, const T*, const T*, const void*, const T*, T*, T*, T, int, \
-                                              hipStream_t);                                                       \
-    extern template pd_status damage_impl<T>(pd_plan, const uint8_t*, T*, hipStream_t);                           \
-    extern template pd_status test_conv_impl<T>(pd_plan, const T*, const int*, int, T*, hipStream_t);             \
-    extern template pd_status verlet_impl<T>(pd_plan, pd_state*, const T*, const T*, double, int, double*,        \
-                                             hipStream_t);                                                        \
-    extern template pd_status verlet_adjoint_impl<T>(pd_plan, const T*, const T*, const T*, T*, T*, T*, double,   \
-                                                     hipStream_t);                                                \
-    extern template pd_status cg_run<T, T>(pd_plan, T*, T*, T*, T*, T*, double, double, int, int*, int*, double*, \
-                                           hipStream_t);                                                          \
-    extern template pd_status lin_apply<T, 3>(pd_plan, const T*, T*, const T*, hipStream_t);                      \
-    extern template pd_status lin_apply<T, 2>(pd_plan, const T*, T*, const T*, hipStream_t);                      \
-    extern template pd_status precond_apply<T, double, T>(pd_plan, const double*, T*, hipStream_t);
-PD_EXTERN(float)
-PD_EXTERN(double)
-#undef PD_EXTERN
-}  // namespace pdi
 
 using namespace pdi;
 
@@ -184,7 +161,7 @@ pd_status pd_test_conv(pd_plan p, const void* x, const int* shift, int parity, v
 }
 
 pd_status pd_test_set_lastaxis(pd_plan p, int mode) {
-    if (!p || mode < PD_LASTAXIS_AUTO || mode > PD_LASTAXIS_FFT_GENERIC) return PD_EINVAL;
+    if (!p || mode < PD_LASTAXIS_AUTO || mode > PD_LASTAXIS_YFFT) return PD_EINVAL;
     p->lastaxis = mode;
     if (p->sub32) p->sub32->lastaxis = mode;
     return PD_OK;

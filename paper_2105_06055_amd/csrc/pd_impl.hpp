@@ -80,6 +80,35 @@ __global__ void k_taps(int dim, int n1, int n2, int h1, long NP, int ntap, int n
     for (int c = 0; c < nct; ++c) taps[((long)p * nct + c) * ntap + t] = T(acc[c] * sc);
 }
 
+// Partial x-spectra over the (y, z) quarter disc, FP64 accumulation:
+//   tau_c(kx; a, b) = sc * sum_{o in S, o_y = a, o_z = b} K_c(o) trig_{p_cx}(2 pi kx o_x / n1)
+// for a, b >= 0, a^2 + b^2 <= MT^2 (tap u = yz_tap(MT, a, b)); sc = 1/n1,
+// the normalisation of the unnormalised x transform pair.  The taps at
+// negative o_y, o_z follow from the parities of K_c.  Layout [kx][c][u].
+template <class T>
+__global__ void k_taps_yz(int n1, int h1, int MT, int nu, int ns, const int* __restrict__ offs,
+                          const double* __restrict__ kval, int kstride, int nct, const uint8_t* __restrict__ par,
+                          const double* __restrict__ tw64, double sc, T* __restrict__ taps) {
+    long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)h1 * nu) return;
+    const int kx = (int)(idx / nu), u = (int)(idx % nu);
+    int ta = -1, tb = -1;
+    for (int b = 0; b <= MT && ta < 0; ++b)
+        for (int a = 0; a <= MT; ++a)
+            if (a * a + b * b <= MT * MT && yz_tap(MT, a, b) == u) { ta = a; tb = b; break; }
+    double acc[12];
+    for (int c = 0; c < nct; ++c) acc[c] = 0.0;
+    const double* twx = tw64 + 2 * n1;
+    for (int s = 0; s < ns; ++s) {
+        if (offs[3 * s + 1] != ta || offs[3 * s + 2] != tb) continue;
+        int ex = (int)(((long)kx * offs[3 * s]) % n1);
+        if (ex < 0) ex += n1;
+        const double cxv = twx[2 * ex], sxv = -twx[2 * ex + 1];
+        for (int c = 0; c < nct; ++c) acc[c] += kval[(long)s * kstride + c] * (par[3 * c] ? sxv : cxv);
+    }
+    for (int c = 0; c < nct; ++c) taps[((long)kx * nct + c) * nu + u] = T(acc[c] * sc);
+}
+
 // Static embedded-constraint fields by direct quadrature over the horizon
 // (the paper allows P = C (*) 1 either by quadrature or by FFT, Sec. 3.1):
 //   stat_c(x) = sum_{o in S} chi_B(x + o) K_c(o)   on the body box.
@@ -277,7 +306,8 @@ pd_status launch_lastmul(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, con
     constexpr bool direct_ok = !M::RT_ODD && !is_nonlocal<M>::value;
     int path = 2;   // 0 direct, 1 specialised FFT, 2 generic FFT
     if constexpr (direct_ok) {
-        if (p->lastaxis == PD_LASTAXIS_AUTO && taps_d && ntap >= 2 && ntap <= 5) path = 0;
+        if ((p->lastaxis == PD_LASTAXIS_AUTO || p->lastaxis == PD_LASTAXIS_YFFT) && taps_d && ntap >= 2 && ntap <= 5)
+            path = 0;
     }
     if constexpr (!M::RT_ODD) {
         if (path != 0 && p->lastaxis != PD_LASTAXIS_FFT_GENERIC && ln.N == 512 && ntap == 4) path = 1;
@@ -322,6 +352,110 @@ pd_status launch_lastmul(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, con
                         (double)M::NC * ntap * ln.nlines * sizeof(T));
     }
     return pdh::check(hipGetLastError());
+}
+
+// (y, z) direct pass (3D), for horizons of radius MT = 2 or 3 spacings in
+// (y, z).  A multiplier qualifies when its terms have compile-time parities
+// (par3) and are local, the ring of 2 MT + 1 output planes fits in at most
+// 128 registers per thread, and it is one of the chains built with the pass
+// (the force, Verlet and static chains: LPS dilatation and force, unweighted
+// bond-based); the weighted bond-based and adjoint chains, with up to 13
+// outputs, take the y transform path.
+template <class M, class = void>
+struct has_par3 : std::false_type {};
+template <class M>
+struct has_par3<M, std::void_t<decltype(M::par3(0))>> : std::true_type {};
+
+template <class T, class M, int MT>
+constexpr bool yz_fits() {
+    return M::NOUT * (2 * MT + 1) * 2 * (int)(sizeof(T) / 4) <= 128;
+}
+template <class T, class M>
+constexpr bool yz_capable() {
+    return std::is_same<M, MulLPSA<T>>::value || std::is_same<M, MulLPSB<T>>::value ||
+           std::is_same<M, MulBB<T, 3, false, false>>::value;
+}
+
+template <class T, class M, int MT, int YT>
+pd_status launch_yzconv_t(pd_plan p, const M& mul, int in_off, int out_off, hipStream_t st) {
+    const Geo& g = p->geo;
+    YZArgs a;
+    a.b2 = g.b2; a.b3 = g.b3; a.h1 = g.h1; a.P2 = g.P2;
+    a.saf = g.saf;
+    a.nyt = (g.b2 + YT - 1) / YT;
+    // planes per chunk: enough blocks for ~16 waves per CU of 256 CUs, and
+    // chunks of at least 4 MT planes (the halo planes are read twice)
+    const long tiles = (long)g.h1 * a.nyt;
+    const long want = std::max(1L, (256L * 16 * 64 / YT + tiles - 1) / tiles);
+    int zc = (int)std::max<long>(4L * MT, (g.b3 + want - 1) / want);
+    zc = std::min(zc, g.b3);
+    a.zc = zc;
+    a.nzc = (g.b3 + zc - 1) / zc;
+    a.in_off = in_off; a.out_off = out_off;
+    a.nct = p->nct;
+    const long nblk = tiles * a.nzc;
+    const size_t lds = (size_t)2 * M::NIN * (YT + 2 * MT) * sizeof(cx<T>);
+    if (lds > (size_t)p->max_lds || nblk > 0x7fffffffL) return PD_EUNSUPPORTED;
+    allow_lds(k_yzconv<T, M, MT, YT>, lds);
+    hipLaunchKernelGGL((k_yzconv<T, M, MT, YT>), dim3((unsigned)nblk), dim3(YT), lds, st, a, mul, SAp<T>(p),
+                       reinterpret_cast<const T*>(p->taps_yz));
+    return PD_OK;
+}
+
+template <class T, class M>
+pd_status launch_yzconv(pd_plan p, const M& mul, int in_off, int out_off, hipStream_t st) {
+    pd_status s = PD_EUNSUPPORTED;
+    ProfScope ps(p, st);
+    const bool wide = p->geo.b2 > 128;
+    auto go = [&](auto mtc) {
+        constexpr int MT = decltype(mtc)::value;
+        if constexpr (yz_fits<T, M, MT>()) {
+            s = wide ? launch_yzconv_t<T, M, MT, 256>(p, mul, in_off, out_off, st)
+                     : launch_yzconv_t<T, M, MT, 128>(p, mul, in_off, out_off, st);
+        }
+    };
+    switch (p->yz_mt) {
+        case 2: go(std::integral_constant<int, 2>{}); break;
+        case 3: go(std::integral_constant<int, 3>{}); break;
+        default: break;
+    }
+    PD_TRY(s);
+    if (p->prof) {
+        const Geo& g = p->geo;
+        char nm[32];
+        std::snprintf(nm, sizeof nm, "yzconv_%dx%d", M::NIN, M::NOUT);
+        ps.done(nm, (double)(M::NIN + M::NOUT) * g.b3 * g.h1 * g.b2 * sizeof(cx<T>) +
+                        (double)M::NC * p->yz_nu * g.h1 * sizeof(T));
+    }
+    return pdh::check(hipGetLastError());
+}
+
+// The (y, z) pass kernels are instantiated once per (dtype, multiplier), in
+// instantiation units of their own (pd_inst.hip, parts 4 and 5).
+template <class T> using YzBB = MulBB<T, 3, false, false>;
+#define PD_YZ_LIST_A(X, T) X(T, MulLPSB<T>)
+#define PD_YZ_LIST_B(X, T) X(T, MulLPSA<T>) X(T, YzBB<T>)
+#define PD_YZ_DECL(T, M) extern template pd_status launch_yzconv<T, M>(pd_plan, const M&, int, int, hipStream_t);
+#if !defined(PD_INST_PART) || (PD_INST_PART != 4 && PD_INST_PART != 5)
+PD_YZ_LIST_A(PD_YZ_DECL, float)
+PD_YZ_LIST_A(PD_YZ_DECL, double)
+PD_YZ_LIST_B(PD_YZ_DECL, float)
+PD_YZ_LIST_B(PD_YZ_DECL, double)
+#endif
+
+// Whether a chain takes the (y, z) direct pass: 3D plan tables, the default
+// kernel choice, and a multiplier that qualifies at the plan's radius.
+template <class T, class M>
+bool use_yz(pd_plan p) {
+    if constexpr (!yz_capable<T, M>()) return false;
+    else {
+        if (p->geo.dim != 3 || !p->taps_yz || p->lastaxis != PD_LASTAXIS_AUTO) return false;
+        switch (p->yz_mt) {
+            case 2: return yz_fits<T, M, 2>();
+            case 3: return yz_fits<T, M, 3>();
+            default: return false;
+        }
+    }
 }
 
 // planes per block of the transposing y passes
@@ -416,6 +550,18 @@ pd_status run_chain(pd_plan p, const G& gen, const M& mul, const F& fin, hipStre
         oddmask = p->oddmask;
     }
     if (std::max(G::NIN, M::NOUT) > p->saf_cap) return PD_EINVAL;
+    if constexpr (yz_capable<T, M>()) {
+        if (taps_d && use_yz<T, M>(p)) {
+            // x transform, (y, z) direct pass, inverse x transform; the generator
+            // writes SA slots [sb_off, sb_off + G::NIN), the multiplier reads
+            // [0, M::NIN) and writes after its inputs
+            const int wo = std::max(out_off, M::NIN);
+            if (sb_off + G::NIN > p->saf_cap || wo + M::NOUT > p->saf_cap) return PD_EINVAL;
+            PD_TRY(launch_xfwd<T>(p, gen, SAp<T>(p) + (long)sb_off * g.saf, st));
+            PD_TRY((launch_yzconv<T, M>(p, mul, 0, wo, st)));
+            return launch_xinv<T>(p, fin, SAp<T>(p) + (long)wo * g.saf, st);
+        }
+    }
     PD_TRY(launch_xfwd<T>(p, gen, SAp<T>(p), st));
     if (g.dim == 2) {
         if (G::NIN != M::NIN) return PD_EINVAL;
@@ -620,6 +766,27 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
                            nl * inv, nl * inv, reinterpret_cast<T*>(p->taps_d));
         HIP_TRY(hipGetLastError());
     }
+    // (y, z) direct pass: needs every bond inside the quarter-disc footprint
+    // of radius MT = max(|o_y|, |o_z|), 2 or 3
+    p->yz_mt = p->yz_nu = 0;
+    if (D == 3) {
+        int mt = 0;
+        for (int s = 0; s < ns; ++s) mt = std::max(mt, std::max(std::abs(S[s].o[1]), std::abs(S[s].o[2])));
+        bool fits = mt >= 2 && mt <= 3;
+        for (int s = 0; s < ns && fits; ++s)
+            fits = S[s].o[1] * S[s].o[1] + S[s].o[2] * S[s].o[2] <= mt * mt;
+        if (fits) {
+            p->yz_mt = mt;
+            p->yz_nu = yz_ntap(mt);
+            const long n = (long)g.h1 * p->yz_nu;
+            HIP_TRY(hipMalloc(&p->taps_yz, sizeof(T) * n * nct));
+            p->bytes += sizeof(T) * n * nct;
+            hipLaunchKernelGGL((k_taps_yz<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.n1, g.h1, mt,
+                               p->yz_nu, ns, p->offs_dev, p->kval_dev, ncs, nct, par_dev, p->tw64,
+                               1.0 / (double)g.n1, reinterpret_cast<T*>(p->taps_yz));
+            HIP_TRY(hipGetLastError());
+        }
+    }
     HIP_TRY(hipMalloc(&p->stat, sizeof(T) * p->nb * ncs));
     p->bytes += sizeof(T) * p->nb * ncs;
     uint8_t* flags = nullptr;
@@ -660,7 +827,7 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
 inline void plan_free(pd_plan p) {
     if (!p) return;
     if (p->stream0) (void)hipStreamSynchronize(p->stream0);
-    void* bufs[] = {p->tw, p->tw64, p->taps, p->taps_d, p->stat, p->stat_int, p->chiB, p->chiO, p->SA, p->SB, p->theta,
+    void* bufs[] = {p->tw, p->tw64, p->taps, p->taps_d, p->taps_yz, p->stat, p->stat_int, p->chiB, p->chiO, p->SA, p->SB, p->theta,
                     p->vtmp, p->vtmp2, p->partials, p->red, p->offs_dev, p->kval_dev};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -714,7 +881,8 @@ pd_status plan_alloc(pd_plan p, hipStream_t st, const uint8_t* chiB_h, const uin
         // weighted + energy: in D+1+nsym, out D+nsym+1; adjoint: in 2D+1+nsym, out 2D+nsym+1
         capA = 2 * D + 1 + nsym(D) + 1;
     } else {
-        capA = (p->kern.model == PD_LPS_LINEAR) ? 4 : (2 * D + 1 + nsym(D) + 1);
+        // LPS: 3 + 1 inputs and the 3 outputs of the (y, z) direct pass
+        capA = (p->kern.model == PD_LPS_LINEAR) ? 7 : (2 * D + 1 + nsym(D) + 1);
         capB = (p->kern.model == PD_LPS_LINEAR) ? 4 : (2 * D + 1 + nsym(D) + 1);
         capC = (p->kern.model == PD_LPS_LINEAR) ? 3 : (2 * D + nsym(D) + 1);
     }
@@ -1638,3 +1806,29 @@ inline hipStream_t S_(void* s) { return reinterpret_cast<hipStream_t>(s); }
 }  // namespace pdi
 
 // ===================================================================== C ABI
+
+// The per-dtype implementation is instantiated once, in pd_inst.hip (each
+// unit defines its share after these declarations); every other use only
+// refers to it, so no unit compiles what another one holds.
+namespace pdi {
+#define PD_EXTERN(T)                                                                                               \
+    extern template pd_status plan_alloc<T>(pd_plan, hipStream_t, const uint8_t*, const uint8_t*);                \
+    extern template pd_status build_device_tables<T>(pd_plan, const std::vector<Bond>&, hipStream_t);             \
+    extern template pd_status force_impl<T>(pd_plan, const T*, const void*, T*, T*, hipStream_t);                 \
+    extern template pd_status adjoint_impl<T>(pd_plan, const T*, const T*, const void*, const T*, T*, T*, T, int, \
+                                              hipStream_t);                                                       \
+    extern template pd_status damage_impl<T>(pd_plan, const uint8_t*, T*, hipStream_t);                           \
+    extern template pd_status test_conv_impl<T>(pd_plan, const T*, const int*, int, T*, hipStream_t);             \
+    extern template pd_status verlet_impl<T>(pd_plan, pd_state*, const T*, const T*, double, int, double*,        \
+                                             hipStream_t);                                                        \
+    extern template pd_status verlet_adjoint_impl<T>(pd_plan, const T*, const T*, const T*, T*, T*, T*, double,   \
+                                                     hipStream_t);                                                \
+    extern template pd_status cg_run<T, T>(pd_plan, T*, T*, T*, T*, T*, double, double, int, int*, int*, double*, \
+                                           hipStream_t);                                                          \
+    extern template pd_status lin_apply<T, 3>(pd_plan, const T*, T*, const T*, hipStream_t);                      \
+    extern template pd_status lin_apply<T, 2>(pd_plan, const T*, T*, const T*, hipStream_t);                      \
+    extern template pd_status precond_apply<T, double, T>(pd_plan, const double*, T*, hipStream_t);
+PD_EXTERN(float)
+PD_EXTERN(double)
+#undef PD_EXTERN
+}  // namespace pdi

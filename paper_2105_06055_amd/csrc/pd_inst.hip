@@ -1,5 +1,6 @@
 // pd_inst.hip -- explicit instantiation of the per-dtype implementation
-// (PD_INST_T = float or double; PD_INST_PART selects a share of it), so that
+// (PD_INST_T = float or double; PD_INST_PART selects a share of it: 0 .. 3
+// the entry-point implementations, 4 and 5 the (y, z) pass kernels), so that
 // the library's device code compiles in parallel units.
 #include "pd_impl.hpp"
 
@@ -7,7 +8,7 @@
 #error "PD_INST_T must be defined (float or double)"
 #endif
 #ifndef PD_INST_PART
-#error "PD_INST_PART must be defined (0 .. 3)"
+#error "PD_INST_PART must be defined (0 .. 5)"
 #endif
 
 namespace pdi {
@@ -24,6 +25,12 @@ template pd_status cg_run<PD_INST_T, PD_INST_T>(pd_plan, PD_INST_T*, PD_INST_T*,
 template pd_status lin_apply<PD_INST_T, 3>(pd_plan, const PD_INST_T*, PD_INST_T*, const PD_INST_T*, hipStream_t);
 template pd_status lin_apply<PD_INST_T, 2>(pd_plan, const PD_INST_T*, PD_INST_T*, const PD_INST_T*, hipStream_t);
 template pd_status precond_apply<PD_INST_T, double, PD_INST_T>(pd_plan, const double*, PD_INST_T*, hipStream_t);
+#elif PD_INST_PART == 4
+#define PD_YZ_DEF(T, M) template pd_status launch_yzconv<T, M>(pd_plan, const M&, int, int, hipStream_t);
+PD_YZ_LIST_A(PD_YZ_DEF, PD_INST_T)
+#elif PD_INST_PART == 5
+#define PD_YZ_DEF(T, M) template pd_status launch_yzconv<T, M>(pd_plan, const M&, int, int, hipStream_t);
+PD_YZ_LIST_B(PD_YZ_DEF, PD_INST_T)
 #else
 template pd_status plan_alloc<PD_INST_T>(pd_plan, hipStream_t, const uint8_t*, const uint8_t*);
 template pd_status build_device_tables<PD_INST_T>(pd_plan, const std::vector<Bond>&, hipStream_t);

@@ -258,6 +258,14 @@ struct DTerm {
 __host__ __device__ constexpr bool sym_diag(int D, int c) {
     return c == 0 || (D == 2 ? c == 2 : (c == 3 || c == 5));
 }
+// Odd axes of the tensor component C_ij stored at symi(D, i, j): bit d set
+// when exactly one of i, j equals d (xi_i xi_j / r^2 changes sign with o_d).
+__host__ __device__ constexpr int sym_par(int D, int c) {
+    for (int i = 0; i < D; ++i)
+        for (int j = i; j < D; ++j)
+            if (symi(D, i, j) == c) return (1 << i) ^ (1 << j);
+    return 0;
+}
 
 // Bond-based: conv_i = sum_j M[C_ij] U_j; [G_c = M[C_c] Phi]; [E = sum_c m_c M[C_c] F_c]
 // with M[C_ij] = K (i == j) or -K (i != j: two odd axes, i^2 = -1).
@@ -270,6 +278,9 @@ struct MulBB {
     static constexpr bool RT_ODD = false;
     static constexpr uint32_t ODD = (D == 2) ? (1u << 1) : ((1u << 2) | (1u << 4));
     __device__ __forceinline__ T ka_value() const { return T(0); }
+    // odd axes (bits x, y, z) of component C0 + c
+    static constexpr int DIM = D;
+    __host__ __device__ static constexpr int par3(int c) { return sym_par(D, c); }
     __host__ __device__ static constexpr DTerm dterm(int O, int J) {
         if (O < D) return J < D ? DTerm{symi(D, O, J), O == J ? 1 : -1, 0, false} : DTerm{0, 0, 0, false};
         if (WPHI && O < D + nsym(D)) return J == D ? DTerm{O - D, sym_diag(D, O - D) ? 1 : -1, 0, false}
@@ -358,6 +369,8 @@ struct MulLPSA {
     static constexpr bool RT_ODD = false;
     static constexpr uint32_t ODD = (1u << 2) | (1u << 4) | (1u << 8);
     __device__ __forceinline__ T ka_value() const { return T(0); }
+    static constexpr int DIM = 3;
+    __host__ __device__ static constexpr int par3(int c) { return 1 << c; }   // a0_c = omega xi_c
     __host__ __device__ static constexpr DTerm dterm(int, int J) { return DTerm{J, 1, 1, false}; }
     template <int O>
     __host__ __device__ static constexpr uint32_t need() { return 7u; }
@@ -382,6 +395,8 @@ struct MulLPSB {
     static constexpr bool RT_ODD = false;
     static constexpr uint32_t ODD = (1u << 2) | (1u << 4) | (1u << 8);
     __device__ __forceinline__ T ka_value() const { return ka; }
+    static constexpr int DIM = 3;
+    __host__ __device__ static constexpr int par3(int c) { return c < 6 ? sym_par(3, c) : 1 << (c - 6); }
     __host__ __device__ static constexpr DTerm dterm(int O, int J) {
         return J < 3 ? DTerm{symi(3, O, J), O == J ? 1 : -1, 0, false} : DTerm{6 + O, 1, 1, true};
     }
@@ -421,6 +436,8 @@ struct MulCount {
     static constexpr bool RT_ODD = false;
     static constexpr uint32_t ODD = 0u;
     __device__ __forceinline__ T ka_value() const { return T(0); }
+    static constexpr int DIM = D;
+    __host__ __device__ static constexpr int par3(int) { return 0; }
     __host__ __device__ static constexpr DTerm dterm(int, int) { return DTerm{0, 1, 0, false}; }
     template <int O>
     __host__ __device__ static constexpr uint32_t need() { return 1u; }
@@ -441,6 +458,8 @@ struct MulAdj {
     static constexpr bool RT_ODD = false;
     static constexpr uint32_t ODD = (D == 2) ? (1u << 1) : ((1u << 2) | (1u << 4));
     __device__ __forceinline__ T ka_value() const { return T(0); }
+    static constexpr int DIM = D;
+    __host__ __device__ static constexpr int par3(int c) { return sym_par(D, c); }
     __host__ __device__ static constexpr DTerm dterm(int O, int J) {
         if (O < D) return J < D ? DTerm{symi(D, O, J), O == J ? 1 : -1, 0, false} : DTerm{0, 0, 0, false};
         if (O < D + nsym(D)) return J == D ? DTerm{O - D, sym_diag(D, O - D) ? 1 : -1, 0, false}

@@ -705,6 +705,193 @@ k_lastconv(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps, int nct) {
 }
 
 // ----------------------------------------------------------------------------
+// (y, z) pass by direct summation (3D).  After the transform along x alone,
+// the multiplier of component c at x-wavenumber kx is, over (y, z), a 2D
+// trigonometric polynomial whose coefficients are the partial x-spectra
+//   tau_c(kx; oy, oz) = sum_ox K_c(o) trig_c(2 pi kx ox / n1)
+// (cos for a component even along x; sin, times i, for an odd one).
+// Multiplying by it and transforming back along y and z is, exactly, the 2D
+// correlation  out(y, z) = sum_{oy, oz} i^{p_x} tau_c(kx; oy, oz) g(y + oy, z + oz)
+// over the body rows and planes: the box leaves at least one horizon of
+// zeros beyond the body along y and z, so the periodic wrap meets only
+// zeros.  K_c is even or odd along y and along z, so the four points
+// (+-oy, +-oz) enter as sums or differences and only the taps with
+// oy, oz >= 0 inside the horizon's quarter disc oy^2 + oz^2 <= MT^2 are
+// stored (yz_tap numbers them).  Each multiplier term (DTerm) applies with
+// the real factor coef * i^(ipow - #odd axes), the powers of i of the full
+// 3D multiplier other than the x one being the y and z parities here.
+//
+// A block takes one x-wavenumber, a tile of YT consecutive rows y (one per
+// thread) and a chunk of planes z, and sweeps the input planes in order.
+// Each plane goes through LDS with MT halo rows on either side, so a thread
+// forms its y-neighbour sums and differences there; the plane's
+// contributions go into the accumulators of the 2 MT + 1 output planes it
+// reaches (a register ring), and an output plane is stored as soon as its
+// last input plane is in.  The inputs of the next plane are loaded before
+// the arithmetic of the current one.  Outputs go to other SA fields than the
+// inputs (neighbouring chunks read each other's planes).
+struct YZArgs {
+    int b2, b3, h1, P2;
+    long saf;              // field stride of SA
+    int nyt, nzc, zc;      // y tiles, z chunks, planes per chunk
+    int in_off, out_off;   // SA field slots of the inputs and of the outputs
+    int nct;               // components per x-wavenumber in the taps table
+};
+
+__host__ __device__ constexpr int yz_tap(int MT, int a, int b) {
+    int n = 0;
+    for (int bb = 0; bb <= MT; ++bb)
+        for (int aa = 0; aa <= MT; ++aa) {
+            if (aa * aa + bb * bb > MT * MT) continue;
+            if (aa == a && bb == b) return n;
+            ++n;
+        }
+    return n;   // (a, b) outside the quarter disc: the number of taps
+}
+__host__ __device__ constexpr int yz_ntap(int MT) { return yz_tap(MT, MT + 1, MT + 1); }
+
+// popcount of a 3-bit parity
+__host__ __device__ constexpr int npar(int p) { return (p & 1) + ((p >> 1) & 1) + ((p >> 2) & 1); }
+
+// Real factor of a term in the (y, z) form: coef * i^(ipow - #odd axes).
+template <class M>
+__host__ __device__ constexpr int yz_factor(DTerm t) {
+    const int e = ((t.ipow - npar(M::par3(t.c))) % 4 + 4) % 4;
+    return e == 0 ? t.coef : -t.coef;   // e is 0 or 2 for a real-space kernel
+}
+
+template <class T, class M, int MT, int YT>
+__global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const T* __restrict__ taps) {
+    constexpr int NI = M::NIN, NO = M::NOUT, R = 2 * MT + 1, W = YT + 2 * MT, NU = yz_ntap(MT);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    lds_ptr<cx<T>> lds = as_lds(reinterpret_cast<cx<T>*>(smem_raw));
+    // block -> (kx, y tile, z chunk): consecutive chunks of one (kx, tile) on one XCD
+    const long nblk = (long)a.h1 * a.nyt * a.nzc;
+    const long bq = nblk >> 3, br = nblk & 7;
+    const long xcd = blockIdx.x & 7, bk = blockIdx.x >> 3;
+    const long lin = xcd < br ? xcd * (bq + 1) + bk : br * (bq + 1) + (xcd - br) * bq + bk;
+    const int zc = (int)(lin % a.nzc);
+    const long t2 = lin / a.nzc;
+    const int yt = (int)(t2 % a.nyt);
+    const int kx = (int)(t2 / a.nyt);
+
+    const int tid = threadIdx.x;
+    const int y0 = yt * YT, y = y0 + tid;
+    const bool yin = y < a.b2;
+    // halo rows: threads 0 .. MT-1 the MT rows below the tile, MT .. 2MT-1 the MT above
+    const bool hlo = tid < MT, hthr = tid < 2 * MT;
+    const int yh = hlo ? y0 - MT + tid : y0 + YT + (tid - MT);
+    const int ph = hlo ? tid : YT + tid;
+    const bool hin = hthr && yh >= 0 && yh < a.b2;
+    const int z0 = zc * a.zc, z1 = min(a.b3, z0 + a.zc);
+    const T* __restrict__ tk = taps + ((long)kx * a.nct + M::C0) * NU;   // block-uniform
+    const T ka = mul.ka_value();
+    const long zs = (long)a.h1 * a.P2;
+    const cx<T>* __restrict__ src = S + (long)a.in_off * a.saf + (long)kx * a.P2;
+    cx<T>* __restrict__ dst = S + (long)a.out_off * a.saf + (long)kx * a.P2 + y;
+
+    cx<T> acc[R][NO];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int o = 0; o < NO; ++o) acc[r][o] = cx<T>{T(0), T(0)};
+    cx<T> nv[NI], nh[NI];   // inputs of the next plane (row y, halo row yh)
+    auto load = [&](int z) {
+        const bool zin = z >= 0 && z < a.b3;
+#pragma unroll
+        for (int J = 0; J < NI; ++J) {
+            nv[J] = cx<T>{T(0), T(0)};
+            nh[J] = cx<T>{T(0), T(0)};
+            if (zin && yin) nv[J] = src[J * a.saf + z * zs + y];
+            if (zin && hin) nh[J] = src[J * a.saf + z * zs + yh];
+        }
+    };
+
+    const int zb = z0 - MT;               // first input plane of the sweep
+    const int nst = (z1 - z0) + 2 * MT;   // input planes swept
+    load(zb);
+    for (int s0 = 0; s0 < nst; s0 += R) {
+        OutLoop<0, R>::run([&](auto rc) {
+            constexpr int rr = decltype(rc)::value;
+            const int s = s0 + rr;
+            if (s >= nst) return;   // block-uniform
+            const int zi = zb + s;
+            const bool act = zi >= 0 && zi < a.b3;   // block-uniform
+            lds_ptr<cx<T>> row = lds + (s & 1) * (NI * W);
+            cx<T> cv[NI];
+            if (act) {
+#pragma unroll
+                for (int J = 0; J < NI; ++J) {
+                    cv[J] = nv[J];
+                    row[J * W + MT + tid] = nv[J];
+                    if (hthr) row[J * W + ph] = nh[J];
+                }
+                __syncthreads();
+            }
+            load(zi + 1);
+            if (act) {
+                OutLoop<0, NI>::run([&](auto Jc) {
+                    constexpr int J = decltype(Jc)::value;
+                    // y-neighbour sums (pe) and differences (po) at this row
+                    cx<T> pe[MT + 1], po[MT + 1];
+                    pe[0] = cv[J];
+                    po[0] = cx<T>{T(0), T(0)};
+#pragma unroll
+                    for (int t = 1; t <= MT; ++t) {
+                        const cx<T> up = row[J * W + MT + tid + t], dn = row[J * W + MT + tid - t];
+                        pe[t] = up + dn;
+                        po[t] = up - dn;
+                    }
+                    OutLoop<0, NO>::run([&](auto Oc) {
+                        constexpr int O = decltype(Oc)::value;
+                        constexpr DTerm tm = M::dterm(O, J);
+                        if constexpr (tm.coef != 0) {
+                            constexpr int pr = M::par3(tm.c);
+                            constexpr bool px = pr & 1, py = (pr >> 1) & 1, pz = (pr >> 2) & 1;
+                            constexpr int fr = yz_factor<M>(tm);
+                            OutLoop<pz ? 1 : 0, MT + 1>::run([&](auto bc) {
+                                constexpr int b = decltype(bc)::value;
+                                cx<T> q = {T(0), T(0)};
+                                OutLoop<py ? 1 : 0, MT + 1>::run([&](auto ac) {
+                                    constexpr int aa = decltype(ac)::value;
+                                    if constexpr (aa * aa + b * b <= MT * MT) {
+                                        const T w = tk[tm.c * NU + yz_tap(MT, aa, b)];
+                                        const cx<T> P = py ? po[aa] : pe[aa];
+                                        q.r += w * P.r;
+                                        q.i += w * P.i;
+                                    }
+                                });
+                                if constexpr (px) q = cx<T>{-q.i, q.r};
+                                if constexpr (tm.ka) q = cscale(q, ka);
+                                if constexpr (fr != 1 && fr != -1) q = cscale(q, T(fr < 0 ? -fr : fr));
+                                // input plane zi reaches output plane zi - b with oz = +b
+                                // and, for b > 0, plane zi + b with oz = -b (sign of pz)
+                                constexpr int sm = (rr - b + R) % R, sp = (rr + b) % R;
+                                if constexpr (fr >= 0) acc[sm][O] = acc[sm][O] + q;
+                                else acc[sm][O] = acc[sm][O] - q;
+                                if constexpr (b > 0) {
+                                    if constexpr ((fr >= 0) != pz) acc[sp][O] = acc[sp][O] + q;
+                                    else acc[sp][O] = acc[sp][O] - q;
+                                }
+                            });
+                        }
+                    });
+                });
+            }
+            // output plane zi - MT has all its inputs
+            constexpr int sd = (rr + MT + 1) % R;
+            const int zo = zi - MT;
+            if (zo >= z0 && yin) {
+#pragma unroll
+                for (int o = 0; o < NO; ++o) dst[o * a.saf + zo * zs] = acc[sd][o];
+            }
+#pragma unroll
+            for (int o = 0; o < NO; ++o) acc[sd][o] = cx<T>{T(0), T(0)};
+        });
+    }
+}
+
+// ----------------------------------------------------------------------------
 // 3D y passes with a transpose, so that the z pass reads contiguous lines.
 //   forward: SA [f][z][kx][y<b2]  --FFT along y-->  SB [f][kx][ky][z<Pz]
 //   inverse: SB [f][kx][ky][z]    --iFFT along y--> SA [f][z][kx][y<b2]

@@ -49,6 +49,8 @@ struct pd_plan_s {
     double* tw64;                // FP64 twiddles, same layout
     void* taps;                  // T [NP][nct][ntap], transform convention
     void* taps_d;                // T [NP][nct][ntap], direct convention
+    void* taps_yz;               // T [h1][nct][yz_nu]: partial x-spectra over the (y, z) quarter disc (3D)
+    int yz_mt, yz_nu;            // its radius in spacings (0: no (y, z) direct pass) and tap count
     void* stat;                  // T [ncs][nb]
     void* stat_int;              // T [ncs]: the static fields at interior nodes
     long n_edge;                 // body-box nodes that are not interior

@@ -117,8 +117,10 @@ def test_lps3d_ragged_voids(orc, dtype):
 
 
 # Lines of 512 points along the last axis (numpy axis 0) with a horizon of 3
-# spacings: the default direct line correlation, the specialised 512-point
-# transform kernel and the runtime-length transform kernel, each against the
+# spacings: the default path (3D: direct (y, z) correlation; 2D: direct line
+# correlation), the y transform with the direct z line correlation, the
+# specialised 512-point transform kernel and the runtime-length transform
+# kernel, each against the
 # oracle (ragged body up to the largest body the padding allows) and against
 # each other on the same plan.
 @pytest.mark.parametrize("dtype", DT)
@@ -140,7 +142,7 @@ def test_specialised_lastaxis_512(orc, dtype, model, body):
         Lo = orc.bb_force(g, orc.bb_alpha(D, 70e9, 3 * dx), chi.astype(float), u)
     _check(L, Lo, u, plan, 2700.0, dtype)
     tol = 1e-13 if dtype == torch.float64 else 1e-5
-    for mode in ("fft", "fft_generic"):
+    for mode in ("fft", "fft_generic", "yfft"):
         plan.set_lastaxis(mode)
         Lg = plan.force(_dev(u, dtype)).cpu().numpy()
         _check(Lg, Lo, u, plan, 2700.0, dtype)
@@ -218,3 +220,36 @@ def test_plan_validation_errors():
     with pytest.raises(binding.PDError) as e:
         binding.Plan((64, 64), (40, 40), 1e-3, 3e-3, model="lps")
     assert e.value.status == binding.PD_EUNSUPPORTED
+
+
+# The direct (y, z) pass (3D default): bodies spanning two y tiles (b2 > 256)
+# and several z chunks with a ragged last one, a narrow body (128-row
+# tiles), horizons of 2 and 3 spacings, LPS and bond-based, against the
+# oracle and against the y transform path on the same plan.  A horizon of
+# 2.5 spacings has a (y, z) footprint beyond the disc of radius 2 and takes
+# the y transform path.
+@pytest.mark.parametrize("dtype", DT)
+@pytest.mark.parametrize("model,body,fft,r", [("lps", (12, 300, 40), (16, 512, 64), 3.0),
+                                              ("bb", (12, 300, 40), (16, 512, 64), 2.0),
+                                              ("lps", (20, 100, 30), (32, 128, 64), 2.0),
+                                              ("bb", (20, 100, 30), (32, 128, 64), 3.0),
+                                              ("lps", (14, 37, 29), (32, 64, 64), 2.5)])
+def test_yz_direct_tiles(orc, dtype, model, body, fft, r):
+    from paper_2105_06055_amd import binding
+    dx = 1e-3
+    chi = wl.random_mask(body, 31)
+    u = wl.random_field((3,) + body, 32, 1e-6)
+    plan = binding.Plan(fft, body, dx, r * dx, model=model, E=70e9, nu=0.3, chiB=chi, dtype=dtype)
+    L = plan.force(_dev(u, dtype)).cpu().numpy()
+    g = orc.geom(body, dx, r * dx)
+    if model == "lps":
+        Lo, _ = orc.lps_force(g, 70e9, 0.3, chi.astype(float), u)
+    else:
+        Lo = orc.bb_force(g, orc.bb_alpha(3, 70e9, r * dx), chi.astype(float), u)
+    _check(L, Lo, u, plan, 2700.0, dtype)
+    plan.set_lastaxis("yfft")
+    Ly = plan.force(_dev(u, dtype)).cpu().numpy()
+    _check(Ly, Lo, u, plan, 2700.0, dtype)
+    tol = 1e-13 if dtype == torch.float64 else 1e-5
+    assert np.linalg.norm(L - Ly) / np.linalg.norm(Lo) <= tol
+    plan.close()
