@@ -322,9 +322,12 @@ def main():
     if not args.no_fp64:
         r64 = run_dynamics(wl, torch.float64, args.steps, args.warmup, with_profile=True)
         log(f"[bench] fp64 step {r64['s_per_step'] * 1e3:.3f} ms, force {r64['s_per_force'] * 1e3:.3f} ms")
-    r32f = None
+    r32f = r32y = None
     if not args.no_fft_variant:
-        # the same step with the transform form along the last axis as well
+        # the same step with the y transform and the direct line correlation
+        # along z, and with transforms on all three axes
+        r32y = run_dynamics(wl, torch.float32, args.steps, args.warmup, with_profile=True, lastaxis="yfft")
+        log(f"[bench] fp32 step, y transform + direct z: {r32y['s_per_step'] * 1e3:.3f} ms")
         r32f = run_dynamics(wl, torch.float32, args.steps, args.warmup, with_profile=True, lastaxis="fft")
         log(f"[bench] fp32 step, FFT on all three axes: {r32f['s_per_step'] * 1e3:.3f} ms")
     passes = r32["passes"]
@@ -391,6 +394,10 @@ def main():
                 "step_Gnode_s": nodes / r64["s_per_step"] / 1e9, "ms_per_step": r64["s_per_step"] * 1e3,
                 "force_Gnode_s": nodes / r64["s_per_force"] / 1e9, "force_ms": r64["s_per_force"] * 1e3,
                 "finite": r64["finite"], "passes": r64["passes"]},
+            "fp32_yfft_zdirect": None if r32y is None else {
+                "step_Gnode_s": nodes / r32y["s_per_step"] / 1e9, "ms_per_step": r32y["s_per_step"] * 1e3,
+                "force_Gnode_s": nodes / r32y["s_per_force"] / 1e9, "force_ms": r32y["s_per_force"] * 1e3,
+                "finite": r32y["finite"], "passes": r32y["passes"]},
             "fp32_fft_all_axes": None if r32f is None else {
                 "step_Gnode_s": nodes / r32f["s_per_step"] / 1e9, "ms_per_step": r32f["s_per_step"] * 1e3,
                 "force_Gnode_s": nodes / r32f["s_per_force"] / 1e9, "force_ms": r32f["s_per_force"] * 1e3,

@@ -760,9 +760,56 @@ __host__ __device__ constexpr int yz_factor(DTerm t) {
     return e == 0 ? t.coef : -t.coef;   // e is 0 or 2 for a real-space kernel
 }
 
+// Whether output O has a term of an input in [J0, J1) whose component has
+// z-parity G.
+template <class M, int O, int G, int J0, int J1>
+__host__ __device__ constexpr bool yz_group_used() {
+    for (int J = J0; J < J1; ++J) {
+        const DTerm t = M::dterm(O, J);
+        if (t.coef != 0 && ((M::par3(t.c) >> 2) & 1) == G) return true;
+    }
+    return false;
+}
+
+// q += (real factor) * i^{p_x} * sum_a tau_c(a, b) P(a): one term at z-offset b,
+// P the y-neighbour sums (component even along y) or differences (odd).
+// C: component (relative to the multiplier's first), PR: its odd axes, FR:
+// the real factor, KA: times k_a.
+template <class T, int MT, int NU, int C, int PR, int FR, bool KA, int b>
+__device__ __forceinline__ void yz_term(cx<T>& q, const T* __restrict__ tk, const cx<T> (&pe)[MT + 1],
+                                        const cx<T> (&po)[MT + 1], T ka) {
+    constexpr bool px = PR & 1, py = (PR >> 1) & 1;
+    constexpr int fr = FR;
+    constexpr bool plain = !KA && (fr == 1 || fr == -1);
+    cx<T> st = {T(0), T(0)};
+    OutLoop<py ? 1 : 0, MT + 1>::run([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        if constexpr (a * a + b * b <= MT * MT) {
+            const T w = tk[C * NU + yz_tap(MT, a, b)];
+            const cx<T> P = py ? po[a] : pe[a];
+            if constexpr (plain) {
+                // straight into q, the sign and the i of an odd x-parity folded in
+                const T sw = fr > 0 ? w : -w;
+                if constexpr (px) { q.r -= sw * P.i; q.i += sw * P.r; }
+                else { q.r += sw * P.r; q.i += sw * P.i; }
+            } else {
+                st.r += w * P.r;
+                st.i += w * P.i;
+            }
+        }
+    });
+    if constexpr (!plain) {
+        T sc = T(fr);
+        if constexpr (KA) sc *= ka;
+        if constexpr (px) { q.r -= sc * st.i; q.i += sc * st.r; }
+        else { q.r += sc * st.r; q.i += sc * st.i; }
+    }
+}
+
 template <class T, class M, int MT, int YT>
 __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const T* __restrict__ taps) {
     constexpr int NI = M::NIN, NO = M::NOUT, R = 2 * MT + 1, W = YT + 2 * MT, NU = yz_ntap(MT);
+    constexpr bool YZ_GROUP = sizeof(T) == 4;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     lds_ptr<cx<T>> lds = as_lds(reinterpret_cast<cx<T>*>(smem_raw));
     // block -> (kx, y tile, z chunk): consecutive chunks of one (kx, tile) on one XCD
@@ -783,6 +830,9 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
     const int yh = hlo ? y0 - MT + tid : y0 + YT + (tid - MT);
     const int ph = hlo ? tid : YT + tid;
     const bool hin = hthr && yh >= 0 && yh < a.b2;
+    // block-uniform: a neighbouring tile exists (else the halo rows are zero,
+    // written once below)
+    const bool halo = a.nyt > 1;
     const int z0 = zc * a.zc, z1 = min(a.b3, z0 + a.zc);
     const T* __restrict__ tk = taps + ((long)kx * a.nct + M::C0) * NU;   // block-uniform
     const T ka = mul.ka_value();
@@ -796,16 +846,33 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
 #pragma unroll
         for (int o = 0; o < NO; ++o) acc[r][o] = cx<T>{T(0), T(0)};
     cx<T> nv[NI], nh[NI];   // inputs of the next plane (row y, halo row yh)
+#pragma unroll
+    for (int J = 0; J < NI; ++J) nv[J] = nh[J] = cx<T>{T(0), T(0)};
+    // straight-line loads: the plane index is clamped into the body (planes
+    // outside it are never used) and rows beyond the body read row 0 and are
+    // replaced by zeros
+    const int yl = yin ? y : 0;
     auto load = [&](int z) {
-        const bool zin = z >= 0 && z < a.b3;
+        const cx<T>* __restrict__ sp = src + min(max(z, 0), a.b3 - 1) * zs;
 #pragma unroll
         for (int J = 0; J < NI; ++J) {
-            nv[J] = cx<T>{T(0), T(0)};
-            nh[J] = cx<T>{T(0), T(0)};
-            if (zin && yin) nv[J] = src[J * a.saf + z * zs + y];
-            if (zin && hin) nh[J] = src[J * a.saf + z * zs + yh];
+            const cx<T> v = sp[J * a.saf + yl];
+            nv[J] = yin ? v : cx<T>{T(0), T(0)};
+        }
+        if (halo) {
+#pragma unroll
+            for (int J = 0; J < NI; ++J) {
+                nh[J] = cx<T>{T(0), T(0)};
+                if (hin) nh[J] = sp[J * a.saf + yh];
+            }
         }
     };
+    // halo rows of both buffers start at zero (the only value they keep
+    // when the tile has no neighbour on that side)
+    if (hthr) {
+#pragma unroll
+        for (int J = 0; J < 2 * NI; ++J) lds[J * W + ph] = cx<T>{T(0), T(0)};
+    }
 
     const int zb = z0 - MT;               // first input plane of the sweep
     const int nst = (z1 - z0) + 2 * MT;   // input planes swept
@@ -818,23 +885,55 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
             const int zi = zb + s;
             const bool act = zi >= 0 && zi < a.b3;   // block-uniform
             lds_ptr<cx<T>> row = lds + (s & 1) * (NI * W);
-            cx<T> cv[NI];
             if (act) {
 #pragma unroll
-                for (int J = 0; J < NI; ++J) {
-                    cv[J] = nv[J];
-                    row[J * W + MT + tid] = nv[J];
-                    if (hthr) row[J * W + ph] = nh[J];
+                for (int J = 0; J < NI; ++J) row[J * W + MT + tid] = nv[J];
+                if (halo) {
+                    if (hthr) {
+#pragma unroll
+                        for (int J = 0; J < NI; ++J) row[J * W + ph] = nh[J];
+                    }
                 }
                 __syncthreads();
             }
             load(zi + 1);
             if (act) {
-                OutLoop<0, NI>::run([&](auto Jc) {
-                    constexpr int J = decltype(Jc)::value;
-                    // y-neighbour sums (pe) and differences (po) at this row
-                    cx<T> pe[MT + 1], po[MT + 1];
-                    pe[0] = cv[J];
+                // per output, the terms even (G = 0) and odd (G = 1) along z of
+                // inputs J0 .. J1-1 summed, then added to the planes they reach
+                auto terms = [&](auto j0c, auto j1c, const cx<T>(*pe)[MT + 1], const cx<T>(*po)[MT + 1]) {
+                    constexpr int J0 = decltype(j0c)::value, J1 = decltype(j1c)::value;
+                    OutLoop<0, NO>::run([&](auto Oc) {
+                        constexpr int O = decltype(Oc)::value;
+                        OutLoop<0, 2>::run([&](auto Gc) {
+                            constexpr int G = decltype(Gc)::value;
+                            if constexpr (yz_group_used<M, O, G, J0, J1>()) {
+                                OutLoop<G, MT + 1>::run([&](auto bc) {
+                                    constexpr int b = decltype(bc)::value;
+                                    cx<T> q = {T(0), T(0)};
+                                    OutLoop<J0, J1>::run([&](auto Jc) {
+                                        constexpr int J = decltype(Jc)::value;
+                                        constexpr DTerm tm = M::dterm(O, J);
+                                        if constexpr (tm.coef != 0 && ((M::par3(tm.c) >> 2) & 1) == G) {
+                                            yz_term<T, MT, NU, tm.c, M::par3(tm.c), yz_factor<M>(tm), tm.ka, b>(
+                                                q, tk, pe[J - J0], po[J - J0], ka);
+                                        }
+                                    });
+                                    // input plane zi reaches output plane zi - b with oz = +b
+                                    // and, for b > 0, plane zi + b with oz = -b (sign (-1)^G)
+                                    constexpr int sm = (rr - b + R) % R, sp = (rr + b) % R;
+                                    acc[sm][O] = acc[sm][O] + q;
+                                    if constexpr (b > 0) {
+                                        if constexpr (G == 0) acc[sp][O] = acc[sp][O] + q;
+                                        else acc[sp][O] = acc[sp][O] - q;
+                                    }
+                                });
+                            }
+                        });
+                    });
+                };
+                // y-neighbour sums (pe) and differences (po) at this row
+                auto nbr = [&](int J, cx<T>(&pe)[MT + 1], cx<T>(&po)[MT + 1]) {
+                    pe[0] = row[J * W + MT + tid];
                     po[0] = cx<T>{T(0), T(0)};
 #pragma unroll
                     for (int t = 1; t <= MT; ++t) {
@@ -842,41 +941,22 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
                         pe[t] = up + dn;
                         po[t] = up - dn;
                     }
-                    OutLoop<0, NO>::run([&](auto Oc) {
-                        constexpr int O = decltype(Oc)::value;
-                        constexpr DTerm tm = M::dterm(O, J);
-                        if constexpr (tm.coef != 0) {
-                            constexpr int pr = M::par3(tm.c);
-                            constexpr bool px = pr & 1, py = (pr >> 1) & 1, pz = (pr >> 2) & 1;
-                            constexpr int fr = yz_factor<M>(tm);
-                            OutLoop<pz ? 1 : 0, MT + 1>::run([&](auto bc) {
-                                constexpr int b = decltype(bc)::value;
-                                cx<T> q = {T(0), T(0)};
-                                OutLoop<py ? 1 : 0, MT + 1>::run([&](auto ac) {
-                                    constexpr int aa = decltype(ac)::value;
-                                    if constexpr (aa * aa + b * b <= MT * MT) {
-                                        const T w = tk[tm.c * NU + yz_tap(MT, aa, b)];
-                                        const cx<T> P = py ? po[aa] : pe[aa];
-                                        q.r += w * P.r;
-                                        q.i += w * P.i;
-                                    }
-                                });
-                                if constexpr (px) q = cx<T>{-q.i, q.r};
-                                if constexpr (tm.ka) q = cscale(q, ka);
-                                if constexpr (fr != 1 && fr != -1) q = cscale(q, T(fr < 0 ? -fr : fr));
-                                // input plane zi reaches output plane zi - b with oz = +b
-                                // and, for b > 0, plane zi + b with oz = -b (sign of pz)
-                                constexpr int sm = (rr - b + R) % R, sp = (rr + b) % R;
-                                if constexpr (fr >= 0) acc[sm][O] = acc[sm][O] + q;
-                                else acc[sm][O] = acc[sm][O] - q;
-                                if constexpr (b > 0) {
-                                    if constexpr ((fr >= 0) != pz) acc[sp][O] = acc[sp][O] + q;
-                                    else acc[sp][O] = acc[sp][O] - q;
-                                }
-                            });
-                        }
+                };
+                if constexpr (YZ_GROUP) {
+                    // FP32: all inputs at once, one scatter per (output, parity, offset)
+                    cx<T> pe[NI][MT + 1], po[NI][MT + 1];
+#pragma unroll
+                    for (int J = 0; J < NI; ++J) nbr(J, pe[J], po[J]);
+                    terms(std::integral_constant<int, 0>{}, std::integral_constant<int, NI>{}, pe, po);
+                } else {
+                    // FP64: one input at a time (half the registers of the sums)
+                    OutLoop<0, NI>::run([&](auto Jc) {
+                        constexpr int J = decltype(Jc)::value;
+                        cx<T> pe[1][MT + 1], po[1][MT + 1];
+                        nbr(J, pe[0], po[0]);
+                        terms(std::integral_constant<int, J>{}, std::integral_constant<int, J + 1>{}, pe, po);
                     });
-                });
+                }
             }
             // output plane zi - MT has all its inputs
             constexpr int sd = (rr + MT + 1) % R;
