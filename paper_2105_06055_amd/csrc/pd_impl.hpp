@@ -184,6 +184,7 @@ NodeCtx<T> ctx(pd_plan p) {
     c.chiO = p->chiO;
     c.stat = reinterpret_cast<const T*>(p->stat);
     c.stat_int = reinterpret_cast<const T*>(p->stat_int);
+    for (int q = 0; q < 10; ++q) c.sint[q] = T(q < p->ncs ? p->stat_int_h[q] : 0.0);
     c.edge_frac = p->nb > 0 ? (double)p->n_edge / (double)p->nb : 0.0;
     return c;
 }
@@ -815,6 +816,7 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
             double acc = 0.0;
             for (int s = 0; s < ns; ++s) acc += kv[(size_t)s * ncs + c];
             si[(size_t)c] = T(acc);
+            if (c < 10) p->stat_int_h[c] = (double)si[(size_t)c];
         }
         HIP_TRY(hipMalloc(&p->stat_int, sizeof(T) * ncs));
         HIP_TRY(hipMemcpy(p->stat_int, si.data(), sizeof(T) * ncs, hipMemcpyHostToDevice));

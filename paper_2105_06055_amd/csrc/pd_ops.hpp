@@ -42,19 +42,70 @@ enum { WK_NONE = 0, WK_LAMBDA = 1, WK_SCALE = 2 };
 // read from that small cached table instead of the per-node arrays.  The
 // passes load chiB[i] ahead of the node's other loads and hand it to the
 // generators' and epilogues' load steps.
+// Node index of the x passes, split into a block-uniform part (the start of
+// the block's run of body nodes) and a small per-thread part, so that every
+// field access is a uniform base plus a 32-bit offset: the addressing mode
+// with the base in scalar registers, instead of a 64-bit address per thread
+// and field.
+struct Nd {
+    long base;      // block-uniform
+    uint32_t off;   // per thread, < 2^20
+};
+// A block-uniform address, taken through readfirstlane so that it stays a
+// scalar base (otherwise the compiler folds it into one 64-bit per-thread
+// offset), as a global-memory pointer.
+__device__ __forceinline__ __attribute__((address_space(1))) char* uniform_base(const void* p) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return reinterpret_cast<__attribute__((address_space(1))) char*>(((uintptr_t)hi << 32) | lo);
+}
+// load / store of field p at node n
+template <class T>
+__device__ __forceinline__ T ldf(const T* p, Nd n) {
+    auto b = uniform_base(p + n.base) + n.off * (uint32_t)sizeof(T);
+    return *reinterpret_cast<const __attribute__((address_space(1))) T*>(b);
+}
+template <class T>
+struct ident { using type = T; };
+template <class T>
+__device__ __forceinline__ void stf(T* p, Nd n, typename ident<T>::type v) {
+    auto b = uniform_base(p + n.base) + n.off * (uint32_t)sizeof(T);
+    *reinterpret_cast<__attribute__((address_space(1))) T*>(b) = v;
+}
+// address of field p at node n (for address selects)
+template <class T>
+__device__ __forceinline__ const T* adf(const T* p, Nd n) {
+    return p + n.base + n.off;
+}
+
 template <class T>
 struct NodeCtx {
     long nb;                   // body nodes
     const uint8_t* chiB;       // [nb] body | interior << 1
     const uint8_t* chiO;       // [D][nb]
     const T* stat;             // static fields [ncs][nb]
-    const T* stat_int;         // [ncs] values at interior nodes
+    const T* stat_int;         // [ncs] values at interior nodes (device copy)
+    T sint[10];                // the same values, as kernel arguments
     double edge_frac;          // host bookkeeping: fraction of body-box nodes that
                                // read per-node static fields (not interior)
-    // static field q at node i with flags cb (a select of addresses, no branch)
-    __device__ __forceinline__ T st(int q, long i, uint8_t cb) const {
-        const T* a = (cb & 2) ? stat_int + q : stat + (long)q * nb + i;
+    // static field q (runtime index) at node i with flags cb (a select of
+    // addresses, no branch)
+    __device__ __forceinline__ T st(int q, Nd i, uint8_t cb) const {
+        const T* a = (cb & 2) ? stat_int + q : adf(stat + (long)q * nb, i);
         return *a;
+    }
+    // static fields Q0 .. Q0+N-1 at node i: the interior values at interior
+    // nodes (no memory access), the per-node arrays at the others, loaded
+    // under a branch that waves without edge nodes skip
+    template <int Q0, int N>
+    __device__ __forceinline__ void st_range(Nd i, uint8_t cb, T* out) const {
+#pragma unroll
+        for (int k = 0; k < N; ++k) out[k] = sint[Q0 + k];
+        if (!(cb & 2)) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) out[k] = ldf(stat + (long)(Q0 + k) * nb, i);
+        }
     }
 };
 
@@ -101,33 +152,33 @@ struct GenU {
         uint8_t chiB, lam;
         T s, W;
     };
-    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
+    __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const {
         Ld L;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            const long k = d * c.nb + i;
-            L.u[d] = u[k];
+            const long k = d * c.nb;
+            L.u[d] = ldf(u + k, i);
             if constexpr (VV) {
-                L.v[d] = v[k];
-                L.F[d] = F[k];
-                L.w[d] = (w ? w : u)[k];
-                L.o[d] = c.chiO[k];
+                L.v[d] = ldf(v + k, i);
+                L.F[d] = ldf(F + k, i);
+                L.w[d] = ldf((w ? w : u) + k, i);
+                L.o[d] = ldf(c.chiO + k, i);
             }
         }
         L.chiB = cb;
-        L.lam = (WK == WK_LAMBDA) ? lam_in[i] : uint8_t(1);
-        L.s = (WK == WK_SCALE) ? s[i] : T(1);
-        L.W = (VV && WK == WK_LAMBDA) ? W[i] : T(0);
+        L.lam = (WK == WK_LAMBDA) ? ldf(lam_in, i) : uint8_t(1);
+        L.s = (WK == WK_SCALE) ? ldf(s, i) : T(1);
+        L.W = (VV && WK == WK_LAMBDA) ? ldf(W, i) : T(0);
         return L;
     }
-    __device__ __forceinline__ void gen(long i, const Ld& L, T (&in)[NIN]) const {
+    __device__ __forceinline__ void gen(Nd i, const Ld& L, T (&in)[NIN]) const {
         T ud[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             T x = L.u[d];
             if constexpr (VV) {
                 x = L.o[d] ? x + dt * L.v[d] + c2 * L.F[d] : (w ? L.w[d] : T(0));
-                u[d * c.nb + i] = x;
+                stf(u + d * c.nb, i, x);
             }
             ud[d] = x;
         }
@@ -136,7 +187,7 @@ struct GenU {
             const uint8_t keep = (l != 0 && L.W <= Wc) ? 1 : 0;
             if (fail) {
                 l = keep;
-                lam_out[i] = l;
+                stf(lam_out, i, l);
             }
         }
         T phi = (L.chiB && l) ? T(1) : T(0);
@@ -162,8 +213,8 @@ struct GenTheta {
     const T* theta;
     __host__ double nbytes() const { return sizeof(T) + 1.0; }
     struct Ld { T th; uint8_t chiB; };
-    __device__ __forceinline__ Ld load(long i, uint8_t cb) const { return {theta[i], cb}; }
-    __device__ __forceinline__ void gen(long, const Ld& L, T (&in)[1]) const { in[0] = L.chiB ? L.th : T(0); }
+    __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const { return {ldf(theta, i), cb}; }
+    __device__ __forceinline__ void gen(Nd, const Ld& L, T (&in)[1]) const { in[0] = L.chiB ? L.th : T(0); }
 };
 
 // Damage count input: chi_B lambda.
@@ -174,8 +225,8 @@ struct GenPhi {
     const uint8_t* lam;
     __host__ double nbytes() const { return 2.0; }
     struct Ld { uint8_t chiB, lam; };
-    __device__ __forceinline__ Ld load(long i, uint8_t cb) const { return {cb, lam[i]}; }
-    __device__ __forceinline__ void gen(long, const Ld& L, T (&in)[1]) const {
+    __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const { return {cb, ldf(lam, i)}; }
+    __device__ __forceinline__ void gen(Nd, const Ld& L, T (&in)[1]) const {
         in[0] = (L.chiB && L.lam) ? T(1) : T(0);
     }
 };
@@ -192,20 +243,20 @@ struct GenAdj {
         return (2 * D + (u2 ? D : 0)) * t + 1 + (WK == WK_SCALE ? t : 0.0) + (WK == WK_LAMBDA ? 1.0 : 0.0);
     }
     struct Ld { T u[D], u2[D], g[D]; uint8_t chiB, lam; T s; };
-    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
+    __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const {
         Ld L;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            L.u[d] = u[d * c.nb + i];
-            L.u2[d] = (u2 ? u2 : u)[d * c.nb + i];
-            L.g[d] = g[d * c.nb + i];
+            L.u[d] = ldf(u + d * c.nb, i);
+            L.u2[d] = ldf((u2 ? u2 : u) + d * c.nb, i);
+            L.g[d] = ldf(g + d * c.nb, i);
         }
         L.chiB = cb;
-        L.lam = (WK == WK_LAMBDA) ? lam[i] : uint8_t(1);
-        L.s = (WK == WK_SCALE) ? s[i] : T(1);
+        L.lam = (WK == WK_LAMBDA) ? ldf(lam, i) : uint8_t(1);
+        L.s = (WK == WK_SCALE) ? ldf(s, i) : T(1);
         return L;
     }
-    __device__ __forceinline__ void gen(long, const Ld& L, T (&in)[NIN]) const {
+    __device__ __forceinline__ void gen(Nd, const Ld& L, T (&in)[NIN]) const {
         T phi = (L.chiB && L.lam) ? T(1) : T(0);
         if constexpr (WK == WK_SCALE) phi *= L.s;
         T ud[D], gd[D];
@@ -231,11 +282,11 @@ template <class T>
 struct GenScalar {
     static constexpr int NIN = 1;
     const T* x;
-    __device__ __forceinline__ uint8_t flags(long) const { return 0; }
+    __device__ __forceinline__ uint8_t flags(Nd) const { return 0; }
     __host__ double nbytes() const { return sizeof(T); }
     struct Ld { T x; };
-    __device__ __forceinline__ Ld load(long i, uint8_t cb) const { return {x[i]}; }
-    __device__ __forceinline__ void gen(long, const Ld& L, T (&in)[1]) const { in[0] = L.x; }
+    __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const { return {ldf(x, i)}; }
+    __device__ __forceinline__ void gen(Nd, const Ld& L, T (&in)[1]) const { in[0] = L.x; }
 };
 
 // ============================================================================
@@ -589,16 +640,16 @@ struct GenMasked {
     const TR* r;
     __host__ double nbytes() const { return D * (sizeof(TR) + 1.0); }
     struct Ld { TR r[D]; uint8_t o[D]; };
-    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
+    __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const {
         Ld L;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            L.r[d] = r[d * c.nb + i];
-            L.o[d] = c.chiO[d * c.nb + i];
+            L.r[d] = ldf(r + d * c.nb, i);
+            L.o[d] = ldf(c.chiO + d * c.nb, i);
         }
         return L;
     }
-    __device__ __forceinline__ void gen(long, const Ld& L, T (&in)[D]) const {
+    __device__ __forceinline__ void gen(Nd, const Ld& L, T (&in)[D]) const {
 #pragma unroll
         for (int d = 0; d < D; ++d) in[d] = L.o[d] ? T(L.r[d]) : T(0);
     }
@@ -662,30 +713,30 @@ struct FinBB {
         uint8_t chiB, lam;
         T s;
     };
-    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
+    __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const {
         Ld Q;
 #pragma unroll
-        for (int d = 0; d < D; ++d) Q.u[d] = u[d * c.nb + i];
-        if constexpr (!WPHI) {
-#pragma unroll
-            for (int q = 0; q < nsym(D); ++q) Q.G[q] = c.st(q, i, cb);
-        }
+        for (int d = 0; d < D; ++d) Q.u[d] = ldf(u + d * c.nb, i);
+        if constexpr (!WPHI) c.template st_range<0, nsym(D)>(i, cb, Q.G);
         if constexpr (VV) {
 #pragma unroll
             for (int d = 0; d < D; ++d) {
-                const long k = d * c.nb + i;
-                Q.v[d] = v[k];
-                Q.F[d] = F[k];
-                Q.b[d] = (b ? b : F)[k];
-                Q.o[d] = c.chiO[k];
+                const long k = d * c.nb;
+                Q.v[d] = ldf(v + k, i);
+                Q.F[d] = ldf(F + k, i);
+                Q.o[d] = ldf(c.chiO + k, i);
+            }
+            if (b) {   // kernel-uniform
+#pragma unroll
+                for (int d = 0; d < D; ++d) Q.b[d] = ldf(b + d * c.nb, i);
             }
         }
         Q.chiB = cb;
-        Q.lam = (WK == WK_LAMBDA) ? lam[i] : uint8_t(1);
-        Q.s = (WK == WK_SCALE) ? s[i] : T(1);
+        Q.lam = (WK == WK_LAMBDA) ? ldf(lam, i) : uint8_t(1);
+        Q.s = (WK == WK_SCALE) ? ldf(s, i) : T(1);
         return Q;
     }
-    __device__ __forceinline__ void fin(long i, const Ld& Q, const T (&val)[NOUT], double* red) const {
+    __device__ __forceinline__ void fin(Nd i, const Ld& Q, const T (&val)[NOUT], double* red) const {
         T phi = (Q.chiB && Q.lam) ? T(1) : T(0);
         if constexpr (WK == WK_SCALE) phi *= Q.s;
         T Gm[nsym(D)];
@@ -707,17 +758,17 @@ struct FinBB {
 #pragma unroll
                 for (int bb = 0; bb < D; ++bb) e += Q.u[a] * Q.u[bb] * Gm[symi(D, a, bb)];
             }
-            Wout[i] = T(0.5) * phi * e;
+            stf(Wout, i, T(0.5) * phi * e);
         }
         if constexpr (VV) {
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                const long k = a * c.nb + i;
+                const long k = a * c.nb;
                 const T bk = b ? Q.b[a] : T(0);
                 T Fn = Li[a] + bk;
                 T vn = Q.o[a] ? Q.v[a] + c1 * (Q.F[a] + Fn) : T(0);
-                v[k] = vn;
-                F[k] = Fn;
+                stf(v + k, i, vn);
+                stf(F + k, i, Fn);
                 if constexpr (ENRED) {
                     red[0] += 0.5 * double(rho) * double(vn) * double(vn);
                     red[1] += -0.5 * double(Q.u[a]) * double(Li[a]);
@@ -727,7 +778,7 @@ struct FinBB {
             }
         } else {
 #pragma unroll
-            for (int a = 0; a < D; ++a) L[a * c.nb + i] = Li[a];
+            for (int a = 0; a < D; ++a) stf(L + a * c.nb, i, Li[a]);
         }
     }
 };
@@ -741,23 +792,25 @@ struct FinTheta {
     const T* u; T* theta;
     __host__ double nbytes() const { return 4.0 * sizeof(T) + 4.0 * sizeof(T) * c.edge_frac + 1.0; }
     struct Ld { T m, g[3], u[3]; uint8_t chiB; };
-    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
+    __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const {
         Ld Q;
-        Q.m = c.st(9, i, cb);
+        T st[4];
+        c.template st_range<6, 4>(i, cb, st);
+        Q.m = st[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            Q.g[d] = c.st(6 + d, i, cb);
-            Q.u[d] = u[d * c.nb + i];
+            Q.g[d] = st[d];
+            Q.u[d] = ldf(u + d * c.nb, i);
         }
         Q.chiB = cb;
         return Q;
     }
-    __device__ __forceinline__ void fin(long i, const Ld& Q, const T (&val)[1], double*) const {
+    __device__ __forceinline__ void fin(Nd i, const Ld& Q, const T (&val)[1], double*) const {
         T acc = val[0];
 #pragma unroll
         for (int d = 0; d < 3; ++d) acc -= Q.g[d] * Q.u[d];
         const bool on = Q.chiB && Q.m != T(0);
-        theta[i] = on ? T(3) / (on ? Q.m : T(1)) * acc : T(0);
+        stf(theta, i, on ? T(3) / (on ? Q.m : T(1)) * acc : T(0));
     }
 };
 
@@ -792,33 +845,43 @@ struct FinLin {
         uint8_t o[HAS_O ? D : 1];
         uint8_t chiB;
     };
-    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
+    __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const {
         Ld Q;
         Q.chiB = cb;
 #pragma unroll
-        for (int d = 0; d < D; ++d) Q.u[d] = u[d * c.nb + i];
-#pragma unroll
-        for (int q = 0; q < nsym(D); ++q) Q.G[q] = c.st(q, i, cb);
-        Q.th = T(0);
+        for (int d = 0; d < D; ++d) Q.u[d] = ldf(u + d * c.nb, i);
         if constexpr (LPS) {
-            Q.th = theta[i];
+            // G_ij and g_i are consecutive static fields 0 .. 8
+            T st[nsym(D) + D];
+            c.template st_range<0, nsym(D) + D>(i, cb, st);
 #pragma unroll
-            for (int d = 0; d < D; ++d) Q.g[d] = c.st(6 + d, i, cb);
+            for (int q = 0; q < nsym(D); ++q) Q.G[q] = st[q];
+#pragma unroll
+            for (int d = 0; d < D; ++d) Q.g[d] = st[nsym(D) + d];
+            Q.th = ldf(theta, i);
+        } else {
+            c.template st_range<0, nsym(D)>(i, cb, Q.G);
+            Q.th = T(0);
         }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            const long k = d * c.nb + i;
-            if constexpr (HAS_O) Q.o[d] = c.chiO[k];
+            const long k = d * c.nb;
+            if constexpr (HAS_O) Q.o[d] = ldf(c.chiO + k, i);
             if constexpr (MODE == 1) {
-                Q.v[d] = v[k];
-                Q.F[d] = F[k];
-                Q.b[d] = (b ? b : F)[k];
+                Q.v[d] = ldf(v + k, i);
+                Q.F[d] = ldf(F + k, i);
             }
-            if constexpr (MODE == 3) Q.b[d] = b[k];
+            if constexpr (MODE == 3) Q.b[d] = ldf(b + k, i);
+        }
+        if constexpr (MODE == 1) {
+            if (b) {   // kernel-uniform
+#pragma unroll
+                for (int d = 0; d < D; ++d) Q.b[d] = ldf(b + d * c.nb, i);
+            }
         }
         return Q;
     }
-    __device__ __forceinline__ void fin(long i, const Ld& Q, const T (&val)[D], double* red) const {
+    __device__ __forceinline__ void fin(Nd i, const Ld& Q, const T (&val)[D], double* red) const {
         const T chi = Q.chiB ? T(1) : T(0);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -827,15 +890,15 @@ struct FinLin {
             for (int bb = 0; bb < D; ++bb) acc -= Q.G[symi(D, a, bb)] * Q.u[bb];
             if constexpr (LPS) acc += ka * Q.th * Q.g[a];
             T La = chi * acc;
-            const long k = a * c.nb + i;
+            const long k = a * c.nb;
             if constexpr (MODE == 0) {
-                L[k] = La;
+                stf(L + k, i, La);
             } else if constexpr (MODE == 1) {
                 const T bk = b ? Q.b[a] : T(0);
                 T Fn = La + bk;
                 T vn = Q.o[a] ? Q.v[a] + c1 * (Q.F[a] + Fn) : T(0);
-                v[k] = vn;
-                F[k] = Fn;
+                stf(v + k, i, vn);
+                stf(F + k, i, Fn);
                 if constexpr (ENRED) {
                     red[0] += 0.5 * double(rho) * double(vn) * double(vn);
                     red[1] += -0.5 * double(Q.u[a]) * double(La);
@@ -844,11 +907,11 @@ struct FinLin {
                 }
             } else if constexpr (MODE == 2) {
                 T ap = Q.o[a] ? -La : T(0);
-                L[k] = ap;
+                stf(L + k, i, ap);
                 red[0] += double(Q.u[a]) * double(ap);
             } else {
                 T r = Q.o[a] ? La + Q.b[a] : T(0);
-                L[k] = r;
+                stf(L + k, i, r);
                 red[0] += double(r) * double(r);
             }
         }
@@ -865,12 +928,12 @@ struct FinCount {
     const uint8_t* lam; T* d;
     __host__ double nbytes() const { return 2.0 + sizeof(T) + sizeof(T) * c.edge_frac; }
     struct Ld { T st; uint8_t chiB, lam; };
-    __device__ __forceinline__ Ld load(long i, uint8_t cb) const { return {c.st(beta_comp, i, cb), cb, lam[i]}; }
-    __device__ __forceinline__ void fin(long i, const Ld& Q, const T (&val)[1], double*) const {
+    __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const { return {c.st(beta_comp, i, cb), cb, ldf(lam, i)}; }
+    __device__ __forceinline__ void fin(Nd i, const Ld& Q, const T (&val)[1], double*) const {
         int phi = (Q.chiB && Q.lam) ? 1 : 0;
         long cnt = (long)rint(val[0]) + phi;
         long beta = (long)rint(Q.st) + (Q.chiB ? 1 : 0);
-        d[i] = Q.chiB ? T(1.0 - double(phi * cnt) / double(beta > 0 ? beta : 1)) : T(0);
+        stf(d, i, Q.chiB ? T(1.0 - double(phi * cnt) / double(beta > 0 ? beta : 1)) : T(0));
     }
 };
 
@@ -893,21 +956,21 @@ struct FinAdj {
                (wbar ? (accumulate ? 2 : 1) * t : 0.0);
     }
     struct Ld { T u[D], u2[D], g[D]; uint8_t chiB, lam; T s, wb; };
-    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
+    __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const {
         Ld Q;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            Q.u[d] = u[d * c.nb + i];
-            Q.u2[d] = (u2 ? u2 : u)[d * c.nb + i];
-            Q.g[d] = g[d * c.nb + i];
+            Q.u[d] = ldf(u + d * c.nb, i);
+            Q.u2[d] = ldf((u2 ? u2 : u) + d * c.nb, i);
+            Q.g[d] = ldf(g + d * c.nb, i);
         }
         Q.chiB = cb;
-        Q.lam = (WK == WK_LAMBDA) ? lam[i] : uint8_t(1);
-        Q.s = (WK == WK_SCALE) ? s[i] : T(1);
-        Q.wb = (wbar && accumulate) ? wbar[i] : T(0);
+        Q.lam = (WK == WK_LAMBDA) ? ldf(lam, i) : uint8_t(1);
+        Q.s = (WK == WK_SCALE) ? ldf(s, i) : T(1);
+        Q.wb = (wbar && accumulate) ? ldf(wbar, i) : T(0);
         return Q;
     }
-    __device__ __forceinline__ void fin(long i, const Ld& Q, const T (&val)[NOUT], double*) const {
+    __device__ __forceinline__ void fin(Nd i, const Ld& Q, const T (&val)[NOUT], double*) const {
         T phi = (Q.chiB && Q.lam) ? T(1) : T(0);
         if constexpr (WK == WK_SCALE) phi *= Q.s;
         T ud[D], gd[D];
@@ -927,12 +990,12 @@ struct FinAdj {
                 acc_u -= Gab * gd[bb];
                 acc_c -= Gab * ud[bb];
             }
-            if (ubar) ubar[a * c.nb + i] = phi * acc_u;
+            if (ubar) stf(ubar + a * c.nb, i, phi * acc_u);
             pb += gd[a] * acc_c + ud[a] * val[D + nsym(D) + a];
         }
         if (wbar) {
             T add = Q.chiB ? wscale * pb : T(0);
-            wbar[i] = accumulate ? Q.wb + add : add;
+            stf(wbar, i, accumulate ? Q.wb + add : add);
         }
     }
 };
@@ -947,20 +1010,20 @@ struct FinPre {
     TZ* z;
     __host__ double nbytes() const { return D * (sizeof(TR) + sizeof(TZ) + 1.0); }
     struct Ld { TR r[D]; uint8_t o[D]; };
-    __device__ __forceinline__ Ld load(long i, uint8_t cb) const {
+    __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const {
         Ld Q;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            Q.r[d] = r[d * c.nb + i];
-            Q.o[d] = c.chiO[d * c.nb + i];
+            Q.r[d] = ldf(r + d * c.nb, i);
+            Q.o[d] = ldf(c.chiO + d * c.nb, i);
         }
         return Q;
     }
-    __device__ __forceinline__ void fin(long i, const Ld& Q, const T (&val)[D], double* red) const {
+    __device__ __forceinline__ void fin(Nd i, const Ld& Q, const T (&val)[D], double* red) const {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             const TZ zd = Q.o[d] ? TZ(val[d]) : TZ(0);
-            z[d * c.nb + i] = zd;
+            stf(z + d * c.nb, i, zd);
             red[0] += double(Q.r[d]) * double(zd);
         }
     }
@@ -971,11 +1034,11 @@ template <class T>
 struct FinScalar {
     static constexpr int NOUT = 1, NRED = 0;
     T* out;
-    __device__ __forceinline__ uint8_t flags(long) const { return 0; }
+    __device__ __forceinline__ uint8_t flags(Nd) const { return 0; }
     __host__ double nbytes() const { return sizeof(T); }
     struct Ld {};
-    __device__ __forceinline__ Ld load(long, uint8_t) const { return {}; }
-    __device__ __forceinline__ void fin(long i, const Ld&, const T (&val)[1], double*) const { out[i] = val[0]; }
+    __device__ __forceinline__ Ld load(Nd, uint8_t) const { return {}; }
+    __device__ __forceinline__ void fin(Nd i, const Ld&, const T (&val)[1], double*) const { stf(out, i, val[0]); }
 };
 
 }  // namespace pdk

@@ -42,8 +42,11 @@ __host__ __device__ constexpr int line_pitch(int N) { return (fft_lds_len(N) + 1
 template <class T>
 __host__ __device__ constexpr int xblock_threads() { return sizeof(T) == 4 ? 512 : 256; }
 
-// Body nodes whose loads the x passes issue together (see k_xfwd).
-constexpr int NODE_GROUP = 4;
+// Body nodes whose loads the x passes issue together (see k_xfwd): four,
+// and two in the FP64 c2r pass (the epilogues' loads of four FP64 nodes do
+// not fit in the registers of two waves per SIMD).
+template <class T>
+__host__ __device__ constexpr int node_group() { return sizeof(T) == 4 ? 4 : 2; }
 
 // Node flags (body | interior << 1) of node i for a generator or epilogue:
 // from its node context where it has one.
@@ -52,8 +55,8 @@ struct has_ctx : std::false_type {};
 template <class G>
 struct has_ctx<G, std::void_t<decltype(std::declval<G>().c.chiB)>> : std::true_type {};
 template <class G>
-__device__ __forceinline__ uint8_t node_flags(const G& g, long i) {
-    if constexpr (has_ctx<G>::value) return g.c.chiB[i];
+__device__ __forceinline__ uint8_t node_flags(const G& g, Nd i) {
+    if constexpr (has_ctx<G>::value) return ldf(g.c.chiB, i);
     else return g.flags(i);
 }
 
@@ -102,7 +105,7 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
                                                const cx<T>* __restrict__ twb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-    constexpr int NF = G::NIN;
+    constexpr int NF = G::NIN, NG = 4;
     const int lgNc = LG > 0 ? LG : 31 - __clz(g.Nc), Nc = 1 << lgNc, Tc = Nc >> 3;
     const int nthr = LG > 0 ? xblock_threads<T>() : (int)blockDim.x;
     const int Lt = nthr / Tc;
@@ -123,7 +126,7 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
     const long nbase = ((long)z * g.b2 + y0) * g.b1;
     const int nval = min(Lt, g.b2 - y0) * g.b1;
     T gv[NF][RN];
-    // Node slots in groups of NODE_GROUP: all loads of a group are issued
+    // Node slots in groups of NG: all loads of a group are issued
     // before its first store (a store may alias any later load, so a
     // read-modify-write generator would otherwise wait out one memory latency
     // per slot).  A full block takes a branch-free path.
@@ -132,23 +135,23 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
 #pragma unroll
         for (int r = 0; r < RN; ++r) {
             const int e = tid + nthr * r;
-            cbv[r] = (decltype(full)::value || e < nval) ? node_flags(gen, nbase + e) : uint8_t(0);
+            cbv[r] = (decltype(full)::value || e < nval) ? node_flags(gen, Nd{nbase, (uint32_t)e}) : uint8_t(0);
         }
 #pragma unroll
-        for (int r0 = 0; r0 < RN; r0 += NODE_GROUP) {
-            typename G::Ld ld[NODE_GROUP];
+        for (int r0 = 0; r0 < RN; r0 += NG) {
+            typename G::Ld ld[NG];
 #pragma unroll
-            for (int q = 0; q < NODE_GROUP; ++q) {
+            for (int q = 0; q < NG; ++q) {
                 const int e = tid + nthr * (r0 + q);
-                if (decltype(full)::value || e < nval) ld[q] = gen.load(nbase + e, cbv[r0 + q]);
+                if (decltype(full)::value || e < nval) ld[q] = gen.load(Nd{nbase, (uint32_t)e}, cbv[r0 + q]);
             }
 #pragma unroll
-            for (int q = 0; q < NODE_GROUP; ++q) {
+            for (int q = 0; q < NG; ++q) {
                 const int e = tid + nthr * (r0 + q);
                 T a[NF];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) a[f] = T(0);
-                if (decltype(full)::value || e < nval) gen.gen(nbase + e, ld[q], a);
+                if (decltype(full)::value || e < nval) gen.gen(Nd{nbase, (uint32_t)e}, ld[q], a);
 #pragma unroll
                 for (int f = 0; f < NF; ++f) gv[f][r0 + q] = a[f];
             }
@@ -840,30 +843,35 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
     const cx<T>* __restrict__ src = S + (long)a.in_off * a.saf + (long)kx * a.P2;
     cx<T>* __restrict__ dst = S + (long)a.out_off * a.saf + (long)kx * a.P2 + y;
 
-    cx<T> acc[R][NO];
+    // ring of RR = 2 MT + 2 output planes (one more than the 2 MT + 1 an
+    // input plane reaches, so that the sweep unrolls by an even count and the
+    // two register sets of prefetched inputs alternate at compile time)
+    constexpr int RR = R + 1;
+    cx<T> acc[RR][NO];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int r = 0; r < RR; ++r)
 #pragma unroll
         for (int o = 0; o < NO; ++o) acc[r][o] = cx<T>{T(0), T(0)};
-    cx<T> nv[NI], nh[NI];   // inputs of the next plane (row y, halo row yh)
+    cx<T> nv[2][NI], nh[2][NI];   // inputs of the next two planes (row y, halo row yh)
 #pragma unroll
-    for (int J = 0; J < NI; ++J) nv[J] = nh[J] = cx<T>{T(0), T(0)};
+    for (int J = 0; J < NI; ++J) nv[0][J] = nh[0][J] = nv[1][J] = nh[1][J] = cx<T>{T(0), T(0)};
     // straight-line loads: the plane index is clamped into the body (planes
     // outside it are never used) and rows beyond the body read row 0 and are
     // replaced by zeros
     const int yl = yin ? y : 0;
-    auto load = [&](int z) {
+    auto load = [&](auto pc, int z) {
+        constexpr int P = decltype(pc)::value;
         const cx<T>* __restrict__ sp = src + min(max(z, 0), a.b3 - 1) * zs;
 #pragma unroll
         for (int J = 0; J < NI; ++J) {
             const cx<T> v = sp[J * a.saf + yl];
-            nv[J] = yin ? v : cx<T>{T(0), T(0)};
+            nv[P][J] = yin ? v : cx<T>{T(0), T(0)};
         }
         if (halo) {
 #pragma unroll
             for (int J = 0; J < NI; ++J) {
-                nh[J] = cx<T>{T(0), T(0)};
-                if (hin) nh[J] = sp[J * a.saf + yh];
+                nh[P][J] = cx<T>{T(0), T(0)};
+                if (hin) nh[P][J] = sp[J * a.saf + yh];
             }
         }
     };
@@ -876,27 +884,30 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
 
     const int zb = z0 - MT;               // first input plane of the sweep
     const int nst = (z1 - z0) + 2 * MT;   // input planes swept
-    load(zb);
-    for (int s0 = 0; s0 < nst; s0 += R) {
-        OutLoop<0, R>::run([&](auto rc) {
-            constexpr int rr = decltype(rc)::value;
+    load(std::integral_constant<int, 0>{}, zb);
+    load(std::integral_constant<int, 1>{}, zb + 1);
+    for (int s0 = 0; s0 < nst; s0 += RR) {
+        OutLoop<0, RR>::run([&](auto rc) {
+            constexpr int rr = decltype(rc)::value, P = rr & 1;
             const int s = s0 + rr;
             if (s >= nst) return;   // block-uniform
             const int zi = zb + s;
             const bool act = zi >= 0 && zi < a.b3;   // block-uniform
-            lds_ptr<cx<T>> row = lds + (s & 1) * (NI * W);
+            lds_ptr<cx<T>> row = lds + P * (NI * W);
             if (act) {
 #pragma unroll
-                for (int J = 0; J < NI; ++J) row[J * W + MT + tid] = nv[J];
+                for (int J = 0; J < NI; ++J) row[J * W + MT + tid] = nv[P][J];
                 if (halo) {
                     if (hthr) {
 #pragma unroll
-                        for (int J = 0; J < NI; ++J) row[J * W + ph] = nh[J];
+                        for (int J = 0; J < NI; ++J) row[J * W + ph] = nh[P][J];
                     }
                 }
                 __syncthreads();
             }
-            load(zi + 1);
+            // the set just stored takes the plane after next (two planes of
+            // arithmetic to arrive)
+            load(std::integral_constant<int, P>{}, zi + 2);
             if (act) {
                 // per output, the terms even (G = 0) and odd (G = 1) along z of
                 // inputs J0 .. J1-1 summed, then added to the planes they reach
@@ -920,7 +931,7 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
                                     });
                                     // input plane zi reaches output plane zi - b with oz = +b
                                     // and, for b > 0, plane zi + b with oz = -b (sign (-1)^G)
-                                    constexpr int sm = (rr - b + R) % R, sp = (rr + b) % R;
+                                    constexpr int sm = (rr - b + RR) % RR, sp = (rr + b) % RR;
                                     acc[sm][O] = acc[sm][O] + q;
                                     if constexpr (b > 0) {
                                         if constexpr (G == 0) acc[sp][O] = acc[sp][O] + q;
@@ -959,7 +970,7 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
                 }
             }
             // output plane zi - MT has all its inputs
-            constexpr int sd = (rr + MT + 1) % R;
+            constexpr int sd = (rr - MT + RR) % RR;
             const int zo = zi - MT;
             if (zo >= z0 && yin) {
 #pragma unroll
@@ -1066,7 +1077,7 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
                                                const cx<T>* __restrict__ twb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-    constexpr int NO = F::NOUT;
+    constexpr int NO = F::NOUT, NG = node_group<T>();
     const int lgNc = LG > 0 ? LG : 31 - __clz(g.Nc), Nc = 1 << lgNc, Tc = Nc >> 3;
     const int nthr = LG > 0 ? xblock_threads<T>() : (int)blockDim.x;
     const int Lt = nthr / Tc;
@@ -1101,7 +1112,7 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
 #pragma unroll
     for (int r = 0; r < RN; ++r) {
         const int e = tid + nthr * r;
-        cbv[r] = e < nval ? node_flags(fin, nbase + e) : uint8_t(0);
+        cbv[r] = e < nval ? node_flags(fin, Nd{nbase, (uint32_t)e}) : uint8_t(0);
     }
     T val[NO][16];
     lds_ptr<cx<T>> rowv = as_lds(row);
@@ -1161,21 +1172,21 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     for (int r = 0; r < (F::NRED > 0 ? F::NRED : 1); ++r) red[r] = 0.0;
     auto run_fin = [&](auto full) {
 #pragma unroll
-        for (int r0 = 0; r0 < RN; r0 += NODE_GROUP) {
-            typename F::Ld ld[NODE_GROUP];
+        for (int r0 = 0; r0 < RN; r0 += NG) {
+            typename F::Ld ld[NG];
 #pragma unroll
-            for (int q = 0; q < NODE_GROUP; ++q) {
+            for (int q = 0; q < NG; ++q) {
                 const int e = tid + nthr * (r0 + q);
-                if (decltype(full)::value || e < nval) ld[q] = fin.load(nbase + e, cbv[r0 + q]);
+                if (decltype(full)::value || e < nval) ld[q] = fin.load(Nd{nbase, (uint32_t)e}, cbv[r0 + q]);
             }
 #pragma unroll
-            for (int q = 0; q < NODE_GROUP; ++q) {
+            for (int q = 0; q < NG; ++q) {
                 const int e = tid + nthr * (r0 + q);
                 if (decltype(full)::value || e < nval) {
                     T vv[NO];
 #pragma unroll
                     for (int o = 0; o < NO; ++o) vv[o] = nv[o][r0 + q];
-                    fin.fin(nbase + e, ld[q], vv, red);
+                    fin.fin(Nd{nbase, (uint32_t)e}, ld[q], vv, red);
                 }
             }
         }

@@ -53,6 +53,7 @@ struct pd_plan_s {
     int yz_mt, yz_nu;            // its radius in spacings (0: no (y, z) direct pass) and tap count
     void* stat;                  // T [ncs][nb]
     void* stat_int;              // T [ncs]: the static fields at interior nodes
+    double stat_int_h[10];       // the same values (rounded to T) on the host
     long n_edge;                 // body-box nodes that are not interior
     uint8_t* chiB;               // [nb] body | interior << 1 (interior: whole horizon in the body)
     uint8_t* chiO;               // [dim][nb]
