@@ -111,7 +111,8 @@ __global__ void k_taps_yz(int n1, int h1, int MT, int nu, int ns, const int* __r
 
 // Static embedded-constraint fields by direct quadrature over the horizon
 // (the paper allows P = C (*) 1 either by quadrature or by FFT, Sec. 3.1):
-//   stat_c(x) = sum_{o in S} chi_B(x + o) K_c(o)   on the body box.
+//   stat_c(x) = sum_{o in S} chi_B(x + o) K_c(o)   on the body box,
+// stored node-major (stat[i * ncs + c]).
 // Also flags[i] = chiB[i] | 2 when the node's whole horizon lies in the body
 // (then stat equals the interior sums: every bond counted, same order).
 template <class T>
@@ -131,7 +132,7 @@ __global__ void k_static(int b1, int b2, int b3, int ns, const int* __restrict__
         ++inside;
         for (int c = 0; c < ncs; ++c) acc[c] += kval[(long)s * ncs + c];
     }
-    for (int c = 0; c < ncs; ++c) stat[(long)c * nb + i] = T(acc[c]);
+    for (int c = 0; c < ncs; ++c) stat[i * ncs + c] = T(acc[c]);
     flags[i] = (uint8_t)(chiB[i] ? (inside == ns ? 3 : 1) : 0);
 }
 
@@ -183,6 +184,7 @@ NodeCtx<T> ctx(pd_plan p) {
     c.chiB = p->chiB;
     c.chiO = p->chiO;
     c.stat = reinterpret_cast<const T*>(p->stat);
+    c.ncs = p->ncs;
     c.stat_int = reinterpret_cast<const T*>(p->stat_int);
     for (int q = 0; q < 10; ++q) c.sint[q] = T(q < p->ncs ? p->stat_int_h[q] : 0.0);
     c.edge_frac = p->nb > 0 ? (double)p->n_edge / (double)p->nb : 0.0;

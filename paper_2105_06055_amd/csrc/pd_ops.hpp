@@ -73,6 +73,12 @@ __device__ __forceinline__ void stf(T* p, Nd n, typename ident<T>::type v) {
     auto b = uniform_base(p + n.base) + n.off * (uint32_t)sizeof(T);
     *reinterpret_cast<__attribute__((address_space(1))) T*>(b) = v;
 }
+// load of element idx of a block-uniform array p + base (32-bit index)
+template <class T>
+__device__ __forceinline__ T ldo(const T* p, long base, uint32_t idx) {
+    auto b = uniform_base(p + base) + idx * (uint32_t)sizeof(T);
+    return *reinterpret_cast<const __attribute__((address_space(1))) T*>(b);
+}
 // address of field p at node n (for address selects)
 template <class T>
 __device__ __forceinline__ const T* adf(const T* p, Nd n) {
@@ -84,7 +90,8 @@ struct NodeCtx {
     long nb;                   // body nodes
     const uint8_t* chiB;       // [nb] body | interior << 1
     const uint8_t* chiO;       // [D][nb]
-    const T* stat;             // static fields [ncs][nb]
+    const T* stat;             // static fields [nb][ncs] (a node's fields together)
+    int ncs;                   // static fields per node
     const T* stat_int;         // [ncs] values at interior nodes (device copy)
     T sint[10];                // the same values, as kernel arguments
     double edge_frac;          // host bookkeeping: fraction of body-box nodes that
@@ -92,19 +99,21 @@ struct NodeCtx {
     // static field q (runtime index) at node i with flags cb (a select of
     // addresses, no branch)
     __device__ __forceinline__ T st(int q, Nd i, uint8_t cb) const {
-        const T* a = (cb & 2) ? stat_int + q : adf(stat + (long)q * nb, i);
+        const T* a = (cb & 2) ? stat_int + q : stat + (i.base + i.off) * ncs + q;
         return *a;
     }
     // static fields Q0 .. Q0+N-1 at node i: the interior values at interior
-    // nodes (no memory access), the per-node arrays at the others, loaded
-    // under a branch that waves without edge nodes skip
+    // nodes (no memory access), the node's own fields at the others (one
+    // contiguous run), loaded under a branch that waves without edge nodes
+    // skip
     template <int Q0, int N>
     __device__ __forceinline__ void st_range(Nd i, uint8_t cb, T* out) const {
 #pragma unroll
         for (int k = 0; k < N; ++k) out[k] = sint[Q0 + k];
         if (!(cb & 2)) {
+            const uint32_t o = i.off * (uint32_t)ncs + Q0;
 #pragma unroll
-            for (int k = 0; k < N; ++k) out[k] = ldf(stat + (long)(Q0 + k) * nb, i);
+            for (int k = 0; k < N; ++k) out[k] = ldo(stat, i.base * ncs, o + k);
         }
     }
 };

@@ -51,7 +51,7 @@ struct pd_plan_s {
     void* taps_d;                // T [NP][nct][ntap], direct convention
     void* taps_yz;               // T [h1][nct][yz_nu]: partial x-spectra over the (y, z) quarter disc (3D)
     int yz_mt, yz_nu;            // its radius in spacings (0: no (y, z) direct pass) and tap count
-    void* stat;                  // T [ncs][nb]
+    void* stat;                  // T [nb][ncs]
     void* stat_int;              // T [ncs]: the static fields at interior nodes
     double stat_int_h[10];       // the same values (rounded to T) on the host
     long n_edge;                 // body-box nodes that are not interior
