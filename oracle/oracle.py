@@ -64,6 +64,7 @@ def lib():
         _lib.orc_m0.restype = C.c_double
         _lib.orc_bb_force.argtypes = [gp, C.c_double, dp, dp, dp]
         _lib.orc_bb_energy.argtypes = [gp, C.c_double, dp, dp, dp]
+        _lib.orc_nbb_force.argtypes = [gp, C.c_double, dp, dp, dp]
         _lib.orc_lps_force.argtypes = [gp, C.c_double, C.c_double, dp, dp, dp, dp]
         _lib.orc_damage_index.argtypes = [gp, up, up, dp, C.POINTER(C.c_int32)]
         _lib.orc_verlet.argtypes = [gp, mp, up, up, up, dp, dp, dp, dp, dp, dp, dp,
@@ -138,6 +139,16 @@ def bb_force(g: Geom, alpha, phi, u):
     u = _f64(u)
     L = np.empty_like(u)
     lib().orc_bb_force(C.byref(g), alpha, _d(phi), _d(u), _d(L))
+    return L
+
+
+def nbb_force(g: Geom, alpha, phi, u):
+    """Nonlinear rotation-invariant bond-based force density (Eq. 19-20),
+    bond by bond, with bond weights phi."""
+    phi = _f64(phi)
+    u = _f64(u)
+    L = np.empty_like(u)
+    lib().orc_nbb_force(C.byref(g), alpha, _d(phi), _d(u), _d(L))
     return L
 
 

@@ -154,6 +154,50 @@ void orc_bb_force(const orc_geom* g, double alpha, const double* phi, const doub
     free(S);
 }
 
+/* Nonlinear, rotation-invariant bond-based solid (Sec. 3.2, Eq. 19-20), with
+ * bond weights phi(x) phi(x') as for the linear model:
+ *   L_i(x) = phi(x) sum_o phi(x+o) f_i dV,
+ *   f = alpha omega(|xi|) |xi| (s + 3/2 s^2 + 1/2 s^3) (xi + eta)/|xi + eta|,
+ *   s = (|xi + eta| - |xi|) / |xi|   (the bond strain),
+ * xi = o*dx, eta = u(x+o) - u(x).  A bond whose deformed length is zero
+ * carries no force (the limit of f, since s + 3/2 s^2 + 1/2 s^3 = 0 at
+ * s = -1).  No linearisation: evaluated bond by bond as written. */
+void orc_nbb_force(const orc_geom* g, double alpha, const double* phi, const double* u, double* L) {
+    int cap = 20000;
+    int* S = (int*)malloc(sizeof(int) * 3 * cap);
+    int ns = orc_stencil(g, S, cap);
+    long N = orc_nodes(g);
+    int D = g->dim;
+    double dV = orc_dv(g);
+#pragma omp parallel for schedule(static)
+    for (long id = 0; id < N; ++id) {
+        int x = (int)(id % g->nb[0]);
+        int y = (int)((id / g->nb[0]) % g->nb[1]);
+        int z = (int)(id / ((long)g->nb[0] * g->nb[1]));
+        double acc[3] = {0, 0, 0};
+        if (phi[id] != 0.0) {
+            for (int s = 0; s < ns; ++s) {
+                long j = orc_nbr(g, x, y, z, &S[3 * s]);
+                if (j < 0 || phi[j] == 0.0) continue;
+                double xi[3] = {S[3 * s] * g->dx[0], S[3 * s + 1] * g->dx[1], S[3 * s + 2] * g->dx[2]};
+                double r2 = 0, y2 = 0, yv[3] = {0, 0, 0};
+                for (int d = 0; d < D; ++d) {
+                    yv[d] = xi[d] + (u[d * N + j] - u[d * N + id]);
+                    r2 += xi[d] * xi[d];
+                    y2 += yv[d] * yv[d];
+                }
+                double r = sqrt(r2), ry = sqrt(y2);
+                if (ry == 0.0) continue;
+                double st = (ry - r) / r;
+                double mag = alpha * orc_omega(g, r) * r * (st + 1.5 * st * st + 0.5 * st * st * st) * phi[j] * dV;
+                for (int i = 0; i < D; ++i) acc[i] += mag * yv[i] / ry;
+            }
+        }
+        for (int i = 0; i < D; ++i) L[i * N + id] = phi[id] * acc[i];
+    }
+    free(S);
+}
+
 /* Strain energy density of the linearized bond-based solid with bond
  * weights (Eq. 42 with the bond weights inserted as the paper prescribes
  * for bond-breaking models, Eq. 47/102), in its direct bond form:
