@@ -55,7 +55,12 @@ typedef enum { PD_F32 = 0, PD_F64 = 1 } pd_dtype;
 
 typedef enum {
     PD_BB_LINEAR = 0,     /* linearized bond-based solid, Eq. 17-18 */
-    PD_LPS_LINEAR = 1     /* linearized state-based (LPS) solid, Eq. 33-39, 3D only */
+    PD_LPS_LINEAR = 1,    /* linearized state-based (LPS) solid, Eq. 33-39, 3D only */
+    PD_BB_NONLINEAR = 2   /* nonlinear, rotation-invariant bond-based solid,
+                             Eq. 19-20 in the convolution form of Eq. 21-26, 2D;
+                             same micromodulus constant alpha as PD_BB_LINEAR
+                             (it is the small-displacement limit); pd_force only,
+                             PD_WEIGHT_NONE */
 } pd_model;
 
 typedef enum {
@@ -128,9 +133,12 @@ typedef struct {
  * horizon stencil (FP64), forms their partial spectra and the static
  * embedded-constraint fields (C*chi_B, a*chi_B, m; Eq. 56, 92-94, 97) and
  * allocates workspaces.  Returns PD_EINVAL for inconsistent sizes or
- * padding smaller than the horizon, PD_EUNSUPPORTED for the LPS model in 2D
- * or grid lengths outside the supported set, PD_ENOMEM / PD_EDEVICE on HIP
- * failures.  On error *out is NULL. */
+ * padding smaller than the horizon, PD_EUNSUPPORTED for the LPS model in 2D,
+ * the nonlinear bond-based model in 3D or with weights, or grid lengths
+ * outside the supported set, PD_ENOMEM / PD_EDEVICE on HIP failures.  On
+ * error *out is NULL.  Plans of the nonlinear bond-based model serve
+ * pd_force (without W_out) only; the other operations return
+ * PD_EUNSUPPORTED for them. */
 pd_status pd_plan_create(const pd_grid* grid, const pd_horizon* horizon, const pd_kernel* kernel,
                          const pd_mask* mask, pd_dtype dtype, int flags, void* stream,
                          pd_plan* out);
@@ -142,7 +150,8 @@ void pd_plan_destroy(pd_plan plan);
 pd_status pd_plan_query(pd_plan plan, pd_plan_info* info);
 
 /* Internal force density L (Eq. 57/58 for bond-based; Eq. 95-97 for LPS,
- * with the sign reading of the design doc; Eq. 101 with weights).
+ * with the sign reading of the design doc; Eq. 101 with weights; Eq. 21-26 for
+ * the nonlinear bond-based model).
  *   u      [dim][body]  displacement
  *   weight NULL for PD_WEIGHT_NONE; uint8 lambda [body] for INTEGRITY;
  *          dtype s [body] for SCALE

@@ -54,6 +54,7 @@ pd_status pd_force_adjoint(pd_plan p, const void* u, const void* weight, const v
                            void* weight_bar, void* stream) {
     if (!p || !g_bar) return PD_EINVAL;
     if (weight_bar && !u) return PD_EINVAL;
+    if (p->kern.model == PD_BB_NONLINEAR) return PD_EUNSUPPORTED;
     if (p->dtype == PD_F32)
         return adjoint_impl<float>(p, (const float*)u, nullptr, weight, (const float*)g_bar, (float*)u_bar,
                                    (float*)weight_bar, 1.0f, 0, S_(stream));
@@ -64,6 +65,7 @@ pd_status pd_force_adjoint(pd_plan p, const void* u, const void* weight, const v
 pd_status pd_verlet_step(pd_plan p, pd_state* state, const void* b, const void* w, double dt, int nsteps,
                          double* energy_out, void* stream) {
     if (!p || !state) return PD_EINVAL;
+    if (p->kern.model == PD_BB_NONLINEAR) return PD_EUNSUPPORTED;
     if (p->dtype == PD_F32)
         return verlet_impl<float>(p, state, (const float*)b, (const float*)w, dt, nsteps, energy_out, S_(stream));
     return verlet_impl<double>(p, state, (const double*)b, (const double*)w, dt, nsteps, energy_out, S_(stream));
@@ -72,6 +74,7 @@ pd_status pd_verlet_step(pd_plan p, pd_state* state, const void* b, const void* 
 pd_status pd_verlet_adjoint(pd_plan p, const void* u_n, const void* u_np1, const void* s, void* u_bar, void* v_bar,
                             void* s_bar, double dt, void* stream) {
     if (!p) return PD_EINVAL;
+    if (p->kern.model == PD_BB_NONLINEAR) return PD_EUNSUPPORTED;
     if (p->dtype == PD_F32)
         return verlet_adjoint_impl<float>(p, (const float*)u_n, (const float*)u_np1, (const float*)s, (float*)u_bar,
                                           (float*)v_bar, (float*)s_bar, dt, S_(stream));
@@ -82,12 +85,14 @@ pd_status pd_verlet_adjoint(pd_plan p, const void* u_n, const void* u_np1, const
 pd_status pd_static_solve(pd_plan p, const void* b, const void* w, void* u_inout, double rtol, int maxit, int options,
                           pd_solve_info* info, void* stream) {
     if (!p) return PD_EINVAL;
+    if (p->kern.model == PD_BB_NONLINEAR) return PD_EUNSUPPORTED;
     return static_solve_impl(p, (const double*)b, (const double*)w, (double*)u_inout, rtol, maxit, options, info,
                              S_(stream));
 }
 
 pd_status pd_damage_index(pd_plan p, const uint8_t* lambda, void* d_out, void* stream) {
     if (!p) return PD_EINVAL;
+    if (p->kern.model == PD_BB_NONLINEAR) return PD_EUNSUPPORTED;
     if (p->dtype == PD_F32) return damage_impl<float>(p, lambda, (float*)d_out, S_(stream));
     return damage_impl<double>(p, lambda, (double*)d_out, S_(stream));
 }

@@ -651,7 +651,7 @@ inline double symbol_lambda_max(pd_plan p, const std::vector<Bond>& S) {
                     double ph = 0;
                     for (int d = 0; d < D; ++d) ph += 2 * kPi * kk[d] * bd.o[d];
                     const double om = p->influence == 0 ? 1.0 / bd.r : 1.0;
-                    double coef = (p->kern.model == PD_BB_LINEAR) ? p->alpha : 30.0 * p->mu / p->m0;
+                    double coef = (p->kern.model == PD_LPS_LINEAR) ? 30.0 * p->mu / p->m0 : p->alpha;
                     coef *= om / (bd.r * bd.r) * p->dV * (1.0 - std::cos(ph));
                     for (int i = 0; i < D; ++i)
                         for (int j = 0; j < D; ++j) Mx[i][j] += coef * bd.xi[i] * bd.xi[j];
@@ -682,13 +682,16 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
     if (p->kern.model == PD_BB_LINEAR) {
         nct = nsym(D) + (p->kern.weight == PD_WEIGHT_INTEGRITY ? 1 : 0);
         ncs = nct;
+    } else if (p->kern.model == PD_BB_NONLINEAR) {
+        nct = nsym(D) + D + 1;   // C_ab, a_i, c
+        ncs = nct;
     } else {
         nct = 9;
         ncs = 10;
     }
     kv.assign((size_t)ns * ncs, 0.0);
     par.assign((size_t)nct * 3, 0);
-    const double cC = (p->kern.model == PD_BB_LINEAR) ? p->alpha : 30.0 * p->mu / p->m0;
+    const double cC = (p->kern.model == PD_LPS_LINEAR) ? 30.0 * p->mu / p->m0 : p->alpha;
     for (int s = 0; s < ns; ++s) {
         const Bond& bd = S[s];
         const double w = om(bd.r);
@@ -697,6 +700,11 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
                 kv[(size_t)s * ncs + symi(D, i, j)] = cC * w * bd.xi[i] * bd.xi[j] / (bd.r * bd.r) * p->dV;
         if (p->kern.model == PD_BB_LINEAR) {
             if (p->kern.weight == PD_WEIGHT_INTEGRITY) kv[(size_t)s * ncs + nsym(D)] = 1.0;
+        } else if (p->kern.model == PD_BB_NONLINEAR) {
+            // Eq. 24: a_i = c xi_i, c = alpha omega / |xi|^2 (with dV)
+            const double cc = cC * w / (bd.r * bd.r) * p->dV;
+            for (int i = 0; i < D; ++i) kv[(size_t)s * ncs + nsym(D) + i] = cc * bd.xi[i];
+            kv[(size_t)s * ncs + nsym(D) + D] = cc;
         } else {
             for (int i = 0; i < 3; ++i) kv[(size_t)s * ncs + 6 + i] = w * bd.xi[i] * p->dV;
             kv[(size_t)s * ncs + 9] = w * bd.r * bd.r * p->dV;
@@ -710,6 +718,8 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
         }
     if (p->kern.model == PD_LPS_LINEAR)
         for (int i = 0; i < 3; ++i) par[3 * (6 + i) + i] = 1;
+    if (p->kern.model == PD_BB_NONLINEAR)
+        for (int i = 0; i < D; ++i) par[3 * (nsym(D) + i) + i] = 1;
     for (int c = 0; c < nct; ++c)
         if (par[3 * c + (D - 1)]) p->oddmask |= 1u << c;
     p->nct = nct;
@@ -894,6 +904,7 @@ pd_status plan_alloc(pd_plan p, hipStream_t st, const uint8_t* chiB_h, const uin
         // unweighted bond-based: force (D) or force+energy (D+1+nsym)
         capA = std::max(capA, D + 1 + nsym(D));
     }
+    if (p->kern.model == PD_BB_NONLINEAR) capA = std::max(capA, 2 * D + 1 + nsym(D));   // 2D: 8 inputs, 8 outputs
     p->saf_cap = capA;
     p->sbf_cap = std::max(capB, capC);
     p->scf_cap = 0;
@@ -930,7 +941,10 @@ inline pd_status plan_create_impl(const pd_grid* grid, const pd_horizon* hz, con
     const int D = grid->dim;
     if (D != 2 && D != 3) return PD_EINVAL;
     if (kern->model == PD_LPS_LINEAR && D != 3) return PD_EUNSUPPORTED;
-    if (kern->model != PD_BB_LINEAR && kern->model != PD_LPS_LINEAR) return PD_EINVAL;
+    if (kern->model != PD_BB_LINEAR && kern->model != PD_LPS_LINEAR && kern->model != PD_BB_NONLINEAR)
+        return PD_EINVAL;
+    if (kern->model == PD_BB_NONLINEAR && (D != 2 || kern->weight != PD_WEIGHT_NONE || (flags & PD_PLAN_MIXED)))
+        return PD_EUNSUPPORTED;
     if (kern->model == PD_LPS_LINEAR && kern->weight != PD_WEIGHT_NONE) return PD_EUNSUPPORTED;
     if (dtype != PD_F32 && dtype != PD_F64) return PD_EINVAL;
     if (!(hz->delta > 0) || (hz->influence != 0 && hz->influence != 1)) return PD_EINVAL;
@@ -1048,6 +1062,17 @@ pd_status force_impl(pd_plan p, const T* u, const void* weight, T* L, T* W, hipS
         fB.theta = reinterpret_cast<const T*>(p->theta);
         fB.L = L;
         return run_chain<T>(p, gB, mB, fB, st, 3);
+    }
+    if (p->kern.model == PD_BB_NONLINEAR) {
+        if (W || p->dim != 2) return PD_EUNSUPPORTED;
+        GenNBB<T, 2> gg{};
+        gg.c = ctx<T>(p);
+        gg.u = u;
+        FinNBB<T, 2> ff{};
+        ff.c = ctx<T>(p);
+        ff.u = u;
+        ff.L = L;
+        return run_chain<T>(p, gg, MulNBB<T, 2>{}, ff, st);
     }
     // bond-based
     auto go = [&](auto Dc) -> pd_status {

@@ -226,6 +226,42 @@ struct GenTheta {
     __device__ __forceinline__ void gen(Nd, const Ld& L, T (&in)[1]) const { in[0] = L.chiB ? L.th : T(0); }
 };
 
+// Nonlinear bond-based inputs (Sec. 3.2): with h = |u|^2 / 2 and the mask chi,
+//   chi u_j (D) | chi h (1) | chi u_a u_b, a <= b (nsym) | chi h u_i (D).
+template <class T, int D>
+struct GenNBB {
+    static constexpr int NIN = 2 * D + 1 + nsym(D);
+    NodeCtx<T> c;
+    const T* u;
+    __host__ double nbytes() const { return D * sizeof(T) + 1.0; }
+    struct Ld { T u[D]; uint8_t chiB; };
+    __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const {
+        Ld L;
+#pragma unroll
+        for (int d = 0; d < D; ++d) L.u[d] = ldf(u + d * c.nb, i);
+        L.chiB = cb;
+        return L;
+    }
+    __device__ __forceinline__ void gen(Nd, const Ld& L, T (&in)[NIN]) const {
+        const T chi = L.chiB ? T(1) : T(0);
+        T h = T(0);
+#pragma unroll
+        for (int d = 0; d < D; ++d) h += L.u[d] * L.u[d];
+        h *= T(0.5);
+        const T ch = chi * h;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            in[d] = chi * L.u[d];
+            in[D + 1 + nsym(D) + d] = ch * L.u[d];
+        }
+        in[D] = ch;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = a; b < D; ++b) in[D + 1 + symi(D, a, b)] = chi * L.u[a] * L.u[b];
+    }
+};
+
 // Damage count input: chi_B lambda.
 template <class T>
 struct GenPhi {
@@ -486,6 +522,103 @@ struct MulLPSB {
             }
             out[i] = acc;
         }
+    }
+};
+
+// Nonlinear bond-based multiplier (Sec. 3.2, the convolution form of
+// Eq. 21-26 read with xi = x' - x).  Kernel components: C_ab =
+// c xi_a xi_b (nsym), a_i = c xi_i (D), c = alpha omega / |xi|^2 (1), all
+// with dV.  Inputs as GenNBB.  Outputs, every sum that the force later
+// multiplies by the same local factor formed here in spectral space:
+//   D_i  = sum_j C_ij (*) chi u_j + a_i (*) chi h + sum_j a_j (*) chi u_j u_i
+//          + c (*) chi h u_i                                          (D)
+//   S_ab = a_a (*) chi u_b + a_b (*) chi u_a + c (*) chi u_a u_b      (nsym)
+//   t    = sum_j a_j (*) chi u_j + c (*) chi h                        (1)
+//   c_j  = c (*) chi u_j                                              (D)
+// Every (output, input) pair has at most one term: a multiple of the raw
+// correlation with one component, whose multiplier is i^(#odd axes) times
+// its real sum.
+template <class T, int D>
+struct MulNBB {
+    static constexpr int NIN = 2 * D + 1 + nsym(D);
+    static constexpr int NOUT = D + nsym(D) + 1 + D;
+    static constexpr int C0 = 0, NC = nsym(D) + D + 1;
+    static constexpr int DIM = D;
+    static constexpr int CA = nsym(D), CC = nsym(D) + D;   // first a_i, the scalar c
+    static constexpr bool RT_ODD = false;
+    __host__ __device__ static constexpr int par3(int cc) {
+        return cc < CA ? sym_par(D, cc) : (cc < CC ? 1 << (cc - CA) : 0);
+    }
+    // components odd along the last axis: C_xy, a_y (2D); C_xz, C_yz, a_z (3D)
+    static constexpr uint32_t ODD = (D == 2) ? ((1u << 1) | (1u << 4)) : ((1u << 2) | (1u << 4) | (1u << 8));
+    __device__ __forceinline__ T ka_value() const { return T(0); }
+    __host__ __device__ static constexpr int npar3(int p) { return (p & 1) + ((p >> 1) & 1) + ((p >> 2) & 1); }
+    // f times the raw correlation with component cc: f i^(#odd axes) K_cc
+    __host__ __device__ static constexpr DTerm raw(int cc, int f = 1) {
+        const int n = npar3(par3(cc));
+        return DTerm{cc, (n & 2) ? -f : f, n & 1, false};
+    }
+    __host__ __device__ static constexpr DTerm dterm(int O, int J) {
+        constexpr DTerm none{0, 0, 0, false};
+        constexpr int JH = D, JU2 = D + 1, JHU = D + 1 + nsym(D);
+        constexpr int OS = D, OT = D + nsym(D), OC = D + nsym(D) + 1;
+        if (O < OS) {
+            const int i = O;
+            if (J < D) return raw(symi(D, i, J));
+            if (J == JH) return raw(CA + i);
+            if (J < JHU) {
+                for (int a = 0; a < D; ++a)
+                    for (int b = a; b < D; ++b)
+                        if (JU2 + symi(D, a, b) == J) {
+                            if (a == i) return raw(CA + b);
+                            if (b == i) return raw(CA + a);
+                        }
+                return none;
+            }
+            return (J - JHU == i) ? raw(CC) : none;
+        }
+        if (O < OT) {
+            for (int a = 0; a < D; ++a)
+                for (int b = a; b < D; ++b)
+                    if (OS + symi(D, a, b) == O) {
+                        if (J == JU2 + symi(D, a, b)) return raw(CC);
+                        if (a == b) return J == a ? raw(CA + a, 2) : none;
+                        if (J == b) return raw(CA + a);
+                        if (J == a) return raw(CA + b);
+                    }
+            return none;
+        }
+        if (O == OT) return J < D ? raw(CA + J) : (J == JH ? raw(CC) : none);
+        return J == O - OC ? raw(CC) : none;
+    }
+    template <int O>
+    __host__ __device__ static constexpr uint32_t need() {
+        uint32_t m = 0;
+        for (int J = 0; J < NIN; ++J)
+            if (dterm(O, J).coef != 0) m |= 1u << dterm(O, J).c;
+        return m;
+    }
+    template <int O>
+    __device__ __forceinline__ cx<T> one(const T* K, const cx<T>* in) const {
+        cx<T> acc = {T(0), T(0)};
+#pragma unroll
+        for (int J = 0; J < NIN; ++J) {
+            const DTerm t = dterm(O, J);
+            if (t.coef == 0) continue;
+            const T k = T(t.coef) * K[t.c];
+            acc = acc + (t.ipow ? kmuli(k, in[J]) : kmul(k, in[J]));
+        }
+        return acc;
+    }
+    template <int O>
+    __device__ __forceinline__ void mul_from(const T* K, const cx<T>* in, cx<T>* out) const {
+        if constexpr (O < NOUT) {
+            out[O] = one<O>(K, in);
+            mul_from<O + 1>(K, in, out);
+        }
+    }
+    __device__ __forceinline__ void mul(const T* K, int, const cx<T>* in, cx<T>* out) const {
+        mul_from<0>(K, in, out);
     }
 };
 
@@ -923,6 +1056,51 @@ struct FinLin {
                 stf(L + k, i, r);
                 red[0] += double(r) * double(r);
             }
+        }
+    }
+};
+
+// Nonlinear bond-based force (Sec. 3.2): with h = |u|^2 / 2 and the static
+// sums P_ab = C_ab (*) chi, q_i = a_i (*) chi, p = c (*) chi (plan time),
+//   L_i = chi [ D_i - sum_j (P_ij + S_ij) u_j - t u_i
+//               + sum_j (q_j + c_j) u_j u_i + (q_i + c_i) h - p h u_i ].
+template <class T, int D>
+struct FinNBB {
+    static constexpr int NOUT = D + nsym(D) + 1 + D, NRED = 0;
+    NodeCtx<T> c;
+    const T* u;
+    T* L;
+    __host__ double nbytes() const {
+        const double t = sizeof(T);
+        return 2.0 * D * t + 1.0 + (nsym(D) + D + 1) * t * c.edge_frac;
+    }
+    struct Ld { T u[D], st[nsym(D) + D + 1]; uint8_t chiB; };
+    __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const {
+        Ld Q;
+#pragma unroll
+        for (int d = 0; d < D; ++d) Q.u[d] = ldf(u + d * c.nb, i);
+        c.template st_range<0, nsym(D) + D + 1>(i, cb, Q.st);
+        Q.chiB = cb;
+        return Q;
+    }
+    __device__ __forceinline__ void fin(Nd i, const Ld& Q, const T (&val)[NOUT], double*) const {
+        constexpr int OS = D, OT = D + nsym(D), OC = OT + 1;
+        const T chi = Q.chiB ? T(1) : T(0);
+        T h = T(0), qcu = T(0);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            h += Q.u[d] * Q.u[d];
+            qcu += (Q.st[nsym(D) + d] + val[OC + d]) * Q.u[d];
+        }
+        h *= T(0.5);
+        const T p = Q.st[nsym(D) + D];
+        const T lu = qcu - val[OT] - p * h;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            T t = val[a] + lu * Q.u[a] + (Q.st[nsym(D) + a] + val[OC + a]) * h;
+#pragma unroll
+            for (int j = 0; j < D; ++j) t -= (Q.st[symi(D, a, j)] + val[OS + symi(D, a, j)]) * Q.u[j];
+            stf(L + a * c.nb, i, chi * t);
         }
     }
 };
