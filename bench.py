@@ -206,6 +206,39 @@ def run_force_rate(wl, dtype, reps, warmup):
     return t
 
 
+def run_plate_force_rate(model, dtype, reps, warmup, nb=512, nfft=1024):
+    """pd_force alone on the 2D plate (nb^2 body with holes on an nfft^2 grid,
+    delta = 3 dx): mean time over `reps` calls.  The displacement is a
+    seeded field of amplitude 0.1 dx, so the nonlinear model's higher-order
+    terms are well inside its range."""
+    import torch
+
+    from paper_2105_06055_amd import binding
+    from paper_2105_06055_amd import workloads
+    dx = 1e-3
+    body = (nb, nb)
+    chi = workloads.random_mask(body, 44)
+    plan = binding.Plan((nfft, nfft), body, dx, 3 * dx, model=model, E=72e9, rho=2440.0, chiB=chi, dtype=dtype)
+    u = torch.tensor(workloads.random_field((2,) + body, 45, 0.1 * dx), dtype=dtype, device="cuda")
+    L = torch.empty_like(u)
+    for _ in range(max(1, warmup)):
+        plan.force(u, out=L)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.force(u, out=L)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    prof = ProfileSession(plan)
+    plan.force(u, out=L)
+    torch.cuda.synchronize()
+    passes = prof.read()
+    plan.close()
+    del u, L
+    torch.cuda.empty_cache()
+    return t, passes
+
+
 def run_energy(wl, dtype, nsteps):
     """nsteps EC Verlet steps from the workload's initial state with FP64
     energy accounting every step; returns the energy histories."""
@@ -286,6 +319,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-nbb", action="store_true", help="skip the 2D nonlinear bond-based force rate")
     ap.add_argument("--no-fft-variant", action="store_true",
                     help="skip the step timing with FFTs along all three axes")
     ap.add_argument("--no-energy", action="store_true", help="skip the 1000-step energy-drift runs")
@@ -346,6 +380,18 @@ def main():
               "fp64_force_ms": t64 * 1e3, "fp64_Gnode_s": w2.nodes / t64 / 1e9,
               "fp64_fft_grid_Gpoint_s": 256 ** 3 / t64 / 1e9}
         log(f"[bench] c2 {json.dumps(c2)}")
+    nbb = None
+    if not args.no_nbb:
+        nbb = {"workload": "2D plate 512^2 nodes with holes on a 1024^2 FFT grid, delta = 3 dx, "
+                           "displacement amplitude 0.1 dx (pd_force alone)"}
+        for model, tag in (("nbb", "nonlinear"), ("bb", "linear")):
+            for dt, dn in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+                t, ps = run_plate_force_rate(model, dt, args.steps, args.warmup)
+                nbb[f"{tag}_{dn}_force_ms"] = t * 1e3
+                nbb[f"{tag}_{dn}_Gnode_s"] = 512 * 512 / t / 1e9
+                if model == "nbb":
+                    nbb[f"{tag}_{dn}_passes"] = ps
+        log(f"[bench] nbb {json.dumps({k: v for k, v in nbb.items() if not k.endswith('passes')})}")
     energy = None
     if not args.no_energy:
         log(f"[bench] energy drift over {args.energy_steps} steps (FP32 and FP64)")
@@ -404,6 +450,7 @@ def main():
                 "finite": r32f["finite"], "passes": r32f["passes"]},
             "cg_time_to_1e-10": cg,
             "c2_force": c2,
+            "nonlinear_bb_plate_force": nbb,
             "energy_drift": energy,
         },
     }
