@@ -206,20 +206,20 @@ def run_force_rate(wl, dtype, reps, warmup):
     return t
 
 
-def run_plate_force_rate(model, dtype, reps, warmup, nb=512, nfft=1024):
-    """pd_force alone on the 2D plate (nb^2 body with holes on an nfft^2 grid,
-    delta = 3 dx): mean time over `reps` calls.  The displacement is a
-    seeded field of amplitude 0.1 dx, so the nonlinear model's higher-order
-    terms are well inside its range."""
+def run_plate_force_rate(model, dtype, reps, warmup, nb=512, nfft=1024, dim=2):
+    """pd_force alone on the 2D plate (nb^2 body with holes on an nfft^2 grid)
+    or the 3D block (nb^3 on nfft^3), delta = 3 dx: mean time over `reps`
+    calls.  The displacement is a seeded field of amplitude 0.1 dx, so the
+    nonlinear model's higher-order terms are well inside its range."""
     import torch
 
     from paper_2105_06055_amd import binding
     from paper_2105_06055_amd import workloads
     dx = 1e-3
-    body = (nb, nb)
+    body = (nb,) * dim
     chi = workloads.random_mask(body, 44)
-    plan = binding.Plan((nfft, nfft), body, dx, 3 * dx, model=model, E=72e9, rho=2440.0, chiB=chi, dtype=dtype)
-    u = torch.tensor(workloads.random_field((2,) + body, 45, 0.1 * dx), dtype=dtype, device="cuda")
+    plan = binding.Plan((nfft,) * dim, body, dx, 3 * dx, model=model, E=72e9, rho=2440.0, chiB=chi, dtype=dtype)
+    u = torch.tensor(workloads.random_field((dim,) + body, 45, 0.1 * dx), dtype=dtype, device="cuda")
     L = torch.empty_like(u)
     for _ in range(max(1, warmup)):
         plan.force(u, out=L)
@@ -382,8 +382,9 @@ def main():
         log(f"[bench] c2 {json.dumps(c2)}")
     nbb = None
     if not args.no_nbb:
-        nbb = {"workload": "2D plate 512^2 nodes with holes on a 1024^2 FFT grid, delta = 3 dx, "
-                           "displacement amplitude 0.1 dx (pd_force alone)"}
+        nbb = {"workload": "2D plate 512^2 nodes with holes on a 1024^2 FFT grid and 3D block 128^3 nodes "
+                           "with holes on a 256^3 grid, delta = 3 dx, displacement amplitude 0.1 dx "
+                           "(pd_force alone)"}
         for model, tag in (("nbb", "nonlinear"), ("bb", "linear")):
             for dt, dn in ((torch.float32, "fp32"), (torch.float64, "fp64")):
                 t, ps = run_plate_force_rate(model, dt, args.steps, args.warmup)
@@ -391,6 +392,12 @@ def main():
                 nbb[f"{tag}_{dn}_Gnode_s"] = 512 * 512 / t / 1e9
                 if model == "nbb":
                     nbb[f"{tag}_{dn}_passes"] = ps
+                # the 3D block: 128^3 nodes with holes on the 256^3 grid
+                t, ps = run_plate_force_rate(model, dt, args.steps, args.warmup, nb=128, nfft=256, dim=3)
+                nbb[f"{tag}_3d128_{dn}_force_ms"] = t * 1e3
+                nbb[f"{tag}_3d128_{dn}_Gnode_s"] = 128 ** 3 / t / 1e9
+                if model == "nbb":
+                    nbb[f"{tag}_3d128_{dn}_passes"] = ps
         log(f"[bench] nbb {json.dumps({k: v for k, v in nbb.items() if not k.endswith('passes')})}")
     energy = None
     if not args.no_energy:

@@ -57,7 +57,7 @@ typedef enum {
     PD_BB_LINEAR = 0,     /* linearized bond-based solid, Eq. 17-18 */
     PD_LPS_LINEAR = 1,    /* linearized state-based (LPS) solid, Eq. 33-39, 3D only */
     PD_BB_NONLINEAR = 2   /* nonlinear, rotation-invariant bond-based solid,
-                             Eq. 19-20 in the convolution form of Eq. 21-26, 2D;
+                             Eq. 19-20 in the convolution form of Eq. 21-26;
                              same micromodulus constant alpha as PD_BB_LINEAR
                              (it is the small-displacement limit); pd_force only,
                              PD_WEIGHT_NONE */
@@ -134,7 +134,7 @@ typedef struct {
  * embedded-constraint fields (C*chi_B, a*chi_B, m; Eq. 56, 92-94, 97) and
  * allocates workspaces.  Returns PD_EINVAL for inconsistent sizes or
  * padding smaller than the horizon, PD_EUNSUPPORTED for the LPS model in 2D,
- * the nonlinear bond-based model in 3D or with weights, or grid lengths
+ * the nonlinear bond-based model with weights, or grid lengths
  * outside the supported set, PD_ENOMEM / PD_EDEVICE on HIP failures.  On
  * error *out is NULL.  Plans of the nonlinear bond-based model serve
  * pd_force (without W_out) only; the other operations return

@@ -21,7 +21,7 @@ from .build import LIB
 
 PD_OK, PD_EINVAL, PD_ENOMEM, PD_EDEVICE, PD_ENOTCONV, PD_ENUMERIC, PD_EUNSUPPORTED = range(7)
 _WEIGHTS = {"none": 0, "integrity": 1, "scale": 2}
-_MODELS = {"bb": 0, "lps": 1, "nbb": 2}   # nbb: nonlinear bond-based (Eq. 19-26), 2D, pd_force only
+_MODELS = {"bb": 0, "lps": 1, "nbb": 2}   # nbb: nonlinear bond-based (Eq. 19-26), pd_force only
 
 
 class PDError(RuntimeError):

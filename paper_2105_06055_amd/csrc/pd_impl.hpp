@@ -306,7 +306,10 @@ pd_status launch_lastmul(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, con
                          int ntap, int nct, uint32_t oddmask, hipStream_t st) {
     const int Tn = ln.N / 8;
     ProfScope ps(p, st);
-    constexpr bool direct_ok = !M::RT_ODD && !is_nonlocal<M>::value;
+    // the direct line correlation holds 4 points of every input and output
+    // per lane: beyond 16 fields in FP64 it spills heavily (13 + 13: 8.6 ms
+    // against 2.4 ms for the transform form on the 128^3 block)
+    constexpr bool direct_ok = !M::RT_ODD && !is_nonlocal<M>::value && !(sizeof(T) == 8 && M::NIN + M::NOUT > 16);
     int path = 2;   // 0 direct, 1 specialised FFT, 2 generic FFT
     if constexpr (direct_ok) {
         if ((p->lastaxis == PD_LASTAXIS_AUTO || p->lastaxis == PD_LASTAXIS_YFFT) && taps_d && ntap >= 2 && ntap <= 5)
@@ -904,7 +907,11 @@ pd_status plan_alloc(pd_plan p, hipStream_t st, const uint8_t* chiB_h, const uin
         // unweighted bond-based: force (D) or force+energy (D+1+nsym)
         capA = std::max(capA, D + 1 + nsym(D));
     }
-    if (p->kern.model == PD_BB_NONLINEAR) capA = std::max(capA, 2 * D + 1 + nsym(D));   // 2D: 8 inputs, 8 outputs
+    if (p->kern.model == PD_BB_NONLINEAR) {
+        // 8 inputs and 8 outputs in 2D, 13 and 13 in 3D (y transform path)
+        capA = std::max(capA, 2 * D + 1 + nsym(D));
+        if (D == 3) capB = std::max(capB, 2 * D + 1 + nsym(D));
+    }
     p->saf_cap = capA;
     p->sbf_cap = std::max(capB, capC);
     p->scf_cap = 0;
@@ -943,7 +950,7 @@ inline pd_status plan_create_impl(const pd_grid* grid, const pd_horizon* hz, con
     if (kern->model == PD_LPS_LINEAR && D != 3) return PD_EUNSUPPORTED;
     if (kern->model != PD_BB_LINEAR && kern->model != PD_LPS_LINEAR && kern->model != PD_BB_NONLINEAR)
         return PD_EINVAL;
-    if (kern->model == PD_BB_NONLINEAR && (D != 2 || kern->weight != PD_WEIGHT_NONE || (flags & PD_PLAN_MIXED)))
+    if (kern->model == PD_BB_NONLINEAR && (kern->weight != PD_WEIGHT_NONE || (flags & PD_PLAN_MIXED)))
         return PD_EUNSUPPORTED;
     if (kern->model == PD_LPS_LINEAR && kern->weight != PD_WEIGHT_NONE) return PD_EUNSUPPORTED;
     if (dtype != PD_F32 && dtype != PD_F64) return PD_EINVAL;
@@ -1064,15 +1071,19 @@ pd_status force_impl(pd_plan p, const T* u, const void* weight, T* L, T* W, hipS
         return run_chain<T>(p, gB, mB, fB, st, 3);
     }
     if (p->kern.model == PD_BB_NONLINEAR) {
-        if (W || p->dim != 2) return PD_EUNSUPPORTED;
-        GenNBB<T, 2> gg{};
-        gg.c = ctx<T>(p);
-        gg.u = u;
-        FinNBB<T, 2> ff{};
-        ff.c = ctx<T>(p);
-        ff.u = u;
-        ff.L = L;
-        return run_chain<T>(p, gg, MulNBB<T, 2>{}, ff, st);
+        if (W) return PD_EUNSUPPORTED;
+        auto nbb = [&](auto Dc) -> pd_status {
+            constexpr int DD = decltype(Dc)::value;
+            GenNBB<T, DD> gg{};
+            gg.c = ctx<T>(p);
+            gg.u = u;
+            FinNBB<T, DD> ff{};
+            ff.c = ctx<T>(p);
+            ff.u = u;
+            ff.L = L;
+            return run_chain<T>(p, gg, MulNBB<T, DD>{}, ff, st);
+        };
+        return p->dim == 2 ? nbb(std::integral_constant<int, 2>{}) : nbb(std::integral_constant<int, 3>{});
     }
     // bond-based
     auto go = [&](auto Dc) -> pd_status {

@@ -1,8 +1,9 @@
 """The nonlinear rotation-invariant bond-based model (Sec. 3.2, Eq. 19-26)
 through pd_force against the oracle's bond-by-bond Eq. 19: masked ragged
-plates at horizons of 3 and 4 spacings with displacements large enough for
-the quadratic and cubic terms to matter, a finite rigid rotation (zero
-force), and the full 512^2 plate on sampled nodes.
+plates at horizons of 3 and 4 spacings and masked 3D boxes at 2 and 3, with
+displacements large enough for the quadratic and cubic terms to matter, a
+finite rigid rotation (zero force) in 2D and 3D, and the full 512^2 plate
+on sampled nodes.
 
 Bar: FP64 relative L2 error <= 1e-12; FP32 error normalised by
 lambda_max |u| (1 + |u|_inf/dx)^2 (the operator scale, grown by the
@@ -80,10 +81,8 @@ def test_nbb2d_rigid_rotation_zero_force(orc, dtype):
 
 
 def test_nbb_plan_scope():
-    """The nonlinear model serves pd_force only, in 2D, without weights."""
+    """The nonlinear model serves pd_force only, without weights."""
     from paper_2105_06055_amd import binding
-    with pytest.raises(RuntimeError):
-        binding.Plan((32, 32, 32), (20, 20, 20), 1e-3, 3e-3, model="nbb")
     with pytest.raises(RuntimeError):
         binding.Plan((64, 64), (40, 40), 1e-3, 3e-3, model="nbb", weight="scale")
     plan = binding.Plan((64, 64), (40, 40), 1e-3, 3e-3, model="nbb", dtype=torch.float64)
@@ -124,4 +123,39 @@ def test_nbb2d_plate_512_sampled(orc, dtype):
         lam = 2440.0 * (2.0 / plan.info["dt_max"]) ** 2
         scale = lam * np.abs(u).max() * (1 + np.abs(u).max() / dx) ** 2
         assert np.abs(got - ref).max() <= 1e-5 * scale
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", DT)
+@pytest.mark.parametrize("body,fft,m,amp", [((20, 23, 17), (32, 32, 32), 2, 0.2), ((12, 30, 21), (16, 64, 32), 3, 0.1)])
+def test_nbb3d_masked(orc, dtype, body, fft, m, amp):
+    dx = 1e-3
+    chi = wl.random_mask(body, 47)
+    u = wl.random_field((3,) + body, 48, amp * dx)
+    plan = _plan(fft, body, dx, m, chi, dtype)
+    L = plan.force(_dev(u, dtype)).cpu().numpy()
+    g = orc.geom(body, dx, m * dx)
+    alpha = orc.bb_alpha(3, 72e9, m * dx)
+    Lo = orc.nbb_force(g, alpha, chi.astype(float), u)
+    _check(L, Lo, u, plan, dx, dtype)
+    Lb = orc.bb_force(g, alpha, chi.astype(float), u)
+    assert np.linalg.norm(Lo - Lb) >= 1e-2 * np.linalg.norm(Lo)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", DT)
+def test_nbb3d_rigid_rotation_zero_force(orc, dtype):
+    body, fft, dx, m = (14, 17, 19), (32, 32, 32), 1e-3, 3
+    chi = wl.random_mask(body, 49)
+    z, y, x = np.meshgrid(*[np.arange(n) * dx for n in body], indexing="ij")
+    X = np.stack([x, y, z])
+    q, _ = np.linalg.qr(np.random.default_rng(50).normal(size=(3, 3)))
+    R = q if np.linalg.det(q) > 0 else -q
+    u = np.einsum("ij,j...->i...", R - np.eye(3), X) + 0.2 * dx
+    plan = _plan(fft, body, dx, m, chi, dtype)
+    L = plan.force(_dev(u, dtype)).cpu().numpy()
+    lam = 2440.0 * (2.0 / plan.info["dt_max"]) ** 2
+    err = np.abs(L).max() / (lam * np.abs(u).max() * (1 + np.abs(u).max() / dx) ** 2)
+    print(f"3D rigid rotation, {dtype}: max |L| / operator scale = {err:.2e}")
+    assert err <= (1e-13 if dtype == torch.float64 else 1e-6)
     plan.close()
