@@ -84,11 +84,14 @@ __global__ void k_taps(int dim, int n1, int n2, int h1, long NP, int ntap, int n
 //   tau_c(kx; a, b) = sc * sum_{o in S, o_y = a, o_z = b} K_c(o) trig_{p_cx}(2 pi kx o_x / n1)
 // for a, b >= 0, a^2 + b^2 <= MT^2 (tap u = yz_tap(MT, a, b)); sc = 1/n1,
 // the normalisation of the unnormalised x transform pair.  The taps at
-// negative o_y, o_z follow from the parities of K_c.  Layout [kx][c][u].
+// negative o_y, o_z follow from the parities of K_c.  Layout [kx][c][u],
+// with nx extra components after the nct ones (scaled copies, so that a
+// constant factor of a multiplier term is folded into its taps).
 template <class T>
 __global__ void k_taps_yz(int n1, int h1, int MT, int nu, int ns, const int* __restrict__ offs,
                           const double* __restrict__ kval, int kstride, int nct, const uint8_t* __restrict__ par,
-                          const double* __restrict__ tw64, double sc, T* __restrict__ taps) {
+                          const double* __restrict__ tw64, double sc, int nx, int x0, double xs,
+                          T* __restrict__ taps) {
     long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)h1 * nu) return;
     const int kx = (int)(idx / nu), u = (int)(idx % nu);
@@ -106,7 +109,10 @@ __global__ void k_taps_yz(int n1, int h1, int MT, int nu, int ns, const int* __r
         const double cxv = twx[2 * ex], sxv = -twx[2 * ex + 1];
         for (int c = 0; c < nct; ++c) acc[c] += kval[(long)s * kstride + c] * (par[3 * c] ? sxv : cxv);
     }
-    for (int c = 0; c < nct; ++c) taps[((long)kx * nct + c) * nu + u] = T(acc[c] * sc);
+    // nx extra components: xs times components x0 .. x0+nx-1 (LPS: k_a a0_i)
+    const int nall = nct + nx;
+    for (int c = 0; c < nct; ++c) taps[((long)kx * nall + c) * nu + u] = T(acc[c] * sc);
+    for (int c = 0; c < nx; ++c) taps[((long)kx * nall + nct + c) * nu + u] = T(acc[x0 + c] * sc * xs);
 }
 
 // Static embedded-constraint fields by direct quadrature over the horizon
@@ -398,7 +404,7 @@ pd_status launch_yzconv_t(pd_plan p, const M& mul, int in_off, int out_off, hipS
     a.zc = zc;
     a.nzc = (g.b3 + zc - 1) / zc;
     a.in_off = in_off; a.out_off = out_off;
-    a.nct = p->nct;
+    a.nct = p->nct_yz;
     const long nblk = tiles * a.nzc;
     const size_t lds = (size_t)2 * M::NIN * (YT + 2 * MT) * sizeof(cx<T>);
     if (lds > (size_t)p->max_lds || nblk > 0x7fffffffL) return PD_EUNSUPPORTED;
@@ -506,7 +512,7 @@ pd_status launch_ytrans(pd_plan p, int F, int fb, hipStream_t st) {
 
 // Pass 5 (+ deterministic reduction into p->red when F::NRED > 0)
 template <class T, class F, int LG>
-pd_status launch_xinv_lg(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st) {
+pd_status launch_xinv_lg(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st, cx<T>* SAout = nullptr) {
     const Geo& g = p->geo;
     const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
     if (LG > 0 && Tc * Lt != xblock_threads<T>()) return PD_EUNSUPPORTED;
@@ -518,11 +524,14 @@ pd_status launch_xinv_lg(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t s
     if (F::NRED > 0 && nblk * F::NRED > p->partials_cap) return PD_EINVAL;
     allow_lds(k_xinv<T, F, LG>, lds);
     ProfScope ps(p, st);
-    hipLaunchKernelGGL((k_xinv<T, F, LG>), grid, block, lds, st, g, fin, SA, p->partials, TWp<T>(p));
+    constexpr int NCH = fin_chain_n<F>::value;
+    if (NCH > 0 && !SAout) return PD_EINVAL;
+    hipLaunchKernelGGL((k_xinv<T, F, LG>), grid, block, lds, st, g, fin, SA, p->partials, TWp<T>(p), SAout);
     if (p->prof) {
         char nm[32];
-        std::snprintf(nm, sizeof nm, "xinv_%d", F::NOUT);
-        ps.done(nm, fin.nbytes() * (double)g.nb + (double)F::NOUT * g.b3 * g.h1 * g.b2 * sizeof(cx<T>));
+        if (NCH > 0) std::snprintf(nm, sizeof nm, "xinvfwd_%d_%d", F::NOUT, NCH);
+        else std::snprintf(nm, sizeof nm, "xinv_%d", F::NOUT);
+        ps.done(nm, fin.nbytes() * (double)g.nb + (double)(F::NOUT + NCH) * g.b3 * g.h1 * g.b2 * sizeof(cx<T>));
     }
     PD_TRY(pdh::check(hipGetLastError()));
     if (F::NRED > 0) {
@@ -532,9 +541,10 @@ pd_status launch_xinv_lg(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t s
     return PD_OK;
 }
 template <class T, class F>
-pd_status launch_xinv(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st) {
-    if (p->geo.Nc == (1 << kFastLgX) && p->geo.b1 <= p->geo.Nc) return launch_xinv_lg<T, F, kFastLgX>(p, fin, SA, st);
-    return launch_xinv_lg<T, F, 0>(p, fin, SA, st);
+pd_status launch_xinv(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st, cx<T>* SAout = nullptr) {
+    if (p->geo.Nc == (1 << kFastLgX) && p->geo.b1 <= p->geo.Nc)
+        return launch_xinv_lg<T, F, kFastLgX>(p, fin, SA, st, SAout);
+    return launch_xinv_lg<T, F, 0>(p, fin, SA, st, SAout);
 }
 
 // One full chain.  3D: sb_off is the SB field slot the generator's fields go
@@ -794,12 +804,15 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
         if (fits) {
             p->yz_mt = mt;
             p->yz_nu = yz_ntap(mt);
+            // LPS: three more components, k_a a0_i, for the force stage's k_a term
+            const int nx = (p->kern.model == PD_LPS_LINEAR) ? 3 : 0;
+            p->nct_yz = nct + nx;
             const long n = (long)g.h1 * p->yz_nu;
-            HIP_TRY(hipMalloc(&p->taps_yz, sizeof(T) * n * nct));
-            p->bytes += sizeof(T) * n * nct;
+            HIP_TRY(hipMalloc(&p->taps_yz, sizeof(T) * n * p->nct_yz));
+            p->bytes += sizeof(T) * n * p->nct_yz;
             hipLaunchKernelGGL((k_taps_yz<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.n1, g.h1, mt,
                                p->yz_nu, ns, p->offs_dev, p->kval_dev, ncs, nct, par_dev, p->tw64,
-                               1.0 / (double)g.n1, reinterpret_cast<T*>(p->taps_yz));
+                               1.0 / (double)g.n1, nx, 6, p->ka, reinterpret_cast<T*>(p->taps_yz));
             HIP_TRY(hipGetLastError());
         }
     }
@@ -1040,6 +1053,34 @@ inline pd_status plan_create_impl(const pd_grid* grid, const pd_horizon* hz, con
 }
 
 // ------------------------------------------------------------------ force
+// The two LPS chains: the dilatation (generator gA, epilogue fA writing
+// theta) and the force (multiplier mB, epilogue fB).  With the (y, z) pass
+// the dilatation's c2r and the force stage's r2c of chi theta run as one
+// pass (FinThetaChain): x transform of chi u -> SA 0..2, (y, z) dilatation
+// -> SA 4, c2r + theta + r2c -> SA 3, (y, z) force stage SA 0..3 -> SA
+// 4..6, c2r + epilogue.
+template <class T, class GA, class FB>
+pd_status run_lps(pd_plan p, const GA& gA, const FinTheta<T>& fA, const MulLPSB<T>& mB, const FB& fB,
+                  hipStream_t st) {
+    if (use_yz<T, MulLPSA<T>>(p) && use_yz<T, MulLPSB<T>>(p)) {
+        const Geo& g = p->geo;
+        cx<T>* SA = SAp<T>(p);
+        if (p->saf_cap < 7) return PD_EINVAL;
+        PD_TRY(launch_xfwd<T>(p, gA, SA, st));
+        PD_TRY((launch_yzconv<T, MulLPSA<T>>(p, MulLPSA<T>{}, 0, 4, st)));
+        FinThetaChain<T> fc{};
+        static_cast<FinTheta<T>&>(fc) = fA;
+        PD_TRY(launch_xinv<T>(p, fc, SA + 4 * g.saf, st, SA + 3 * g.saf));
+        PD_TRY((launch_yzconv<T, MulLPSB<T>>(p, mB, 0, 4, st)));
+        return launch_xinv<T>(p, fB, SA + 4 * g.saf, st);
+    }
+    PD_TRY(run_chain<T>(p, gA, MulLPSA<T>{}, fA, st, 0, 3));
+    GenTheta<T> gB{};
+    gB.c = ctx<T>(p);
+    gB.theta = fA.theta;
+    return run_chain<T>(p, gB, mB, fB, st, 3);
+}
+
 template <class T>
 pd_status force_impl(pd_plan p, const T* u, const void* weight, T* L, T* W, hipStream_t st) {
     const int D = p->dim;
@@ -1055,11 +1096,7 @@ pd_status force_impl(pd_plan p, const T* u, const void* weight, T* L, T* W, hipS
         fA.c = ctx<T>(p);
         fA.u = u;
         fA.theta = reinterpret_cast<T*>(p->theta);
-        PD_TRY(run_chain<T>(p, gA, MulLPSA<T>{}, fA, st, 0, 3));
         // stage B: force
-        GenTheta<T> gB{};
-        gB.c = ctx<T>(p);
-        gB.theta = reinterpret_cast<const T*>(p->theta);
         MulLPSB<T> mB{};
         mB.ka = T(p->ka);
         FinLin<T, 3, 0, false, true> fB{};
@@ -1068,7 +1105,7 @@ pd_status force_impl(pd_plan p, const T* u, const void* weight, T* L, T* W, hipS
         fB.u = u;
         fB.theta = reinterpret_cast<const T*>(p->theta);
         fB.L = L;
-        return run_chain<T>(p, gB, mB, fB, st, 3);
+        return run_lps<T>(p, gA, fA, mB, fB, st);
     }
     if (p->kern.model == PD_BB_NONLINEAR) {
         if (W) return PD_EUNSUPPORTED;
@@ -1309,10 +1346,6 @@ pd_status lin_apply(pd_plan p, const T* x, T* out, const T* b, hipStream_t st) {
         fA.c = ctx<T>(p);
         fA.u = x;
         fA.theta = reinterpret_cast<T*>(p->theta);
-        PD_TRY(run_chain<T>(p, gA, MulLPSA<T>{}, fA, st, 0, 3));
-        GenTheta<T> gB{};
-        gB.c = ctx<T>(p);
-        gB.theta = reinterpret_cast<const T*>(p->theta);
         MulLPSB<T> mB{};
         mB.ka = T(p->ka);
         FinLin<T, 3, MODE, false, true> fB{};
@@ -1322,7 +1355,7 @@ pd_status lin_apply(pd_plan p, const T* x, T* out, const T* b, hipStream_t st) {
         fB.theta = reinterpret_cast<const T*>(p->theta);
         fB.L = out;
         fB.b = b;
-        return run_chain<T>(p, gB, mB, fB, st, 3);
+        return run_lps<T>(p, gA, fA, mB, fB, st);
     }
     auto go = [&](auto Dc) -> pd_status {
         constexpr int DD = decltype(Dc)::value;
@@ -1380,17 +1413,13 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, hipSt
         fA.c = ctx<T>(p);
         fA.u = u;
         fA.theta = reinterpret_cast<T*>(p->theta);
-        PD_TRY(run_chain<T>(p, gA, MulLPSA<T>{}, fA, st, 0, 3));
-        GenTheta<T> gB{};
-        gB.c = ctx<T>(p);
-        gB.theta = reinterpret_cast<const T*>(p->theta);
         MulLPSB<T> mB{};
         mB.ka = T(p->ka);
         FinLin<T, 3, 1, ENRED, true> fB{};
         fB.c = ctx<T>(p);
         fB.ka = T(p->ka); fB.u = u; fB.theta = reinterpret_cast<const T*>(p->theta);
         fB.v = v; fB.F = F; fB.b = b; fB.c1 = c1; fB.rho = rho;
-        return run_chain<T>(p, gB, mB, fB, st, 3);
+        return run_lps<T>(p, gA, fA, mB, fB, st);
     }
     auto go = [&](auto Dc) -> pd_status {
         constexpr int DD = decltype(Dc)::value;

@@ -492,9 +492,16 @@ struct MulLPSB {
     static constexpr uint32_t ODD = (1u << 2) | (1u << 4) | (1u << 8);
     __device__ __forceinline__ T ka_value() const { return ka; }
     static constexpr int DIM = 3;
-    __host__ __device__ static constexpr int par3(int c) { return c < 6 ? sym_par(3, c) : 1 << (c - 6); }
+    // components: C_ij (0..5), a0_i (6..8); in the (y, z) taps also k_a a0_i (9..11)
+    __host__ __device__ static constexpr int par3(int c) {
+        return c < 6 ? sym_par(3, c) : 1 << (c < 9 ? c - 6 : c - 9);
+    }
     __host__ __device__ static constexpr DTerm dterm(int O, int J) {
         return J < 3 ? DTerm{symi(3, O, J), O == J ? 1 : -1, 0, false} : DTerm{6 + O, 1, 1, true};
+    }
+    // the (y, z) pass reads k_a a0_i from the scaled components instead
+    __host__ __device__ static constexpr DTerm dterm_yz(int O, int J) {
+        return J < 3 ? dterm(O, J) : DTerm{9 + O, 1, 1, false};
     }
     T ka;
     template <int O>
@@ -947,12 +954,30 @@ struct FinTheta {
         Q.chiB = cb;
         return Q;
     }
-    __device__ __forceinline__ void fin(Nd i, const Ld& Q, const T (&val)[1], double*) const {
-        T acc = val[0];
+    __device__ __forceinline__ T value(const Ld& Q, T S) const {
+        T acc = S;
 #pragma unroll
         for (int d = 0; d < 3; ++d) acc -= Q.g[d] * Q.u[d];
         const bool on = Q.chiB && Q.m != T(0);
-        stf(theta, i, on ? T(3) / (on ? Q.m : T(1)) * acc : T(0));
+        return on ? T(3) / (on ? Q.m : T(1)) * acc : T(0);
+    }
+    __device__ __forceinline__ void fin(Nd i, const Ld& Q, const T (&val)[1], double*) const {
+        stf(theta, i, value(Q, val[0]));
+    }
+};
+
+// The dilatation stage's epilogue chained to the force stage's generator:
+// theta stored as by FinTheta and also handed on (chi theta = theta, zero off
+// the body) for the r2c of the force stage in the same pass.
+template <class T>
+struct FinThetaChain : FinTheta<T> {
+    static constexpr int NCHAIN = 1;
+    __host__ double nbytes() const { return FinTheta<T>::nbytes(); }
+    __device__ __forceinline__ void fin_chain(Nd i, const typename FinTheta<T>::Ld& Q, const T (&val)[1], double*,
+                                              T (&next)[1]) const {
+        const T th = this->value(Q, val[0]);
+        stf(this->theta, i, th);
+        next[0] = th;
     }
 };
 

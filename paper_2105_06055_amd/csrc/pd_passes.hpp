@@ -96,72 +96,20 @@ __device__ __forceinline__ void block_reduce_store(double (&red)[NR], double* ou
     }
 }
 
-// ----------------------------------------------------------------------------
-// Pass 1: generator + r2c along x + transposed store.
-// grid (ceil(b2/Lt), b3), block Tc*Lt, Tc = Nc/8; dynamic LDS Lt*(Nc+2) complex.
-// LG > 0 fixes Nc = 2^LG at compile time (the runtime g.Nc must match).
-template <class T, class G, int LG>
-__global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ SA,
-                                               const cx<T>* __restrict__ twb) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-    constexpr int NF = G::NIN, NG = 4;
-    const int lgNc = LG > 0 ? LG : 31 - __clz(g.Nc), Nc = 1 << lgNc, Tc = Nc >> 3;
-    const int nthr = LG > 0 ? xblock_threads<T>() : (int)blockDim.x;
-    const int Lt = nthr / Tc;
+// r2c along x of NF real fields held in the flat node mapping (thread tid
+// holds nodes tid + nthr r of the block's run, r < RN) and transposed store
+// into SA (field f at SA + f*saf).  The twiddles of length n1 must be staged
+// in LDS after the Lt row buffers; every LDS use is fenced here.
+template <class T, int NF, int RN>
+__device__ __forceinline__ void r2c_store(const Geo& g, const T (&gv)[NF][RN], cx<T>* __restrict__ SA, cx<T>* lds,
+                                          int lgNc, int nthr, int nval) {
+    const int Nc = 1 << lgNc, Tc = Nc >> 3, Lt = nthr / Tc;
     const int tid = threadIdx.x, j = tid % Tc, l = tid / Tc;
     const int z = blockIdx.y;
     const int y0 = blockIdx.x * Lt;
-    const int y = y0 + l;
-    const bool rowok = y < g.b2;
+    const bool rowok = y0 + l < g.b2;
     const int pitch = row_pitch(Nc);
-    // The block's rows y0 .. y0+Lt-1 are consecutive in node order, so its
-    // body nodes form one run [nbase, nbase + nval).  The generator runs over
-    // that run with consecutive threads on consecutive nodes (coalesced
-    // loads and stores); its values reach the FFT layout (thread j holds the
-    // x pairs 2(j + Tc q), +1) through a flat [Lt][b1] staging area that
-    // overlays the row buffers.  Nodes per thread: Lt*b1/nthr = 8 b1/Nc,
-    // at most 8 when b1 <= Nc (required for LG > 0), else at most 16.
-    constexpr int RN = LG > 0 ? 8 : 16;
-    const long nbase = ((long)z * g.b2 + y0) * g.b1;
-    const int nval = min(Lt, g.b2 - y0) * g.b1;
-    T gv[NF][RN];
-    // Node slots in groups of NG: all loads of a group are issued
-    // before its first store (a store may alias any later load, so a
-    // read-modify-write generator would otherwise wait out one memory latency
-    // per slot).  A full block takes a branch-free path.
-    auto run_gen = [&](auto full) {
-        uint8_t cbv[RN];
-#pragma unroll
-        for (int r = 0; r < RN; ++r) {
-            const int e = tid + nthr * r;
-            cbv[r] = (decltype(full)::value || e < nval) ? node_flags(gen, Nd{nbase, (uint32_t)e}) : uint8_t(0);
-        }
-#pragma unroll
-        for (int r0 = 0; r0 < RN; r0 += NG) {
-            typename G::Ld ld[NG];
-#pragma unroll
-            for (int q = 0; q < NG; ++q) {
-                const int e = tid + nthr * (r0 + q);
-                if (decltype(full)::value || e < nval) ld[q] = gen.load(Nd{nbase, (uint32_t)e}, cbv[r0 + q]);
-            }
-#pragma unroll
-            for (int q = 0; q < NG; ++q) {
-                const int e = tid + nthr * (r0 + q);
-                T a[NF];
-#pragma unroll
-                for (int f = 0; f < NF; ++f) a[f] = T(0);
-                if (decltype(full)::value || e < nval) gen.gen(Nd{nbase, (uint32_t)e}, ld[q], a);
-#pragma unroll
-                for (int f = 0; f < NF; ++f) gv[f][r0 + q] = a[f];
-            }
-        }
-    };
-    if (nval == RN * nthr) run_gen(std::true_type{});
-    else run_gen(std::false_type{});
-    // twiddles of length n1 in LDS after the rows; W_Nc^e = W_n1^(2e)
     cx<T>* twn1 = lds + Lt * pitch;
-    stage_twiddles(twn1, twb, g.n1);
     cx<T>* row = lds + l * pitch;
     lds_ptr<cx<T>> rowv = as_lds(row);
     lds_ptr<cx<T>> ldsv = as_lds(lds);
@@ -219,6 +167,72 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
             if (kk == 0) dst[(long)Nc * g.P2] = ldsv[ll * pitch + Nc];
         }
     }
+}
+
+
+// ----------------------------------------------------------------------------
+// Pass 1: generator + r2c along x + transposed store.
+// grid (ceil(b2/Lt), b3), block Tc*Lt, Tc = Nc/8; dynamic LDS Lt*(Nc+2) complex.
+// LG > 0 fixes Nc = 2^LG at compile time (the runtime g.Nc must match).
+template <class T, class G, int LG>
+__global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ SA,
+                                               const cx<T>* __restrict__ twb) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+    constexpr int NF = G::NIN, NG = 4;
+    const int lgNc = LG > 0 ? LG : 31 - __clz(g.Nc), Nc = 1 << lgNc, Tc = Nc >> 3;
+    const int nthr = LG > 0 ? xblock_threads<T>() : (int)blockDim.x;
+    const int Lt = nthr / Tc;
+    const int tid = threadIdx.x;
+    const int z = blockIdx.y;
+    const int y0 = blockIdx.x * Lt;
+    // The block's rows y0 .. y0+Lt-1 are consecutive in node order, so its
+    // body nodes form one run [nbase, nbase + nval).  The generator runs over
+    // that run with consecutive threads on consecutive nodes (coalesced
+    // loads and stores); its values reach the FFT layout (thread j holds the
+    // x pairs 2(j + Tc q), +1) through a flat [Lt][b1] staging area that
+    // overlays the row buffers.  Nodes per thread: Lt*b1/nthr = 8 b1/Nc,
+    // at most 8 when b1 <= Nc (required for LG > 0), else at most 16.
+    constexpr int RN = LG > 0 ? 8 : 16;
+    const long nbase = ((long)z * g.b2 + y0) * g.b1;
+    const int nval = min(Lt, g.b2 - y0) * g.b1;
+    T gv[NF][RN];
+    // Node slots in groups of NG: all loads of a group are issued
+    // before its first store (a store may alias any later load, so a
+    // read-modify-write generator would otherwise wait out one memory latency
+    // per slot).  A full block takes a branch-free path.
+    auto run_gen = [&](auto full) {
+        uint8_t cbv[RN];
+#pragma unroll
+        for (int r = 0; r < RN; ++r) {
+            const int e = tid + nthr * r;
+            cbv[r] = (decltype(full)::value || e < nval) ? node_flags(gen, Nd{nbase, (uint32_t)e}) : uint8_t(0);
+        }
+#pragma unroll
+        for (int r0 = 0; r0 < RN; r0 += NG) {
+            typename G::Ld ld[NG];
+#pragma unroll
+            for (int q = 0; q < NG; ++q) {
+                const int e = tid + nthr * (r0 + q);
+                if (decltype(full)::value || e < nval) ld[q] = gen.load(Nd{nbase, (uint32_t)e}, cbv[r0 + q]);
+            }
+#pragma unroll
+            for (int q = 0; q < NG; ++q) {
+                const int e = tid + nthr * (r0 + q);
+                T a[NF];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) a[f] = T(0);
+                if (decltype(full)::value || e < nval) gen.gen(Nd{nbase, (uint32_t)e}, ld[q], a);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) gv[f][r0 + q] = a[f];
+            }
+        }
+    };
+    if (nval == RN * nthr) run_gen(std::true_type{});
+    else run_gen(std::false_type{});
+    // twiddles of length n1 in LDS after the rows; W_Nc^e = W_n1^(2e)
+    stage_twiddles(lds + Lt * row_pitch(Nc), twb, g.n1);
+    r2c_store<T, NF, RN>(g, gv, SA, lds, lgNc, nthr, nval);
 }
 
 // Output O of the spectral multiply for the 8 wavenumbers of thread j along
@@ -730,8 +744,8 @@ k_lastconv(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps, int nct) {
 // forms its y-neighbour sums and differences there; the plane's
 // contributions go into the accumulators of the 2 MT + 1 output planes it
 // reaches (a register ring), and an output plane is stored as soon as its
-// last input plane is in.  The inputs of the next plane are loaded before
-// the arithmetic of the current one.  Outputs go to other SA fields than the
+// last input plane is in.  The inputs are loaded two planes ahead of the
+// arithmetic (two register sets).  Outputs go to other SA fields than the
 // inputs (neighbouring chunks read each other's planes).
 struct YZArgs {
     int b2, b3, h1, P2;
@@ -763,12 +777,24 @@ __host__ __device__ constexpr int yz_factor(DTerm t) {
     return e == 0 ? t.coef : -t.coef;   // e is 0 or 2 for a real-space kernel
 }
 
+// The term of output O and input J in the (y, z) pass: dterm_yz when the
+// multiplier has one (constant factors folded into extra tap components).
+template <class M, class = void>
+struct has_dterm_yz : std::false_type {};
+template <class M>
+struct has_dterm_yz<M, std::void_t<decltype(M::dterm_yz(0, 0))>> : std::true_type {};
+template <class M>
+__host__ __device__ constexpr DTerm yz_dterm(int O, int J) {
+    if constexpr (has_dterm_yz<M>::value) return M::dterm_yz(O, J);
+    else return M::dterm(O, J);
+}
+
 // Whether output O has a term of an input in [J0, J1) whose component has
 // z-parity G.
 template <class M, int O, int G, int J0, int J1>
 __host__ __device__ constexpr bool yz_group_used() {
     for (int J = J0; J < J1; ++J) {
-        const DTerm t = M::dterm(O, J);
+        const DTerm t = yz_dterm<M>(O, J);
         if (t.coef != 0 && ((M::par3(t.c) >> 2) & 1) == G) return true;
     }
     return false;
@@ -923,7 +949,7 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
                                     cx<T> q = {T(0), T(0)};
                                     OutLoop<J0, J1>::run([&](auto Jc) {
                                         constexpr int J = decltype(Jc)::value;
-                                        constexpr DTerm tm = M::dterm(O, J);
+                                        constexpr DTerm tm = yz_dterm<M>(O, J);
                                         if constexpr (tm.coef != 0 && ((M::par3(tm.c) >> 2) & 1) == G) {
                                             yz_term<T, MT, NU, tm.c, M::par3(tm.c), yz_factor<M>(tm), tm.ka, b>(
                                                 q, tk, pe[J - J0], po[J - J0], ka);
@@ -1071,10 +1097,18 @@ __global__ void __launch_bounds__(1024) k_yti(Geo g, const cx<T>* __restrict__ S
 // Pass 5: transposed load of body rows from SA, c2r along x, epilogue.
 // grid (ceil(b2/Lt), b3), block Tc*Lt; LDS Lt*(Nc+2) complex + reduction.
 // partials: per block NRED doubles at (blockIdx.y*gridDim.x + blockIdx.x)*NRED.
+// An epilogue with NCHAIN > 0 also returns NCHAIN values per node (fin_chain),
+// which the pass transforms forward again (r2c) and stores to SAout: the c2r
+// of one chain and the r2c of the next in one pass over the block's rows.
+template <class F, class = void>
+struct fin_chain_n : std::integral_constant<int, 0> {};
+template <class F>
+struct fin_chain_n<F, std::void_t<decltype(F::NCHAIN)>> : std::integral_constant<int, F::NCHAIN> {};
+
 template <class T, class F, int LG>
 __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restrict__ SA,
                                                double* __restrict__ partials,
-                                               const cx<T>* __restrict__ twb) {
+                                               const cx<T>* __restrict__ twb, cx<T>* __restrict__ SAout) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int NO = F::NOUT, NG = node_group<T>();
@@ -1170,6 +1204,12 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     double red[F::NRED > 0 ? F::NRED : 1];
 #pragma unroll
     for (int r = 0; r < (F::NRED > 0 ? F::NRED : 1); ++r) red[r] = 0.0;
+    constexpr int NCH = fin_chain_n<F>::value;
+    T chv[NCH > 0 ? NCH : 1][RN];
+#pragma unroll
+    for (int c = 0; c < (NCH > 0 ? NCH : 1); ++c)
+#pragma unroll
+        for (int r = 0; r < RN; ++r) chv[c][r] = T(0);
     auto run_fin = [&](auto full) {
 #pragma unroll
         for (int r0 = 0; r0 < RN; r0 += NG) {
@@ -1186,13 +1226,25 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
                     T vv[NO];
 #pragma unroll
                     for (int o = 0; o < NO; ++o) vv[o] = nv[o][r0 + q];
-                    fin.fin(Nd{nbase, (uint32_t)e}, ld[q], vv, red);
+                    if constexpr (NCH > 0) {
+                        T cn[NCH];
+                        fin.fin_chain(Nd{nbase, (uint32_t)e}, ld[q], vv, red, cn);
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) chv[c][r0 + q] = cn[c];
+                    } else {
+                        fin.fin(Nd{nbase, (uint32_t)e}, ld[q], vv, red);
+                    }
                 }
             }
         }
     };
     if (nval == RN * nthr) run_fin(std::true_type{});   // branch-free, as in k_xfwd
     else run_fin(std::false_type{});
+    if constexpr (NCH > 0) {
+        // the twiddles are still in LDS after the row buffers
+        static_assert(F::NRED == 0, "a chained epilogue has no reductions");
+        r2c_store<T, NCH, RN>(g, chv, SAout, lds, lgNc, nthr, nval);
+    }
     if constexpr (F::NRED > 0) {
         __syncthreads();
         double* sm = reinterpret_cast<double*>(smem_raw);

@@ -49,8 +49,9 @@ struct pd_plan_s {
     double* tw64;                // FP64 twiddles, same layout
     void* taps;                  // T [NP][nct][ntap], transform convention
     void* taps_d;                // T [NP][nct][ntap], direct convention
-    void* taps_yz;               // T [h1][nct][yz_nu]: partial x-spectra over the (y, z) quarter disc (3D)
+    void* taps_yz;               // T [h1][nct_yz][yz_nu]: partial x-spectra over the (y, z) quarter disc (3D)
     int yz_mt, yz_nu;            // its radius in spacings (0: no (y, z) direct pass) and tap count
+    int nct_yz;                  // components in taps_yz (nct, + 3 scaled copies k_a a0_i for LPS)
     void* stat;                  // T [nb][ncs]
     void* stat_int;              // T [ncs]: the static fields at interior nodes
     double stat_int_h[10];       // the same values (rounded to T) on the host
