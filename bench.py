@@ -320,6 +320,7 @@ def main():
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-nbb", action="store_true", help="skip the 2D nonlinear bond-based force rate")
+    ap.add_argument("--no-mconv", action="store_true", help="skip the m-convergence table")
     ap.add_argument("--no-fft-variant", action="store_true",
                     help="skip the step timing with FFTs along all three axes")
     ap.add_argument("--no-energy", action="store_true", help="skip the 1000-step energy-drift runs")
@@ -399,6 +400,13 @@ def main():
                 if model == "nbb":
                     nbb[f"{tag}_3d128_{dn}_passes"] = ps
         log(f"[bench] nbb {json.dumps({k: v for k, v in nbb.items() if not k.endswith('passes')})}")
+    mconv_tab = None
+    if not args.no_mconv:
+        from paper_2105_06055_amd import mconv
+        mconv_tab = {"workload": "quadratic field, force at the centre of an interior block, fixed horizon "
+                                 "delta = 3e-3 m, m = delta/dx; FP64; relative error vs the continuum Navier operator",
+                     "rows": mconv.run()}
+        log(f"[bench] m-convergence {json.dumps(mconv_tab['rows'])}")
     energy = None
     if not args.no_energy:
         log(f"[bench] energy drift over {args.energy_steps} steps (FP32 and FP64)")
@@ -458,6 +466,7 @@ def main():
             "cg_time_to_1e-10": cg,
             "c2_force": c2,
             "nonlinear_bb_plate_force": nbb,
+            "m_convergence": mconv_tab,
             "energy_drift": energy,
         },
     }
