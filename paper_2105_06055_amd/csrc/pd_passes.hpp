@@ -744,8 +744,8 @@ k_lastconv(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps, int nct) {
 // forms its y-neighbour sums and differences there; the plane's
 // contributions go into the accumulators of the 2 MT + 1 output planes it
 // reaches (a register ring), and an output plane is stored as soon as its
-// last input plane is in.  The inputs are loaded two planes ahead of the
-// arithmetic (two register sets).  Outputs go to other SA fields than the
+// last input plane is in.  The inputs are loaded two (four for the light
+// FP64 passes) planes ahead of the arithmetic.  Outputs go to other SA fields than the
 // inputs (neighbouring chunks read each other's planes).
 struct YZArgs {
     int b2, b3, h1, P2;
@@ -878,9 +878,15 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
     for (int r = 0; r < RR; ++r)
 #pragma unroll
         for (int o = 0; o < NO; ++o) acc[r][o] = cx<T>{T(0), T(0)};
-    cx<T> nv[2][NI], nh[2][NI];   // inputs of the next two planes (row y, halo row yh)
+    // PF register sets of prefetched inputs (planes zi+1 .. zi+PF in flight):
+    // four for the light dilatation-type passes in FP64 (NI * NO <= 4), else
+    // two (in FP32 the extra registers cost more occupancy than they gain)
+    constexpr int PF = (sizeof(T) == 8 && NI * NO <= 4 && RR % 4 == 0) ? 4 : 2;
+    cx<T> nv[PF][NI], nh[PF][NI];   // row y, halo row yh
 #pragma unroll
-    for (int J = 0; J < NI; ++J) nv[0][J] = nh[0][J] = nv[1][J] = nh[1][J] = cx<T>{T(0), T(0)};
+    for (int k = 0; k < PF; ++k)
+#pragma unroll
+        for (int J = 0; J < NI; ++J) nv[k][J] = nh[k][J] = cx<T>{T(0), T(0)};
     // straight-line loads: the plane index is clamped into the body (planes
     // outside it are never used) and rows beyond the body read row 0 and are
     // replaced by zeros
@@ -910,11 +916,10 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
 
     const int zb = z0 - MT;               // first input plane of the sweep
     const int nst = (z1 - z0) + 2 * MT;   // input planes swept
-    load(std::integral_constant<int, 0>{}, zb);
-    load(std::integral_constant<int, 1>{}, zb + 1);
+    OutLoop<0, PF>::run([&](auto kc) { load(kc, zb + decltype(kc)::value); });
     for (int s0 = 0; s0 < nst; s0 += RR) {
         OutLoop<0, RR>::run([&](auto rc) {
-            constexpr int rr = decltype(rc)::value, P = rr & 1;
+            constexpr int rr = decltype(rc)::value, P = rr & 1, PS = rr % PF;
             const int s = s0 + rr;
             if (s >= nst) return;   // block-uniform
             const int zi = zb + s;
@@ -922,18 +927,18 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
             lds_ptr<cx<T>> row = lds + P * (NI * W);
             if (act) {
 #pragma unroll
-                for (int J = 0; J < NI; ++J) row[J * W + MT + tid] = nv[P][J];
+                for (int J = 0; J < NI; ++J) row[J * W + MT + tid] = nv[PS][J];
                 if (halo) {
                     if (hthr) {
 #pragma unroll
-                        for (int J = 0; J < NI; ++J) row[J * W + ph] = nh[P][J];
+                        for (int J = 0; J < NI; ++J) row[J * W + ph] = nh[PS][J];
                     }
                 }
                 __syncthreads();
             }
-            // the set just stored takes the plane after next (two planes of
-            // arithmetic to arrive)
-            load(std::integral_constant<int, P>{}, zi + 2);
+            // the set just stored takes plane zi + PF (PF planes of arithmetic
+            // to arrive)
+            load(std::integral_constant<int, PS>{}, zi + PF);
             if (act) {
                 // per output, the terms even (G = 0) and odd (G = 1) along z of
                 // inputs J0 .. J1-1 summed, then added to the planes they reach
