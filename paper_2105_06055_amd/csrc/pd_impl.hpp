@@ -201,6 +201,9 @@ template <class T>
 int rows_per_block(pd_plan p) {
     const int Tc = p->geo.Nc / 8;
     int Lt = (sizeof(T) == 4) ? 16 : 8;
+    // 128-point rows (the 256-point x box): as many rows as fill the
+    // specialised block (32 in FP32, 16 in FP64)
+    if (p->geo.Nc == 128) Lt = xblock_threads<T>() / Tc;
     while (Lt > 1 && Tc * Lt > 512) Lt >>= 1;
     while (Lt > 1 && ((size_t)Lt * row_pitch(p->geo.Nc) + tw_lds_len(p->geo.n1)) * sizeof(cx<T>) > (size_t)p->max_lds) Lt >>= 1;
     return Lt;
@@ -255,10 +258,11 @@ long xinv_blocks(pd_plan p) {
 }
 
 // Lengths with compile-time specialisations of the x and y passes (the
-// 512^3 box: 256-point complex rows along x, 512-point lines along y); any
-// other length runs the runtime-length kernels (LG = 0).  The specialised x
-// passes also assume a body no longer than half the x box (b1 <= Nc).
-constexpr int kFastLgX = 8, kFastLgY = 9;
+// 512^3 box: 256-point complex rows along x, 512-point lines along y; the
+// 256-point x box: 128-point rows); any other length runs the
+// runtime-length kernels (LG = 0).  The specialised x passes also assume a
+// body no longer than half the x box (b1 <= Nc).
+constexpr int kFastLgX = 8, kFastLgX2 = 7, kFastLgY = 9;
 
 // Pass 1
 template <class T, class G, int LG>
@@ -280,7 +284,10 @@ pd_status launch_xfwd_lg(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
 }
 template <class T, class G>
 pd_status launch_xfwd(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
-    if (p->geo.Nc == (1 << kFastLgX) && p->geo.b1 <= p->geo.Nc) return launch_xfwd_lg<T, G, kFastLgX>(p, gen, SA, st);
+    if (p->geo.b1 <= p->geo.Nc) {
+        if (p->geo.Nc == (1 << kFastLgX)) return launch_xfwd_lg<T, G, kFastLgX>(p, gen, SA, st);
+        if (p->geo.Nc == (1 << kFastLgX2)) return launch_xfwd_lg<T, G, kFastLgX2>(p, gen, SA, st);
+    }
     return launch_xfwd_lg<T, G, 0>(p, gen, SA, st);
 }
 
@@ -542,8 +549,10 @@ pd_status launch_xinv_lg(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t s
 }
 template <class T, class F>
 pd_status launch_xinv(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st, cx<T>* SAout = nullptr) {
-    if (p->geo.Nc == (1 << kFastLgX) && p->geo.b1 <= p->geo.Nc)
-        return launch_xinv_lg<T, F, kFastLgX>(p, fin, SA, st, SAout);
+    if (p->geo.b1 <= p->geo.Nc) {
+        if (p->geo.Nc == (1 << kFastLgX)) return launch_xinv_lg<T, F, kFastLgX>(p, fin, SA, st, SAout);
+        if (p->geo.Nc == (1 << kFastLgX2)) return launch_xinv_lg<T, F, kFastLgX2>(p, fin, SA, st, SAout);
+    }
     return launch_xinv_lg<T, F, 0>(p, fin, SA, st, SAout);
 }
 
