@@ -1215,12 +1215,26 @@ __device__ __forceinline__ void ew_block_reduce(double (&acc)[NR], double* part)
     block_reduce_store<NR>(acc, part + (long)blockIdx.x * NR, sm);
 }
 
-// CG update: x += a p; r -= a Ap; partial |r|^2.   (types may differ: x is
-// the iterate precision, r/p/Ap the operator precision)
+// CG coefficients stay on the device: alpha = rho / (p . Ap) and
+// beta = rho_new / rho are formed by every thread from the reduction results
+// (0 when the denominator is 0), so no scalar travels through the host.
+__device__ __forceinline__ double dev_ratio(const double* __restrict__ num, const double* __restrict__ den) {
+    const double d = den[0];
+    return d != 0.0 ? num[0] / d : 0.0;
+}
+// Thread 0 of block 0 keeps rho_new for the next iteration's alpha (a slot
+// that no thread of the launch reads).
+__device__ __forceinline__ void keep_rho(double* __restrict__ save, const double* __restrict__ num) {
+    if (save && blockIdx.x == 0 && threadIdx.x == 0) save[0] = num[0];
+}
+
+// CG update: x += a p; r -= a Ap; partial |r|^2, a = num / den.  (types may
+// differ: x is the iterate precision, r/p/Ap the operator precision)
 template <class TX, class T>
 __global__ void k_cg_update(TX* __restrict__ x, const T* __restrict__ p, T* __restrict__ r, const T* __restrict__ Ap,
-                            const double* __restrict__ coef, long n, double* __restrict__ part) {
-    const double a = coef[0];
+                            const double* __restrict__ num, const double* __restrict__ den, long n,
+                            double* __restrict__ part) {
+    const double a = dev_ratio(num, den);
     double acc[1] = {0.0};
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
         x[k] = TX(double(x[k]) + a * double(p[k]));
@@ -1231,10 +1245,12 @@ __global__ void k_cg_update(TX* __restrict__ x, const T* __restrict__ p, T* __re
     ew_block_reduce<1>(acc, part);
 }
 
-// p = r + b p
+// p = r + b p, b = num / den
 template <class T>
-__global__ void k_cg_dir(T* __restrict__ p, const T* __restrict__ r, const double* __restrict__ coef, long n) {
-    const double b = coef[0];
+__global__ void k_cg_dir(T* __restrict__ p, const T* __restrict__ r, const double* __restrict__ num,
+                         const double* __restrict__ den, double* __restrict__ save, long n) {
+    const double b = dev_ratio(num, den);
+    keep_rho(save, num);
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
         p[k] = T(double(r[k]) + b * double(p[k]));
 }
@@ -1249,11 +1265,11 @@ static __global__ void k_cgm_start(double* __restrict__ p, float* __restrict__ p
     }
 }
 // x += a p32;  r -= a Ap32  (FP64 accumulation of the FP32 operator output);
-// partial |r|^2
+// partial |r|^2, a = num / den
 static __global__ void k_cgm_update(double* __restrict__ x, const float* __restrict__ p32, double* __restrict__ r,
-                                    const float* __restrict__ Ap32, const double* __restrict__ coef, long n,
-                                    double* __restrict__ part) {
-    const double a = coef[0];
+                                    const float* __restrict__ Ap32, const double* __restrict__ num,
+                                    const double* __restrict__ den, long n, double* __restrict__ part) {
+    const double a = dev_ratio(num, den);
     double acc[1] = {0.0};
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
         x[k] += a * double(p32[k]);
@@ -1263,10 +1279,12 @@ static __global__ void k_cgm_update(double* __restrict__ x, const float* __restr
     }
     ew_block_reduce<1>(acc, part);
 }
-// p = r + b p;  p32 = (float) p
+// p = r + b p;  p32 = (float) p, b = num / den
 static __global__ void k_cgm_dir(double* __restrict__ p, float* __restrict__ p32, const double* __restrict__ r,
-                                 const double* __restrict__ coef, long n) {
-    const double b = coef[0];
+                                 const double* __restrict__ num, const double* __restrict__ den,
+                                 double* __restrict__ save, long n) {
+    const double b = dev_ratio(num, den);
+    keep_rho(save, num);
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
         const double v = r[k] + b * p[k];
         p[k] = v;
@@ -1274,10 +1292,12 @@ static __global__ void k_cgm_dir(double* __restrict__ p, float* __restrict__ p32
     }
 }
 
-// Preconditioned CG directions: p = z + b p
+// Preconditioned CG directions: p = z + b p, b = num / den
 template <class T>
-__global__ void k_pcg_dir(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ coef, long n) {
-    const double b = coef[0];
+__global__ void k_pcg_dir(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ num,
+                          const double* __restrict__ den, double* __restrict__ save, long n) {
+    const double b = dev_ratio(num, den);
+    keep_rho(save, num);
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
         p[k] = T(double(z[k]) + b * double(p[k]));
 }
@@ -1289,10 +1309,12 @@ static __global__ void k_pcgm_start(double* __restrict__ p, float* __restrict__ 
         p32[k] = z32[k];
     }
 }
-// mixed: p = z32 + b p (FP64);  p32 = (float) p
+// mixed: p = z32 + b p (FP64);  p32 = (float) p, b = num / den
 static __global__ void k_pcgm_dir(double* __restrict__ p, float* __restrict__ p32, const float* __restrict__ z32,
-                                  const double* __restrict__ coef, long n) {
-    const double b = coef[0];
+                                  const double* __restrict__ num, const double* __restrict__ den,
+                                  double* __restrict__ save, long n) {
+    const double b = dev_ratio(num, den);
+    keep_rho(save, num);
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
         const double v = double(z32[k]) + b * p[k];
         p[k] = v;
@@ -1321,11 +1343,6 @@ __global__ void k_vva_final(T* __restrict__ ub, T* __restrict__ vb, const T* __r
         ub[k] = c1 * La[k] + ut[k] + c2 * Lut[k];
         vb[k] = a[k] + dt * ut[k];
     }
-}
-
-// single-thread scalar ops on device values (alpha = num/den etc.)
-static __global__ void k_ratio(const double* __restrict__ num, const double* __restrict__ den, double* __restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = (den[0] != 0.0) ? num[0] / den[0] : 0.0;
 }
 
 template <int NR>
@@ -1572,6 +1589,63 @@ pd_status verlet_adjoint_impl(pd_plan p, const T* un, const T* unp1, const T* s,
 }
 
 // --------------------------------------------------------- static solve
+// The host reads the residual norm of each CG iteration one iteration late:
+// the value is copied to pinned memory behind that iteration's kernels and
+// the host waits for it only after the next iteration is queued, so the
+// device never idles on a host round trip.  Slots 8 and 9 of red_host.
+struct LagRead {
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    double* h = nullptr;
+    pd_status init(pd_plan p) {
+        h = p->red_host + 8;
+        for (hipEvent_t& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        return PD_OK;
+    }
+    ~LagRead() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    pd_status post(int k, const double* src, hipStream_t st) {
+        HIP_TRY(hipMemcpyAsync(h + (k & 1), src, sizeof(double), hipMemcpyDeviceToHost, st));
+        return pdh::check(hipEventRecord(ev[k & 1], st));
+    }
+    pd_status get(int k, double* v) {
+        HIP_TRY(hipEventSynchronize(ev[k & 1]));
+        *v = h[k & 1];
+        return std::isfinite(*v) ? PD_OK : PD_ENUMERIC;
+    }
+};
+// Device slots of red used by the solvers: [0] the operator's or the
+// preconditioner's reduction, [2] |r|^2 of the last update, [6 + (k & 1)]
+// rho of iteration k (r.r, or r.z when preconditioned).
+constexpr int kRedRR = 2, kRedRho = 6;
+
+// Drive a CG loop whose iterations are queued by issue(k): issue more while
+// the lagged |r|^2 is above stop2, then confirm on the last iteration's value
+// (CG residuals are not monotone, so the extra iteration queued behind the
+// converged one is checked too) and continue if it is not converged.
+template <class Issue>
+pd_status cg_drive(LagRead& lag, double stop2, int maxit, int* issued_out, double* rr_out, Issue&& issue) {
+    int issued = 0;
+    double rr = *rr_out;
+    while (rr > stop2 && issued < maxit) {
+        bool hint = false;
+        while (issued < maxit && !hint) {
+            PD_TRY(issue(issued));
+            ++issued;
+            if (issued >= 2) {
+                double v;
+                PD_TRY(lag.get(issued - 2, &v));
+                hint = v <= stop2;
+            }
+        }
+        PD_TRY(lag.get(issued - 1, &rr));
+    }
+    *issued_out = issued;
+    *rr_out = rr;
+    return PD_OK;
+}
+
 // Plain CG in the plan precision on A = -chi_O L chi_O; x holds the full
 // displacement (constrained components already = w).  Vectors r, pp, Ap of
 // type T.  Returns the number of operator applications used.
@@ -1580,32 +1654,28 @@ pd_status cg_run(pd_plan p, TX* x_unused, T* xT, T* r, T* pp, T* Ap, double rr0,
                  int* applies, double* rr_out, hipStream_t st) {
     (void)x_unused;
     const long n = p->nb * p->dim;
-    double rr = rr0;
-    int it = 0;
+    const unsigned nb = ew_blocks(n);
+    double* dev = p->red;
+    LagRead lag;
+    PD_TRY(lag.init(p));
     HIP_TRY(hipMemcpyAsync(pp, r, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
-    double* dev = p->red;      // [0] pAp, [1] alpha, [2] rr_new, [3] beta, [4] rr
-    while (it < maxit && rr > stop2) {
+    p->red_host[kRedRho] = rr0;
+    HIP_TRY(hipMemcpyAsync(dev + kRedRho, p->red_host + kRedRho, sizeof(double), hipMemcpyHostToDevice, st));
+    auto issue = [&](int k) -> pd_status {
+        double* rho = dev + kRedRho + (k & 1);
+        double* rho_new = dev + kRedRho + ((k + 1) & 1);
         PD_TRY((lin_apply<T, 2>(p, pp, Ap, nullptr, st)));   // red[0] = p.Ap
-        // alpha = rr / pAp  (rr kept on the host, pushed to red[4])
-        p->red_host[4] = rr;
-        HIP_TRY(hipMemcpyAsync(dev + 4, p->red_host + 4, sizeof(double), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, st, dev + 4, dev + 0, dev + 1);
-        const unsigned nb = ew_blocks(n);
         hipLaunchKernelGGL((k_cg_update<T, T>), dim3(nb), dim3(EW_THREADS), 0, st, xT, (const T*)pp, r, (const T*)Ap,
-                           (const double*)(dev + 1), n, p->partials);
-        PD_TRY(ew_finish<1>(p, nb, dev + 2, st));
-        double v[3];
-        PD_TRY(fetch_red(p, 3, st, v));
-        const double rr_new = v[2];
-        ++it;
-        if (!std::isfinite(rr_new)) return PD_ENUMERIC;
-        if (rr_new <= stop2) { rr = rr_new; break; }
-        p->red_host[3] = rr_new / rr;
-        HIP_TRY(hipMemcpyAsync(dev + 3, p->red_host + 3, sizeof(double), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_cg_dir<T>, dim3(nb), dim3(EW_THREADS), 0, st, pp, (const T*)r, (const double*)(dev + 3), n);
-        HIP_TRY(hipGetLastError());
-        rr = rr_new;
-    }
+                           (const double*)rho, (const double*)dev, n, p->partials);
+        PD_TRY(ew_finish<1>(p, nb, rho_new, st));
+        PD_TRY(lag.post(k, rho_new, st));
+        hipLaunchKernelGGL(k_cg_dir<T>, dim3(nb), dim3(EW_THREADS), 0, st, pp, (const T*)r, (const double*)rho_new,
+                           (const double*)rho, (double*)nullptr, n);
+        return pdh::check(hipGetLastError());
+    };
+    int it = 0;
+    double rr = rr0;
+    PD_TRY(cg_drive(lag, stop2, maxit, &it, &rr, issue));
     *its = it;
     *applies = it;
     *rr_out = rr;
@@ -1667,40 +1737,32 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
         SOLVE_TRY(pdh::check(hipMalloc(&pp, sizeof(double) * n)));
         SOLVE_TRY(pdh::check(hipMalloc(&Ap, sizeof(double) * n)));
         SOLVE_TRY(pdh::check(hipMalloc(&z, sizeof(double) * n)));
-        double* dev = p->red;   // [0] pAp or rz, [1] alpha, [2] rr, [3] beta, [4] rz (device copies)
+        double* dev = p->red;
         int it = 0;
         if (rr > stop2) {
-            SOLVE_TRY((precond_apply<double, double, double>(p, r, z, st)));
-            SOLVE_TRY(fetch_red(p, 1, st, v));
+            LagRead lag;
+            SOLVE_TRY(lag.init(p));
+            SOLVE_TRY((precond_apply<double, double, double>(p, r, z, st)));   // red[0] = r.z
             inf.precond_applies += 1;
-            double rz = v[0];
+            SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + kRedRho, dev, sizeof(double), hipMemcpyDeviceToDevice, st)));
             SOLVE_TRY(pdh::check(hipMemcpyAsync(pp, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st)));
-            while (it < maxit) {
-                SOLVE_TRY((lin_apply<double, 2>(p, pp, Ap, nullptr, st)));   // red[0] = p.Ap
-                inf.applies_fp64 += 1;
-                p->red_host[4] = rz;
-                SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + 4, p->red_host + 4, sizeof(double), hipMemcpyHostToDevice, st)));
-                hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, st, dev + 4, dev + 0, dev + 1);
-                hipLaunchKernelGGL((k_cg_update<double, double>), dim3(nb), dim3(EW_THREADS), 0, st, u, (const double*)pp,
-                                   r, (const double*)Ap, (const double*)(dev + 1), n, p->partials);
-                SOLVE_TRY(pdh::check(hipGetLastError()));
-                SOLVE_TRY(ew_finish<1>(p, nb, dev + 2, st));
-                SOLVE_TRY(fetch_red(p, 3, st, v));
-                ++it;
-                rr = v[2];
-                if (!std::isfinite(rr)) return fail(PD_ENUMERIC);
-                if (rr <= stop2) break;
-                SOLVE_TRY((precond_apply<double, double, double>(p, r, z, st)));   // red[0] = r.z
-                inf.precond_applies += 1;
-                SOLVE_TRY(fetch_red(p, 1, st, v));
-                const double rz_new = v[0];
-                p->red_host[3] = rz_new / rz;
-                SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + 3, p->red_host + 3, sizeof(double), hipMemcpyHostToDevice, st)));
+            auto issue = [&](int k) -> pd_status {
+                double* rho = dev + kRedRho + (k & 1);
+                double* rho_new = dev + kRedRho + ((k + 1) & 1);
+                PD_TRY((lin_apply<double, 2>(p, pp, Ap, nullptr, st)));   // red[0] = p.Ap
+                hipLaunchKernelGGL((k_cg_update<double, double>), dim3(nb), dim3(EW_THREADS), 0, st, u,
+                                   (const double*)pp, r, (const double*)Ap, (const double*)rho, (const double*)dev, n,
+                                   p->partials);
+                PD_TRY(ew_finish<1>(p, nb, dev + kRedRR, st));
+                PD_TRY(lag.post(k, dev + kRedRR, st));
+                PD_TRY((precond_apply<double, double, double>(p, r, z, st)));   // red[0] = r.z
                 hipLaunchKernelGGL(k_pcg_dir<double>, dim3(nb), dim3(EW_THREADS), 0, st, pp, (const double*)z,
-                                   (const double*)(dev + 3), n);
-                SOLVE_TRY(pdh::check(hipGetLastError()));
-                rz = rz_new;
-            }
+                                   (const double*)dev, (const double*)rho, rho_new, n);
+                return pdh::check(hipGetLastError());
+            };
+            SOLVE_TRY(cg_drive(lag, stop2, maxit, &it, &rr, issue));
+            inf.applies_fp64 += it;
+            inf.precond_applies += it;
         }
         inf.iters_fp64 = it;
     } else {
@@ -1711,70 +1773,78 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
         // chi_O (L x + b) whenever it has dropped by a factor 10 since the
         // last replacement and at the end (residual replacement keeps the
         // FP32 operator's errors from accumulating in r), so the returned
-        // iterate meets rtol in FP64.
+        // iterate meets rtol in FP64.  The host sees |r|^2 one iteration
+        // late, so a replacement follows the iteration queued behind the one
+        // that triggered it.
         pd_plan q = p->sub32;
         SOLVE_TRY(pdh::check(hipMalloc(&pp, sizeof(double) * n)));
         SOLVE_TRY(pdh::check(hipMalloc(&p32, sizeof(float) * n)));
         SOLVE_TRY(pdh::check(hipMalloc(&Ap32, sizeof(float) * n)));
         if (pre) SOLVE_TRY(pdh::check(hipMalloc(&z32, sizeof(float) * n)));
-        double* dev = q->red;   // [0] pAp / r.z, [1] alpha, [2] rr, [3] beta, [4] rho (device copies)
+        double* dev = q->red;
+        LagRead lag;
+        SOLVE_TRY(lag.init(q));
         // rho = r.z (preconditioned) or r.r; the direction starts from z or r
-        auto precond = [&](double* rz) -> pd_status {
-            PD_TRY((precond_apply<float, double, float>(q, r, z32, st)));
-            inf.precond_applies += 1;
-            PD_TRY(fetch_red(q, 1, st, v));
-            *rz = v[0];
-            return PD_OK;
-        };
-        double rho = rr;
         if (pre) {
-            if (rr > stop2) SOLVE_TRY(precond(&rho));
+            if (rr > stop2) {
+                SOLVE_TRY((precond_apply<float, double, float>(q, r, z32, st)));   // q->red[0] = r.z
+                inf.precond_applies += 1;
+                SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + kRedRho, dev, sizeof(double), hipMemcpyDeviceToDevice, st)));
+            }
             hipLaunchKernelGGL(k_pcgm_start, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const float*)z32, n);
         } else {
+            q->red_host[kRedRho] = rr;
+            SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + kRedRho, q->red_host + kRedRho, sizeof(double),
+                                                hipMemcpyHostToDevice, st)));
             hipLaunchKernelGGL(k_cgm_start, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const double*)r, n);
         }
         SOLVE_TRY(pdh::check(hipGetLastError()));
-        double rr_rep = rr;   // |r|^2 at the last replacement
-        int it = 0;
-        while (rr > stop2 && it < maxit) {
-            SOLVE_TRY((lin_apply<float, 2>(q, p32, Ap32, nullptr, st)));   // q->red[0] = p32 . Ap32
-            inf.applies_fp32 += 1;
-            q->red_host[4] = rho;
-            SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + 4, q->red_host + 4, sizeof(double), hipMemcpyHostToDevice, st)));
-            hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, st, dev + 4, dev + 0, dev + 1);
+        auto issue = [&](int k) -> pd_status {
+            double* rho = dev + kRedRho + (k & 1);
+            double* rho_new = dev + kRedRho + ((k + 1) & 1);
+            PD_TRY((lin_apply<float, 2>(q, p32, Ap32, nullptr, st)));   // q->red[0] = p32 . Ap32
             hipLaunchKernelGGL(k_cgm_update, dim3(nb), dim3(EW_THREADS), 0, st, u, (const float*)p32, r,
-                               (const float*)Ap32, (const double*)(dev + 1), n, q->partials);
-            SOLVE_TRY(pdh::check(hipGetLastError()));
-            SOLVE_TRY(ew_finish<1>(q, nb, dev + 2, st));
-            SOLVE_TRY(fetch_red(q, 3, st, v));
-            double rr_new = v[2];
+                               (const float*)Ap32, (const double*)rho, (const double*)dev, n, q->partials);
+            PD_TRY(ew_finish<1>(q, nb, dev + kRedRR, st));
+            PD_TRY(lag.post(k, dev + kRedRR, st));
+            if (pre) {
+                PD_TRY((precond_apply<float, double, float>(q, r, z32, st)));   // q->red[0] = r.z
+                hipLaunchKernelGGL(k_pcgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const float*)z32,
+                                   (const double*)dev, (const double*)rho, rho_new, n);
+            } else {
+                hipLaunchKernelGGL(k_cgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const double*)r,
+                                   (const double*)(dev + kRedRR), (const double*)rho, rho_new, n);
+            }
+            return pdh::check(hipGetLastError());
+        };
+        double rr_rep = rr;   // |r|^2 at the last replacement
+        int it = 0, fresh = 0;  // iterations from `fresh` on follow the last replacement
+        while (rr > stop2 && it < maxit) {
+            SOLVE_TRY(issue(it));
             ++it;
             inf.iters_fp32 += 1;
-            if (!std::isfinite(rr_new)) return fail(PD_ENUMERIC);
-            if (rr_new <= stop2 || rr_new <= 1e-2 * rr_rep) {
-                // residual replacement in FP64
+            inf.applies_fp32 += 1;
+            if (pre) inf.precond_applies += 1;
+            if (it - 2 < fresh) continue;
+            double rr_lag;
+            SOLVE_TRY(lag.get(it - 2, &rr_lag));
+            if (rr_lag <= stop2 || rr_lag <= 1e-2 * rr_rep) {
+                // residual replacement in FP64, after the queued iteration
                 SOLVE_TRY((lin_apply<double, 3>(p, u, r, b, st)));
                 SOLVE_TRY(fetch_red(p, 1, st, v));
                 inf.applies_fp64 += 1;
                 inf.iters_fp64 += 1;
                 if (!std::isfinite(v[0])) return fail(PD_ENUMERIC);
-                rr_new = v[0];
-                rr_rep = rr_new;
-                if (rr_new <= stop2) { rr = rr_new; break; }
+                rr = rr_rep = v[0];
+                fresh = it;
+                if (!pre) {
+                    // the next alpha uses |r|^2 of the replaced residual
+                    const int sl = kRedRho + (it & 1);
+                    q->red_host[sl] = rr;
+                    SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + sl, q->red_host + sl, sizeof(double),
+                                                        hipMemcpyHostToDevice, st)));
+                }
             }
-            rr = rr_new;
-            double rho_new = rr_new;
-            if (pre) SOLVE_TRY(precond(&rho_new));
-            q->red_host[3] = rho_new / rho;
-            SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + 3, q->red_host + 3, sizeof(double), hipMemcpyHostToDevice, st)));
-            if (pre)
-                hipLaunchKernelGGL(k_pcgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const float*)z32,
-                                   (const double*)(dev + 3), n);
-            else
-                hipLaunchKernelGGL(k_cgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const double*)r,
-                                   (const double*)(dev + 3), n);
-            SOLVE_TRY(pdh::check(hipGetLastError()));
-            rho = rho_new;
         }
     }
     // true FP64 residual of the returned iterate
