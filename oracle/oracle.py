@@ -69,6 +69,15 @@ def lib():
         _lib.orc_damage_index.argtypes = [gp, up, up, dp, C.POINTER(C.c_int32)]
         _lib.orc_verlet.argtypes = [gp, mp, up, up, up, dp, dp, dp, dp, dp, dp, dp,
                                     C.c_double, C.c_int, C.c_int, dp]
+        _lib.orc_bond_sc.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double]
+        _lib.orc_bond_sc.restype = C.c_double
+        _lib.orc_bond_force.argtypes = [gp, C.c_double, up, up, dp, dp]
+        _lib.orc_bond_break.argtypes = [gp, C.c_double, up, up, dp]
+        _lib.orc_bond_break.restype = C.c_long
+        _lib.orc_bond_damage.argtypes = [gp, up, up, dp]
+        _lib.orc_bond_verlet.argtypes = [gp, C.c_double, C.c_double, C.c_double, up, up, up, dp, dp, dp,
+                                         dp, dp, C.c_double, C.c_int, C.c_int]
+        _lib.orc_bond_verlet.restype = C.c_long
         _lib.orc_static_cg.argtypes = [gp, mp, up, up, dp, dp, dp, C.c_double, C.c_int, dp]
         _lib.orc_static_cg.restype = C.c_int
         _lib.orc_bb_force_adjoint.argtypes = [gp, C.c_double, dp, dp, dp, dp, dp]
@@ -253,3 +262,66 @@ def verlet_adjoint(g: Geom, alpha, rho, chiO, phi, b, u0, v0, dt, nsteps, ubarT,
     lib().orc_verlet_adjoint(C.byref(g), alpha, rho, _u8(chiO), _d(phi), _d(b), _d(u0), _d(v0),
                              dt, nsteps, _d(ub), _d(vb), _d(pb))
     return ub, vb, pb
+
+
+# --------------------------------------------------------------------------
+# Comparator only: the critical bond-strain rule (Sec. 2, Eq. 10-12), which
+# has no convolution structure.  ``mu`` is a uint8 array of shape
+# (nodes, len(stencil(g))), one intact flag per bond, node-major.
+
+def bond_sc(dim, alpha, G0, delta, influence=0) -> float:
+    """Critical stretch calibrated to the fracture energy G0 (planar-crack
+    energy balance of the linearized bond energy)."""
+    return lib().orc_bond_sc(dim, influence, alpha, G0, delta)
+
+
+def bond_mu(g: Geom):
+    """All bonds intact."""
+    n = 1
+    for d in range(3):
+        n *= g.nb[d]
+    return np.ones((n, len(stencil(g))), dtype=np.uint8)
+
+
+def bond_force(g: Geom, alpha, chiB, mu, u):
+    """Linearized bond-based force with per-bond intact flags (Eq. 10, 18)."""
+    u = _f64(u)
+    chiB = _mask(chiB)
+    mu = _mask(mu)
+    L = np.empty_like(u)
+    lib().orc_bond_force(C.byref(g), alpha, _u8(chiB), _u8(mu), _d(u), _d(L))
+    return L
+
+
+def bond_break(g: Geom, s_c, chiB, mu, u) -> int:
+    """Clear, in place, the flags of bonds stretched beyond s_c."""
+    assert mu.dtype == np.uint8 and mu.flags.c_contiguous
+    chiB = _mask(chiB)
+    u = _f64(u)
+    return lib().orc_bond_break(C.byref(g), s_c, _u8(chiB), _u8(mu), _d(u))
+
+
+def bond_damage(g: Geom, chiB, mu):
+    """Damage index of Eq. 12 from per-bond flags."""
+    chiB = _mask(chiB)
+    mu = _mask(mu)
+    d = np.empty(chiB.shape, dtype=np.float64)
+    lib().orc_bond_damage(C.byref(g), _u8(chiB), _u8(mu), _d(d))
+    return d
+
+
+def bond_verlet(g: Geom, alpha, rho, s_c, chiB, chiO, mu, u, v, dt, nsteps, b=None, w=None, F=None,
+                init=True):
+    """EC velocity Verlet under the critical bond-strain rule.  ``mu`` is
+    updated in place; returns (state dict, number of flags cleared)."""
+    assert mu.dtype == np.uint8 and mu.flags.c_contiguous
+    chiB = _mask(chiB)
+    chiO = _mask(chiO)
+    u = _f64(u).copy()
+    v = _f64(v).copy()
+    F = np.zeros_like(u) if F is None else _f64(F).copy()
+    b = None if b is None else _f64(b)
+    w = None if w is None else _f64(w)
+    nbk = lib().orc_bond_verlet(C.byref(g), alpha, rho, s_c, _u8(chiB), _u8(chiO), _u8(mu), _d(u), _d(v),
+                                _d(F), _d(b), _d(w), dt, nsteps, int(bool(init)))
+    return {"u": u, "v": v, "F": F, "mu": mu}, nbk

@@ -631,3 +631,168 @@ void orc_verlet_adjoint(const orc_geom* g, double alpha, double rho, const uint8
     free(a); free(ut); free(La); free(us); free(pb);
     free(U); free(v); free(F); free(Lt);
 }
+
+/* ------------------------------------------------------------------ */
+/* Comparator only: the critical bond-strain failure rule of Sec. 2 (Eq. 10-12).
+ * It removes bonds one by one and so has no convolution structure; the fast
+ * method replaces it with the pointwise energy rule (Sec. 3.4), and these
+ * functions exist to compare the two, as the paper does in Sec. 5.2.
+ *
+ * mu holds one intact flag per (node, stencil bond), node-major:
+ * mu[id * ns + s] is the bond from node id along stencil offset s, in the
+ * order orc_stencil lists the offsets.  Bonds whose partner lies outside a
+ * non-periodic box or outside the body are ignored by every function. */
+
+/* Critical stretch s_c calibrated to the fracture energy G0 (the rule the
+ * paper cites for bond-strain models, Sec. 3.4.3 follows its idea): the
+ * energy of every bond crossing a unit area of a planar crack equals G0.
+ * With the linearized bond energy per pair of unit volumes
+ *   w = 1/2 alpha omega(r) (xi . eta)^2 / r^2 = 1/2 alpha omega(r) s^2 r^2
+ * at stretch s, a bond xi with normal component xi_n > 0 crosses the plane
+ * for xi_n of the depths below it, so
+ *   G0 = 1/2 alpha s_c^2 K,  K = int_{|xi| <= delta, xi_n > 0} omega(r) r^2 xi_n dxi,
+ *   K = delta^4 / 2 (2D) or pi delta^5 / 5 (3D) for omega = 1/r,
+ *   K = 2 delta^5 / 5 (2D) or pi delta^6 / 6 (3D) for omega = 1. */
+double orc_bond_sc(int dim, int influence, double alpha, double G0, double delta) {
+    double K;
+    if (influence == 0) K = (dim == 2) ? pow(delta, 4) / 2.0 : ORC_PI * pow(delta, 5) / 5.0;
+    else K = (dim == 2) ? 2.0 * pow(delta, 5) / 5.0 : ORC_PI * pow(delta, 6) / 6.0;
+    return sqrt(2.0 * G0 / (alpha * K));
+}
+
+/* Linearized bond-based force with per-bond intact flags (Eq. 10 with the
+ * integrand of Eq. 18):
+ *   L_i(x) = chi_B(x) sum_o mu(x, o) chi_B(x+o) alpha omega xi_i xi_j / r^2
+ *            (u_j(x+o) - u_j(x)) dV                                        */
+void orc_bond_force(const orc_geom* g, double alpha, const uint8_t* chiB, const uint8_t* mu, const double* u,
+                    double* L) {
+    int cap = 20000;
+    int* S = (int*)malloc(sizeof(int) * 3 * cap);
+    int ns = orc_stencil(g, S, cap);
+    long N = orc_nodes(g);
+    int D = g->dim;
+    double dV = orc_dv(g);
+#pragma omp parallel for schedule(static)
+    for (long id = 0; id < N; ++id) {
+        int x = (int)(id % g->nb[0]);
+        int y = (int)((id / g->nb[0]) % g->nb[1]);
+        int z = (int)(id / ((long)g->nb[0] * g->nb[1]));
+        double acc[3] = {0, 0, 0};
+        if (chiB[id]) {
+            for (int s = 0; s < ns; ++s) {
+                long j = orc_nbr(g, x, y, z, &S[3 * s]);
+                if (j < 0 || !chiB[j] || !mu[id * ns + s]) continue;
+                double xi[3] = {S[3 * s] * g->dx[0], S[3 * s + 1] * g->dx[1], S[3 * s + 2] * g->dx[2]};
+                double r2 = 0, ed = 0;
+                for (int d = 0; d < D; ++d) r2 += xi[d] * xi[d];
+                for (int d = 0; d < D; ++d) ed += xi[d] * (u[d * N + j] - u[d * N + id]);
+                double c = alpha * orc_omega(g, sqrt(r2)) / r2 * dV;
+                for (int i = 0; i < D; ++i) acc[i] += c * xi[i] * ed;
+            }
+        }
+        for (int i = 0; i < D; ++i) L[i * N + id] = acc[i];
+    }
+    free(S);
+}
+
+/* Break, for good, every body bond whose stretch exceeds s_c.  The stretch
+ * of the linearized model is s = xi . eta / |xi|^2 (the first-order part of
+ * (|xi + eta| - |xi|) / |xi|); it is the same seen from either end, so both
+ * directions of a bond break together.  Returns the number of flags
+ * cleared. */
+long orc_bond_break(const orc_geom* g, double s_c, const uint8_t* chiB, uint8_t* mu, const double* u) {
+    int cap = 20000;
+    int* S = (int*)malloc(sizeof(int) * 3 * cap);
+    int ns = orc_stencil(g, S, cap);
+    long N = orc_nodes(g);
+    int D = g->dim;
+    long broken = 0;
+#pragma omp parallel for schedule(static) reduction(+ : broken)
+    for (long id = 0; id < N; ++id) {
+        int x = (int)(id % g->nb[0]);
+        int y = (int)((id / g->nb[0]) % g->nb[1]);
+        int z = (int)(id / ((long)g->nb[0] * g->nb[1]));
+        if (!chiB[id]) continue;
+        for (int s = 0; s < ns; ++s) {
+            long j = orc_nbr(g, x, y, z, &S[3 * s]);
+            if (j < 0 || !chiB[j] || !mu[id * ns + s]) continue;
+            double xi[3] = {S[3 * s] * g->dx[0], S[3 * s + 1] * g->dx[1], S[3 * s + 2] * g->dx[2]};
+            double r2 = 0, ed = 0;
+            for (int d = 0; d < D; ++d) r2 += xi[d] * xi[d];
+            for (int d = 0; d < D; ++d) ed += xi[d] * (u[d * N + j] - u[d * N + id]);
+            if (ed / r2 > s_c) {
+                mu[id * ns + s] = 0;
+                ++broken;
+            }
+        }
+    }
+    free(S);
+    return broken;
+}
+
+/* Damage index of Eq. 12 with the one-point quadrature (equal weights dV,
+ * so the ratio of integrals is a ratio of bond counts):
+ *   d(x) = 1 - sum_o mu(x, o) chi_B(x+o) / sum_o chi_B(x+o)   on chi_B = 1,
+ * 0 off the body and for a node without body partners. */
+void orc_bond_damage(const orc_geom* g, const uint8_t* chiB, const uint8_t* mu, double* d) {
+    int cap = 20000;
+    int* S = (int*)malloc(sizeof(int) * 3 * cap);
+    int ns = orc_stencil(g, S, cap);
+    long N = orc_nodes(g);
+#pragma omp parallel for schedule(static)
+    for (long id = 0; id < N; ++id) {
+        int x = (int)(id % g->nb[0]);
+        int y = (int)((id / g->nb[0]) % g->nb[1]);
+        int z = (int)(id / ((long)g->nb[0] * g->nb[1]));
+        long tot = 0, intact = 0;
+        if (chiB[id]) {
+            for (int s = 0; s < ns; ++s) {
+                long j = orc_nbr(g, x, y, z, &S[3 * s]);
+                if (j < 0 || !chiB[j]) continue;
+                ++tot;
+                intact += mu[id * ns + s] ? 1 : 0;
+            }
+        }
+        d[id] = tot ? 1.0 - (double)intact / (double)tot : 0.0;
+    }
+    free(S);
+}
+
+/* Velocity Verlet of the bond-based solid under the critical bond-strain
+ * rule.  Bonds are checked on the new positions u^{n+1} and the force at
+ * t + dt uses the bonds still intact after that check (bond-strain codes
+ * break bonds as soon as they are overstretched; the energy rule of
+ * orc_verlet instead lags one step, Eq. 63).  One step:
+ *   u  <- chi_O [u + dt v + dt^2/(2 rho) F] + (1 - chi_O) w
+ *   mu <- mu AND [s(u) <= s_c]
+ *   F' <- L_mu(u) + b
+ *   v  <- chi_O [v + dt/(2 rho) (F + F')]
+ * If init != 0 the force of the initial state is computed first.  Returns
+ * the number of bond flags cleared. */
+long orc_bond_verlet(const orc_geom* g, double alpha, double rho, double s_c, const uint8_t* chiB,
+                     const uint8_t* chiO, uint8_t* mu, double* u, double* v, double* F, const double* b,
+                     const double* w, double dt, int nsteps, int init) {
+    long N = orc_nodes(g);
+    int D = g->dim;
+    double* Lt = (double*)malloc(sizeof(double) * N * D);
+    long broken = 0;
+    if (init) {
+        orc_bond_force(g, alpha, chiB, mu, u, Lt);
+        for (long i = 0; i < N * D; ++i) F[i] = Lt[i] + (b ? b[i] : 0.0);
+    }
+    for (int step = 0; step < nsteps; ++step) {
+        for (long i = 0; i < N * D; ++i) {
+            double wi = w ? w[i] : 0.0;
+            u[i] = chiO[i] ? (u[i] + dt * v[i] + dt * dt / (2.0 * rho) * F[i]) : wi;
+        }
+        broken += orc_bond_break(g, s_c, chiB, mu, u);
+        orc_bond_force(g, alpha, chiB, mu, u, Lt);
+        for (long i = 0; i < N * D; ++i) {
+            double Fn = Lt[i] + (b ? b[i] : 0.0);
+            v[i] = chiO[i] ? (v[i] + dt / (2.0 * rho) * (F[i] + Fn)) : 0.0;
+            F[i] = Fn;
+        }
+    }
+    free(Lt);
+    return broken;
+}
