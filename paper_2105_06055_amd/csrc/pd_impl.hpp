@@ -1255,14 +1255,12 @@ __global__ void k_cg_dir(T* __restrict__ p, const T* __restrict__ r, const doubl
         p[k] = T(double(r[k]) + b * double(p[k]));
 }
 
-// Mixed-precision CG vectors: the iterate, residual and direction in FP64,
-// the operator applied in FP32 to an FP32 copy of the direction.
-// p = r;  p32 = (float) r
-static __global__ void k_cgm_start(double* __restrict__ p, float* __restrict__ p32, const double* __restrict__ r, long n) {
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        p[k] = r[k];
+// Mixed-precision CG vectors: the iterate and residual in FP64, the
+// direction in FP32, the precision the operator reads it in.
+// p32 = (float) r
+static __global__ void k_cgm_start(float* __restrict__ p32, const double* __restrict__ r, long n) {
+    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
         p32[k] = float(r[k]);
-    }
 }
 // x += a p32;  r -= a Ap32  (FP64 accumulation of the FP32 operator output);
 // partial |r|^2, a = num / den
@@ -1279,17 +1277,14 @@ static __global__ void k_cgm_update(double* __restrict__ x, const float* __restr
     }
     ew_block_reduce<1>(acc, part);
 }
-// p = r + b p;  p32 = (float) p, b = num / den
-static __global__ void k_cgm_dir(double* __restrict__ p, float* __restrict__ p32, const double* __restrict__ r,
+// p32 = (float) (r + b p32), b = num / den
+static __global__ void k_cgm_dir(float* __restrict__ p32, const double* __restrict__ r,
                                  const double* __restrict__ num, const double* __restrict__ den,
                                  double* __restrict__ save, long n) {
     const double b = dev_ratio(num, den);
     keep_rho(save, num);
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        const double v = r[k] + b * p[k];
-        p[k] = v;
-        p32[k] = float(v);
-    }
+    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+        p32[k] = float(r[k] + b * double(p32[k]));
 }
 
 // Preconditioned CG directions: p = z + b p, b = num / den
@@ -1301,25 +1296,14 @@ __global__ void k_pcg_dir(T* __restrict__ p, const T* __restrict__ z, const doub
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
         p[k] = T(double(z[k]) + b * double(p[k]));
 }
-// mixed, first direction: p = z32 (FP64);  p32 = z32
-static __global__ void k_pcgm_start(double* __restrict__ p, float* __restrict__ p32, const float* __restrict__ z32,
-                                    long n) {
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        p[k] = double(z32[k]);
-        p32[k] = z32[k];
-    }
-}
-// mixed: p = z32 + b p (FP64);  p32 = (float) p, b = num / den
-static __global__ void k_pcgm_dir(double* __restrict__ p, float* __restrict__ p32, const float* __restrict__ z32,
+// mixed, preconditioned: p32 = (float) (z32 + b p32), b = num / den
+static __global__ void k_pcgm_dir(float* __restrict__ p32, const float* __restrict__ z32,
                                   const double* __restrict__ num, const double* __restrict__ den,
                                   double* __restrict__ save, long n) {
     const double b = dev_ratio(num, den);
     keep_rho(save, num);
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        const double v = double(z32[k]) + b * p[k];
-        p[k] = v;
-        p32[k] = float(v);
-    }
+    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+        p32[k] = float(double(z32[k]) + b * double(p32[k]));
 }
 
 // Verlet adjoint helpers
@@ -1767,8 +1751,9 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
         inf.iters_fp64 = it;
     } else {
         // CG with the operator (and the preconditioner, if any) applied in
-        // FP32 (sub32 plan) to FP32 copies, with the iterate, residual and
-        // direction updated and every inner product accumulated in FP64; the
+        // FP32 (sub32 plan), with the iterate and residual updated and every
+        // inner product accumulated in FP64 and the direction kept in FP32
+        // (the precision the operator reads it in); the
         // recursively updated residual is replaced by the FP64 residual
         // chi_O (L x + b) whenever it has dropped by a factor 10 since the
         // last replacement and at the end (residual replacement keeps the
@@ -1777,7 +1762,6 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
         // late, so a replacement follows the iteration queued behind the one
         // that triggered it.
         pd_plan q = p->sub32;
-        SOLVE_TRY(pdh::check(hipMalloc(&pp, sizeof(double) * n)));
         SOLVE_TRY(pdh::check(hipMalloc(&p32, sizeof(float) * n)));
         SOLVE_TRY(pdh::check(hipMalloc(&Ap32, sizeof(float) * n)));
         if (pre) SOLVE_TRY(pdh::check(hipMalloc(&z32, sizeof(float) * n)));
@@ -1791,12 +1775,12 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
                 inf.precond_applies += 1;
                 SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + kRedRho, dev, sizeof(double), hipMemcpyDeviceToDevice, st)));
             }
-            hipLaunchKernelGGL(k_pcgm_start, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const float*)z32, n);
+            SOLVE_TRY(pdh::check(hipMemcpyAsync(p32, z32, sizeof(float) * n, hipMemcpyDeviceToDevice, st)));
         } else {
             q->red_host[kRedRho] = rr;
             SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + kRedRho, q->red_host + kRedRho, sizeof(double),
                                                 hipMemcpyHostToDevice, st)));
-            hipLaunchKernelGGL(k_cgm_start, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const double*)r, n);
+            hipLaunchKernelGGL(k_cgm_start, dim3(nb), dim3(EW_THREADS), 0, st, p32, (const double*)r, n);
         }
         SOLVE_TRY(pdh::check(hipGetLastError()));
         auto issue = [&](int k) -> pd_status {
@@ -1809,10 +1793,10 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
             PD_TRY(lag.post(k, dev + kRedRR, st));
             if (pre) {
                 PD_TRY((precond_apply<float, double, float>(q, r, z32, st)));   // q->red[0] = r.z
-                hipLaunchKernelGGL(k_pcgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const float*)z32,
+                hipLaunchKernelGGL(k_pcgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, p32, (const float*)z32,
                                    (const double*)dev, (const double*)rho, rho_new, n);
             } else {
-                hipLaunchKernelGGL(k_cgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, pp, p32, (const double*)r,
+                hipLaunchKernelGGL(k_cgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, p32, (const double*)r,
                                    (const double*)(dev + kRedRR), (const double*)rho, rho_new, n);
             }
             return pdh::check(hipGetLastError());
