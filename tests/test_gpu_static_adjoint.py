@@ -109,6 +109,47 @@ def test_static_maxit_reports_not_converged():
     plan.close()
 
 
+@pytest.mark.parametrize("maxit", [1, 2, 5])
+def test_static_cg_first_iterates_match_oracle(orc, maxit):
+    """Plain FP64 CG stopped after maxit iterations: the GPU iterate equals
+    the oracle's plain CG iterate after the same number of iterations (the
+    device-side alpha/beta and the host's one-iteration-late residual check
+    neither skip nor add an iteration when the cap is reached)."""
+    from paper_2105_06055_amd import binding
+    w = wl.cube_void_static(seed=2, nb=12, nfft=16, clamp_layers=3)
+    plan = binding.Plan.from_workload(w, dtype=torch.float64)
+    u, info = plan.static_solve(_dev(w.b), rtol=1e-10, maxit=maxit, check=False)
+    assert info["status"] == binding.PD_ENOTCONV
+    assert info["iters_fp64"] == maxit
+    g = orc.geom(w.body, w.dx, w.delta)
+    mdl = orc.model("lps", E=w.E, nu=w.nu)
+    uo, it, rr = orc.static_cg(g, mdl, w.chiB, w.chiO, w.b, rtol=1e-10, maxit=maxit)
+    assert it == maxit
+    assert _rel(u.cpu().numpy(), uo) <= 1e-10
+    assert abs(info["rel_res"] - rr) <= 1e-8 * rr
+    plan.close()
+
+
+@pytest.mark.parametrize("precond", [False, True])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_static_cap_and_converged_start(mixed, precond):
+    """Every solve variant: a cap of 1 or 2 iterations reports not converged
+    with exactly that many iterations of its kind; started from a converged
+    solution it does no iteration and reports success."""
+    from paper_2105_06055_amd import binding
+    w = wl.cube_void_static(seed=2, nb=12, nfft=16, clamp_layers=3)
+    plan = binding.Plan.from_workload(w, dtype=torch.float64, mixed=mixed)
+    key = "iters_fp32" if mixed else "iters_fp64"
+    for cap in (1, 2):
+        u, info = plan.static_solve(_dev(w.b), rtol=1e-10, maxit=cap, mixed=mixed, precond=precond, check=False)
+        assert info["status"] == binding.PD_ENOTCONV and info[key] == cap, info
+    u, info = plan.static_solve(_dev(w.b), rtol=1e-10, maxit=20000, mixed=mixed, precond=precond)
+    u2, info2 = plan.static_solve(_dev(w.b), u0=u, rtol=1e-9, maxit=20000, mixed=mixed, precond=precond)
+    assert info2["status"] == binding.PD_OK and info2[key] == 0 and info2["rel_res"] <= 1e-9
+    assert torch.equal(u2, u)
+    plan.close()
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_force_adjoint_scale_weights(orc, dtype):
     from paper_2105_06055_amd import binding
