@@ -149,6 +149,35 @@ def run_dynamics(wl, dtype, steps, warmup, with_profile, lastaxis="auto"):
             "workspace_GB": info["workspace_bytes"] / 1e9, "lds_per_block": info["lds_per_block"]}
 
 
+def run_fracture(steps, warmup):
+    """The notched glass plate (1000 x 400 nodes, delta = 4 dx, 512 x 1024
+    grid, +-12 MPa edge tractions) in FP32 with the pointwise energy damage:
+    time `steps` Verlet steps issued as one library call, after `warmup`
+    steps.  Reports the time per step, node-steps/s and the failed nodes."""
+    import torch
+
+    from paper_2105_06055_amd import binding, workloads
+    w = workloads.notched_plate_fracture()
+    dtype = torch.float32
+    plan = binding.Plan.from_workload(w, dtype=dtype, weight="integrity")
+    dev = lambda a, t=dtype: torch.tensor(np.ascontiguousarray(a), dtype=t, device="cuda")
+    st = {"u": dev(w.u0), "v": dev(w.v0), "F": torch.zeros((2,) + w.body, dtype=dtype, device="cuda"),
+          "lam": dev(w.lam0, torch.uint8), "W": torch.zeros(w.body, dtype=dtype, device="cuda"), "step": 0}
+    b = dev(w.b)
+    plan.verlet(st, w.dt, warmup, b=b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.verlet(st, w.dt, steps, b=b)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    failed = int((torch.tensor(w.lam0, device="cuda").to(torch.int32) - st["lam"].to(torch.int32)).sum().item())
+    finite = bool(torch.isfinite(st["u"]).all().item())
+    plan.close()
+    return {"workload": "notched plate 1000x400 nodes, delta = 4 dx, 512x1024 grid, +-12 MPa, FP32, "
+                        "energy damage", "steps": steps, "warmup": warmup, "ms_per_step": t * 1e3,
+            "Gnode_steps_s": w.nodes / t / 1e9, "failed_nodes": failed, "finite": finite}
+
+
 def run_cg(nb, nfft, maxit):
     import torch
 
@@ -321,6 +350,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-nbb", action="store_true", help="skip the 2D nonlinear bond-based force rate")
     ap.add_argument("--no-mconv", action="store_true", help="skip the m-convergence table")
+    ap.add_argument("--no-fracture", action="store_true", help="skip the fracture-plate step timing")
+    ap.add_argument("--fracture-steps", type=int, default=1000)
     ap.add_argument("--no-fft-variant", action="store_true",
                     help="skip the step timing with FFTs along all three axes")
     ap.add_argument("--no-energy", action="store_true", help="skip the 1000-step energy-drift runs")
@@ -412,6 +443,10 @@ def main():
         log(f"[bench] energy drift over {args.energy_steps} steps (FP32 and FP64)")
         energy = energy_report(wl, args.energy_steps)
         log(f"[bench] energy {json.dumps(energy)}")
+    frac = None
+    if not args.no_fracture:
+        frac = run_fracture(args.fracture_steps, 20)
+        log(f"[bench] fracture {json.dumps(frac)}")
     cg = None
     if not args.no_cg:
         log("[bench] CG time-to-1e-10 (static cube)")
@@ -467,6 +502,7 @@ def main():
             "c2_force": c2,
             "nonlinear_bb_plate_force": nbb,
             "m_convergence": mconv_tab,
+            "fracture_plate": frac,
             "energy_drift": energy,
         },
     }

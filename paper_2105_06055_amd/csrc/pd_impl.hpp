@@ -197,14 +197,31 @@ NodeCtx<T> ctx(pd_plan p) {
     return c;
 }
 
+// Lengths with compile-time specialisations of the x and y passes (the
+// 512^3 box: 256-point complex rows along x, 512-point lines along y; the
+// 256-point x box: 128-point rows); any other length runs the
+// runtime-length kernels (LG = 0).  The specialised x passes also assume a
+// body no longer than half the x box (b1 <= Nc).
+constexpr int kFastLgX = 8, kFastLgX2 = 7, kFastLgY = 9;
+
+inline bool x_fast(const Geo& g) {
+    return g.b1 <= g.Nc && (g.Nc == (1 << kFastLgX) || g.Nc == (1 << kFastLgX2));
+}
+
 template <class T>
 int rows_per_block(pd_plan p) {
-    const int Tc = p->geo.Nc / 8;
+    const Geo& g = p->geo;
+    const int Tc = g.Nc / 8;
     int Lt = (sizeof(T) == 4) ? 16 : 8;
     // 128-point rows (the 256-point x box): as many rows as fill the
     // specialised block (32 in FP32, 16 in FP64)
-    if (p->geo.Nc == 128) Lt = xblock_threads<T>() / Tc;
+    if (g.Nc == 128) Lt = xblock_threads<T>() / Tc;
     while (Lt > 1 && Tc * Lt > 512) Lt >>= 1;
+    // few rows (2D plates, small blocks): fewer rows per block, down to two
+    // (16-byte runs in the transposed stores), until the grid has a block for
+    // each of the 256 compute units
+    if (!x_fast(g))
+        while (Lt > 2 && (long)((g.b2 + Lt - 1) / Lt) * g.b3 < 256) Lt >>= 1;
     while (Lt > 1 && ((size_t)Lt * row_pitch(p->geo.Nc) + tw_lds_len(p->geo.n1)) * sizeof(cx<T>) > (size_t)p->max_lds) Lt >>= 1;
     return Lt;
 }
@@ -256,13 +273,6 @@ long xinv_blocks(pd_plan p) {
     const int Lt = rows_per_block<T>(p);
     return (long)((p->geo.b2 + Lt - 1) / Lt) * p->geo.b3;
 }
-
-// Lengths with compile-time specialisations of the x and y passes (the
-// 512^3 box: 256-point complex rows along x, 512-point lines along y; the
-// 256-point x box: 128-point rows); any other length runs the
-// runtime-length kernels (LG = 0).  The specialised x passes also assume a
-// body no longer than half the x box (b1 <= Nc).
-constexpr int kFastLgX = 8, kFastLgX2 = 7, kFastLgY = 9;
 
 // Pass 1
 template <class T, class G, int LG>
