@@ -178,6 +178,39 @@ def run_fracture(steps, warmup):
             "Gnode_steps_s": w.nodes / t / 1e9, "failed_nodes": failed, "finite": finite}
 
 
+def run_adjoint_plate(dtype_name):
+    """The heterogeneous-micromodulus plate (512 x 512 nodes, 1024 x 1024
+    grid, 200 Verlet steps, checkpoints every 20): time one forward rollout
+    plus the checkpointed adjoint for dL/du0 and dL/ds, after one untimed
+    pass."""
+    import torch
+
+    from paper_2105_06055_amd import binding, workloads
+    from paper_2105_06055_amd.autograd import VerletRollout
+    dtype = {"fp32": torch.float32, "fp64": torch.float64}[dtype_name]
+    w = workloads.hetero_plate_adjoint()
+    plan = binding.Plan.from_workload(w, dtype=dtype)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+    target = dev(w.extra["u_target"])
+
+    def once():
+        u0 = dev(w.u0).requires_grad_(True)
+        s = dev(w.s).requires_grad_(True)
+        uT, _ = VerletRollout.apply(plan, u0, dev(w.v0), s, w.dt, w.steps, 20)
+        ((uT - target) ** 2).sum().backward()
+        return u0.grad, s.grad
+
+    once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gu, gs = once()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    finite = bool(torch.isfinite(gu).all().item() and torch.isfinite(gs).all().item())
+    plan.close()
+    return {"seconds": t, "ms_per_step_fwd_plus_adj": t / w.steps * 1e3, "finite": finite}
+
+
 def run_cg(nb, nfft, maxit):
     import torch
 
@@ -351,6 +384,7 @@ def main():
     ap.add_argument("--no-nbb", action="store_true", help="skip the 2D nonlinear bond-based force rate")
     ap.add_argument("--no-mconv", action="store_true", help="skip the m-convergence table")
     ap.add_argument("--no-fracture", action="store_true", help="skip the fracture-plate step timing")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint plate timing")
     ap.add_argument("--fracture-steps", type=int, default=1000)
     ap.add_argument("--no-fft-variant", action="store_true",
                     help="skip the step timing with FFTs along all three axes")
@@ -443,6 +477,13 @@ def main():
         log(f"[bench] energy drift over {args.energy_steps} steps (FP32 and FP64)")
         energy = energy_report(wl, args.energy_steps)
         log(f"[bench] energy {json.dumps(energy)}")
+    adj = None
+    if not args.no_adjoint:
+        adj = {"workload": "heterogeneous plate 512x512 nodes, 1024x1024 grid, 200 Verlet steps, checkpoints "
+                           "every 20; forward rollout + checkpointed adjoint (dL/du0, dL/ds)"}
+        for dn in ("fp32", "fp64"):
+            adj[dn] = run_adjoint_plate(dn)
+        log(f"[bench] adjoint {json.dumps(adj)}")
     frac = None
     if not args.no_fracture:
         frac = run_fracture(args.fracture_steps, 20)
@@ -503,6 +544,7 @@ def main():
             "nonlinear_bb_plate_force": nbb,
             "m_convergence": mconv_tab,
             "fracture_plate": frac,
+            "adjoint_plate": adj,
             "energy_drift": energy,
         },
     }
