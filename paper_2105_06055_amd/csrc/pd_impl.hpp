@@ -308,10 +308,12 @@ pd_status launch_xfwd(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
 template <class T, class M, int NT>
 pd_status launch_lastconv(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, const T* taps_d, int nct,
                           hipStream_t st) {
-    // one wavefront per line, four lines per block; no LDS; line starts must be
-    // 16-point aligned (the pitches of SA and SB are)
+    // one wavefront per line, four lines per block (one when there are too
+    // few lines to give every compute unit two blocks, as on the 2D plates);
+    // no LDS; line starts must be 16-point aligned (the pitches of SA and SB
+    // are)
     if ((ln.pitch & 15) || (ln.fstride & 15)) return PD_EINVAL;
-    const int Lw = 4;
+    const int Lw = ln.nlines >= 4L * 512 ? 4 : 1;
     dim3 grid((unsigned)((ln.nlines + Lw - 1) / Lw)), block(64 * Lw);
     hipLaunchKernelGGL((k_lastconv<T, M, NT>), grid, block, 0, st, ln, mul, S, taps_d, nct);
     return PD_OK;
