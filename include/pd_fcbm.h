@@ -228,19 +228,22 @@ typedef struct {
  * on entry and the solution (u = w on constrained components) on exit.
  * options = 0: plain FP64 CG (PD_F64 plan).
  * PD_SOLVE_MIXED (PD_F64 plan created with PD_PLAN_MIXED): CG iterations that
- *   apply the operator in FP32 to an FP32 copy of the search direction, with
- *   the iterate, residual and direction updated and every inner product
- *   accumulated in FP64, and the residual replaced by the FP64 residual
- *   chi_O (L(u) + b) each time it has dropped tenfold and at convergence
- *   (refinement against the FP64 operator).
+ *   apply the operator in FP32 to a search direction kept in FP32, with the
+ *   iterate and residual updated and every inner product accumulated in
+ *   FP64, and the residual replaced by the FP64 residual chi_O (L(u) + b)
+ *   each time its norm has dropped tenfold and at convergence (refinement
+ *   against the FP64 operator).
  * PD_SOLVE_PRECOND: preconditioned CG with z = chi_O M^-1 chi_O r, M the
  *   bond-based operator of the same kernel on the full periodic box without
  *   masks (its symbol Ĉ(0) - Ĉ(k), shifted by a quarter of its mean diagonal
  *   at the first nonzero wavenumber along x so that k = 0 is invertible),
  *   applied by transforms; in FP32 when combined with PD_SOLVE_MIXED.  Not a
  *   method of the paper: an option for the solve only.
- * PD_ENOTCONV when maxit CG iterations did not reach rtol; PD_EINVAL for
- * unknown option bits. */
+ * The call returns when done (the host checks the residual norm of each
+ * iteration one iteration late, so one more iteration than needed may run).
+ * PD_ENOTCONV when maxit CG iterations did not reach rtol; PD_ENUMERIC when a
+ * residual norm is not finite (e.g. a NaN in b); PD_EINVAL for unknown option
+ * bits. */
 pd_status pd_static_solve(pd_plan plan, const void* b, const void* w, void* u_inout, double rtol,
                           int maxit, int options, pd_solve_info* info, void* stream);
 

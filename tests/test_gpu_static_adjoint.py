@@ -150,6 +150,24 @@ def test_static_cap_and_converged_start(mixed, precond):
     plan.close()
 
 
+@pytest.mark.parametrize("precond", [False, True])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_static_nonfinite_load_reports_numeric(mixed, precond):
+    """A NaN in the body force on an unconstrained component: every solve
+    variant returns PD_ENUMERIC (the residual norm is not finite) without
+    iterating.  (A NaN where chi_O = 0 is masked out by the problem itself.)"""
+    from paper_2105_06055_amd import binding
+    w = wl.cube_void_static(seed=2, nb=12, nfft=16, clamp_layers=3)
+    plan = binding.Plan.from_workload(w, dtype=torch.float64, mixed=mixed)
+    b = w.b.copy()
+    free = np.argwhere(w.chiO[1] == 1)      # an unconstrained body component
+    b[(1,) + tuple(free[len(free) // 2])] = np.nan
+    u, info = plan.static_solve(_dev(b), rtol=1e-10, maxit=100, mixed=mixed, precond=precond, check=False)
+    assert info["status"] == binding.PD_ENUMERIC
+    assert info["iters_fp32"] == 0 and info["iters_fp64"] == 0
+    plan.close()
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_force_adjoint_scale_weights(orc, dtype):
     from paper_2105_06055_amd import binding
