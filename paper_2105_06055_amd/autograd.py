@@ -50,9 +50,10 @@ class VerletRollout(torch.autograd.Function):
             st["s"] = s.detach().contiguous()
         ckpts = [(st["u"].clone(), st["v"].clone())]
         k = max(1, int(checkpoint_every))
-        for i in range(nsteps):
-            plan.verlet(st, dt_, 1, b=b)
-            if (i + 1) % k == 0 and i + 1 < nsteps:
+        # one library call per segment (the call repeats the same step)
+        for k0 in range(0, nsteps, k):
+            plan.verlet(st, dt_, min(k, nsteps - k0), b=b)
+            if k0 + k < nsteps:
                 ckpts.append((st["u"].clone(), st["v"].clone()))
         ctx.plan, ctx.dt, ctx.nsteps, ctx.k, ctx.b = plan, dt_, nsteps, k, b
         ctx.ckpts = ckpts
