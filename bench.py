@@ -397,7 +397,7 @@ def main():
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; the multi-GPU (slab + halo) path is a design "
+        print("bench.py: the library runs on one GPU; the multi-GPU (slab + halo) path is a design "
               "only, so --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 

@@ -48,7 +48,7 @@ typedef enum {
     PD_EDEVICE = 3,       /* a HIP runtime call failed */
     PD_ENOTCONV = 4,      /* iterative solver reached maxit */
     PD_ENUMERIC = 5,      /* NaN or Inf detected */
-    PD_EUNSUPPORTED = 6   /* valid request this build does not implement */
+    PD_EUNSUPPORTED = 6   /* valid request the library does not implement */
 } pd_status;
 
 typedef enum { PD_F32 = 0, PD_F64 = 1 } pd_dtype;
