@@ -779,6 +779,29 @@ struct MulPre {
             return cscale(kmul(r0, in[0]) + kmul(r1, in[1]) + kmul(r2, in[2]), inv);
         }
     }
+    // All outputs from one evaluation of the symbol and its inverse (the
+    // last-axis pass uses this when a multiplier provides it).
+    __device__ __forceinline__ void all(const T* K, const cx<T>* in, cx<T>* out) const {
+        auto Sij = [&](int i, int j) {
+            const T m = (i == j) ? K[symi(D, i, j)] : -K[symi(D, i, j)];
+            return (i == j ? k0n[i] : T(0)) - kscale * m;
+        };
+        if constexpr (D == 2) {
+            const T a = Sij(0, 0), b = Sij(1, 1), d = Sij(0, 1);
+            const T inv = outscale / (a * b - d * d);
+            out[0] = cscale(kmul(b, in[0]) + kmul(-d, in[1]), inv);
+            out[1] = cscale(kmul(-d, in[0]) + kmul(a, in[1]), inv);
+        } else {
+            const T a = Sij(0, 0), b = Sij(1, 1), c = Sij(2, 2);
+            const T d = Sij(0, 1), e = Sij(0, 2), f = Sij(1, 2);
+            const T A00 = b * c - f * f, A01 = e * f - d * c, A02 = d * f - e * b;
+            const T A11 = a * c - e * e, A12 = d * e - a * f, A22 = a * b - d * d;
+            const T inv = outscale / (a * A00 + d * A01 + e * A02);
+            out[0] = cscale(kmul(A00, in[0]) + kmul(A01, in[1]) + kmul(A02, in[2]), inv);
+            out[1] = cscale(kmul(A01, in[0]) + kmul(A11, in[1]) + kmul(A12, in[2]), inv);
+            out[2] = cscale(kmul(A02, in[0]) + kmul(A12, in[1]) + kmul(A22, in[2]), inv);
+        }
+    }
 };
 
 // Preconditioner input: chi_O r (r in TR, converted to the chain type).

@@ -280,6 +280,50 @@ __device__ __forceinline__ void spectral_out(const M& mul, const T* __restrict__
     }
 }
 
+// Multipliers that form all outputs of a wavenumber at once (mul.all).
+template <class M, class = void>
+struct has_all_out : std::false_type {};
+template <class M>
+struct has_all_out<M, std::void_t<decltype(&M::all)>> : std::true_type {};
+
+// All outputs for the 8 wavenumbers of thread j: every kernel component
+// evaluated once per wavenumber, then mul.all.
+template <class T, class M, int NIN, int NOUT>
+__device__ __forceinline__ void spectral_all(const M& mul, const T* __restrict__ B_g, int ntap, uint32_t oddmask,
+                                             int j, int Tn, int n_last, const cx<T>* __restrict__ twl_g,
+                                             const cx<T> (&vin)[NIN][8], cx<T> (&w)[NOUT][8]) {
+    const uint32_t odd = M::RT_ODD ? oddmask : M::ODD;
+    lds_ptr<const T> B = as_lds(B_g);
+    lds_ptr<const cx<T>> twl = as_lds(twl_g);
+    T Bt[M::NC][9];
+#pragma unroll
+    for (int c = 0; c < M::NC; ++c)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) Bt[c][t] = (t < ntap) ? B[c * ntap + t] : T(0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int k = j + Tn * q;
+        T K[M::NC];
+#pragma unroll
+        for (int c = 0; c < M::NC; ++c) K[c] = Bt[c][0];
+#pragma unroll
+        for (int t = 1; t < 9; ++t) {
+            if (t < ntap) {
+                cx<T> tw = twl[(k * t) & (n_last - 1)];
+                const T cs = tw.r, sn = -tw.i;
+#pragma unroll
+                for (int c = 0; c < M::NC; ++c) K[c] += Bt[c][t] * (((odd >> (M::C0 + c)) & 1u) ? sn : cs);
+            }
+        }
+        cx<T> a[NIN], o[NOUT];
+#pragma unroll
+        for (int f = 0; f < NIN; ++f) a[f] = vin[f][q];
+        mul.all(K, a, o);
+#pragma unroll
+        for (int f = 0; f < NOUT; ++f) w[f][q] = o[f];
+    }
+}
+
 // Compile-time loop over the outputs: multiply, inverse FFT, store.
 template <int O, int NO>
 struct OutLoop {
@@ -344,20 +388,38 @@ __global__ void __launch_bounds__(256) k_lastmul(Lines ln, M mul, cx<T>* S, cons
 #pragma unroll
     for (int f = 0; f < NI; ++f) fft_line<-1>(vin[f], j, lgN, tw, 0, line);
     const T* Bt = tl + l * (M::NC * ntap);
-    OutLoop<0, NO>::run([&](auto Oc) {
-        constexpr int O = decltype(Oc)::value;
-        cx<T> w[8];
-        spectral_out<O, T, M, NI>(mul, Bt, ntap, oddmask, j, Tn, N, tw, vin, w);
-        fft_line<1>(w, j, lgN, tw, 0, line);
-        if (ok) {
-            cx<T>* dst = S + (ln.out_off + O) * ln.fstride + li * ln.pitch;
+    if constexpr (has_all_out<M>::value) {
+        // one symbol evaluation per wavenumber for all outputs
+        cx<T> wa[NO][8];
+        spectral_all<T, M, NI, NO>(mul, Bt, ntap, oddmask, j, Tn, N, tw, vin, wa);
+        OutLoop<0, NO>::run([&](auto Oc) {
+            constexpr int O = decltype(Oc)::value;
+            fft_line<1>(wa[O], j, lgN, tw, 0, line);
+            if (ok) {
+                cx<T>* dst = S + (ln.out_off + O) * ln.fstride + li * ln.pitch;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int p = j + Tn * q;
-                if (p < ln.len) dst[p] = w[q];
+                for (int q = 0; q < 8; ++q) {
+                    const int p = j + Tn * q;
+                    if (p < ln.len) dst[p] = wa[O][q];
+                }
             }
-        }
-    });
+        });
+    } else {
+        OutLoop<0, NO>::run([&](auto Oc) {
+            constexpr int O = decltype(Oc)::value;
+            cx<T> w[8];
+            spectral_out<O, T, M, NI>(mul, Bt, ntap, oddmask, j, Tn, N, tw, vin, w);
+            fft_line<1>(w, j, lgN, tw, 0, line);
+            if (ok) {
+                cx<T>* dst = S + (ln.out_off + O) * ln.fstride + li * ln.pitch;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int p = j + Tn * q;
+                    if (p < ln.len) dst[p] = w[q];
+                }
+            }
+        });
+    }
 }
 
 // ----------------------------------------------------------------------------
