@@ -152,7 +152,8 @@ __global__ void k_fill(T* p, long n, T v) {
 
 namespace pdk {
 
-static __global__ void k_reduce_final(const double* __restrict__ part, long nblk, int NR, double* __restrict__ out) {
+static __global__ void k_reduce_final(const double* __restrict__ part, long nblk, int NR, double* __restrict__ out,
+                                      double* __restrict__ host) {
     __shared__ double sm[256];
     for (int r = 0; r < NR; ++r) {
         double s = 0;
@@ -163,7 +164,10 @@ static __global__ void k_reduce_final(const double* __restrict__ part, long nblk
             if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
             __syncthreads();
         }
-        if (threadIdx.x == 0) out[r] = sm[0];
+        if (threadIdx.x == 0) {
+            out[r] = sm[0];
+            if (host) host[r] = sm[0];
+        }
         __syncthreads();
     }
 }
@@ -554,7 +558,8 @@ pd_status launch_xinv_lg(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t s
     }
     PD_TRY(pdh::check(hipGetLastError()));
     if (F::NRED > 0) {
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, p->partials, nblk, F::NRED, p->red);
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, p->partials, nblk, F::NRED, p->red,
+                           (double*)nullptr);
         PD_TRY(pdh::check(hipGetLastError()));
     }
     return PD_OK;
@@ -971,6 +976,12 @@ pd_status plan_alloc(pd_plan p, hipStream_t st, const uint8_t* chiB_h, const uin
         HIP_TRY(hipMalloc(&p->partials, sizeof(double) * p->partials_cap));
         HIP_TRY(hipMalloc(&p->red, sizeof(double) * 16));
         HIP_TRY(hipHostMalloc(&p->red_host, sizeof(double) * 16, hipHostMallocDefault));
+        // the device address of the pinned buffer, for reductions that write
+        // their result straight to the host (null: results are copied)
+        if (hipHostGetDevicePointer((void**)&p->red_host_dev, p->red_host, 0) != hipSuccess) {
+            p->red_host_dev = nullptr;
+            (void)hipGetLastError();
+        }
     }
     return PD_OK;
 }
@@ -1342,8 +1353,8 @@ __global__ void k_vva_final(T* __restrict__ ub, T* __restrict__ vb, const T* __r
 }
 
 template <int NR>
-pd_status ew_finish(pd_plan p, unsigned nblk, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, p->partials, (long)nblk, NR, out);
+pd_status ew_finish(pd_plan p, unsigned nblk, double* out, hipStream_t st, double* host = nullptr) {
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, p->partials, (long)nblk, NR, out, host);
     return pdh::check(hipGetLastError());
 }
 
@@ -1586,23 +1597,28 @@ pd_status verlet_adjoint_impl(pd_plan p, const T* un, const T* unp1, const T* s,
 
 // --------------------------------------------------------- static solve
 // The host reads the residual norm of each CG iteration one iteration late:
-// the value is copied to pinned memory behind that iteration's kernels and
-// the host waits for it only after the next iteration is queued, so the
-// device never idles on a host round trip.  Slots 8 and 9 of red_host.
+// the reduction writes the value to pinned host memory as well (or it is
+// copied there behind the iteration's kernels) and the host waits for it
+// only after the next iteration is queued, so the device never idles on a
+// host round trip.  Slots 8 and 9 of red_host.
 struct LagRead {
     hipEvent_t ev[2] = {nullptr, nullptr};
     double* h = nullptr;
+    double* hd = nullptr;   // device address of h (the reduction writes it), or null
     pd_status init(pd_plan p) {
         h = p->red_host + 8;
+        hd = p->red_host_dev ? p->red_host_dev + 8 : nullptr;
         for (hipEvent_t& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         return PD_OK;
     }
+    // host slot of iteration k as the reduction kernel addresses it
+    double* dslot(int k) const { return hd ? hd + (k & 1) : nullptr; }
     ~LagRead() {
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
     }
     pd_status post(int k, const double* src, hipStream_t st) {
-        HIP_TRY(hipMemcpyAsync(h + (k & 1), src, sizeof(double), hipMemcpyDeviceToHost, st));
+        if (!hd) HIP_TRY(hipMemcpyAsync(h + (k & 1), src, sizeof(double), hipMemcpyDeviceToHost, st));
         return pdh::check(hipEventRecord(ev[k & 1], st));
     }
     pd_status get(int k, double* v) {
@@ -1663,7 +1679,7 @@ pd_status cg_run(pd_plan p, TX* x_unused, T* xT, T* r, T* pp, T* Ap, double rr0,
         PD_TRY((lin_apply<T, 2>(p, pp, Ap, nullptr, st)));   // red[0] = p.Ap
         hipLaunchKernelGGL((k_cg_update<T, T>), dim3(nb), dim3(EW_THREADS), 0, st, xT, (const T*)pp, r, (const T*)Ap,
                            (const double*)rho, (const double*)dev, n, p->partials);
-        PD_TRY(ew_finish<1>(p, nb, rho_new, st));
+        PD_TRY(ew_finish<1>(p, nb, rho_new, st, lag.dslot(k)));
         PD_TRY(lag.post(k, rho_new, st));
         hipLaunchKernelGGL(k_cg_dir<T>, dim3(nb), dim3(EW_THREADS), 0, st, pp, (const T*)r, (const double*)rho_new,
                            (const double*)rho, (double*)nullptr, n);
@@ -1749,7 +1765,7 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
                 hipLaunchKernelGGL((k_cg_update<double, double>), dim3(nb), dim3(EW_THREADS), 0, st, u,
                                    (const double*)pp, r, (const double*)Ap, (const double*)rho, (const double*)dev, n,
                                    p->partials);
-                PD_TRY(ew_finish<1>(p, nb, dev + kRedRR, st));
+                PD_TRY(ew_finish<1>(p, nb, dev + kRedRR, st, lag.dslot(k)));
                 PD_TRY(lag.post(k, dev + kRedRR, st));
                 PD_TRY((precond_apply<double, double, double>(p, r, z, st)));   // red[0] = r.z
                 hipLaunchKernelGGL(k_pcg_dir<double>, dim3(nb), dim3(EW_THREADS), 0, st, pp, (const double*)z,
@@ -1801,7 +1817,7 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
             PD_TRY((lin_apply<float, 2>(q, p32, Ap32, nullptr, st)));   // q->red[0] = p32 . Ap32
             hipLaunchKernelGGL(k_cgm_update, dim3(nb), dim3(EW_THREADS), 0, st, u, (const float*)p32, r,
                                (const float*)Ap32, (const double*)rho, (const double*)dev, n, q->partials);
-            PD_TRY(ew_finish<1>(q, nb, dev + kRedRR, st));
+            PD_TRY(ew_finish<1>(q, nb, dev + kRedRR, st, lag.dslot(k)));
             PD_TRY(lag.post(k, dev + kRedRR, st));
             if (pre) {
                 PD_TRY((precond_apply<float, double, float>(q, r, z32, st)));   // q->red[0] = r.z

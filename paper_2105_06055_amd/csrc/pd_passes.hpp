@@ -1320,7 +1320,9 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
 }
 
 // Deterministic final sum of per-block partials: out[r] = sum_b part[b*NR + r]
-// (one block, fixed order tree).
-static __global__ void k_reduce_final(const double* __restrict__ part, long nblk, int NR, double* __restrict__ out);
+// (one block, fixed order tree), also written to host[r] when host is not
+// null (the device address of a pinned host buffer).
+static __global__ void k_reduce_final(const double* __restrict__ part, long nblk, int NR, double* __restrict__ out,
+                                      double* __restrict__ host);
 
 }  // namespace pdk

@@ -69,7 +69,8 @@ struct pd_plan_s {
     double* partials;            // per-block reduction partials
     long partials_cap;
     double* red;                 // final reductions [8]
-    double* red_host;            // pinned host copy [8]
+    double* red_host;            // pinned host copy [16]
+    double* red_host_dev;        // device address of red_host (null if not mapped)
     int* offs_dev;               // stencil offsets [ns][3]
     double* kval_dev;            // kernel values [ns][ncs]
     size_t bytes;
