@@ -82,7 +82,7 @@ def lib():
         _lib.orc_static_cg.restype = C.c_int
         _lib.orc_bb_force_adjoint.argtypes = [gp, C.c_double, dp, dp, dp, dp, dp]
         _lib.orc_verlet_adjoint.argtypes = [gp, C.c_double, C.c_double, up, dp, dp, dp, dp,
-                                            C.c_double, C.c_int, dp, dp, dp]
+                                            C.c_double, C.c_int, dp, dp, dp, dp]
     return _lib
 
 
@@ -248,9 +248,10 @@ def bb_force_adjoint(g: Geom, alpha, phi, u, gbar):
     return ub, pb
 
 
-def verlet_adjoint(g: Geom, alpha, rho, chiO, phi, b, u0, v0, dt, nsteps, ubarT, vbarT):
+def verlet_adjoint(g: Geom, alpha, rho, chiO, phi, b, u0, v0, dt, nsteps, ubarT, vbarT, want_bbar=False):
     """Reverse sweep of the fixed-weight EC Verlet rollout.  Returns
-    (ubar0, vbar0, phibar)."""
+    (ubar0, vbar0, phibar), and bbar (the cotangent of the body force) as a
+    fourth value when want_bbar is set."""
     chiO = _mask(chiO)
     phi = _f64(phi)
     b = _f64(b)
@@ -259,9 +260,10 @@ def verlet_adjoint(g: Geom, alpha, rho, chiO, phi, b, u0, v0, dt, nsteps, ubarT,
     ub = _f64(ubarT).copy()
     vb = _f64(vbarT).copy()
     pb = np.zeros(phi.shape, dtype=np.float64)
+    bb = np.zeros_like(ub) if want_bbar else None
     lib().orc_verlet_adjoint(C.byref(g), alpha, rho, _u8(chiO), _d(phi), _d(b), _d(u0), _d(v0),
-                             dt, nsteps, _d(ub), _d(vb), _d(pb))
-    return ub, vb, pb
+                             dt, nsteps, _d(ub), _d(vb), _d(pb), _d(bb))
+    return (ub, vb, pb, bb) if want_bbar else (ub, vb, pb)
 
 
 # --------------------------------------------------------------------------

@@ -88,6 +88,14 @@ int orc_stencil(const orc_geom* g, int* offs, int cap) {
     return n;
 }
 
+/* The whole stencil in a buffer of its own size (free with free()). */
+static int* orc_stencil_alloc(const orc_geom* g, int* ns) {
+    int n = orc_stencil(g, NULL, 0);
+    int* S = (int*)malloc(sizeof(int) * 3 * (size_t)(n > 0 ? n : 1));
+    *ns = orc_stencil(g, S, n);
+    return S;
+}
+
 /* Neighbour linear index of node (x, y, z) shifted by o, or -1 if the
  * neighbour falls outside a non-periodic box. */
 static long orc_nbr(const orc_geom* g, int x, int y, int z, const int* o) {
@@ -123,9 +131,8 @@ double orc_bb_alpha(int dim, int influence, double E, double delta) {
  *   L_i(x) = phi(x) sum_o phi(x+o) alpha omega xi_i xi_j / r^2
  *            (u_j(x+o) - u_j(x)) dV                                        */
 void orc_bb_force(const orc_geom* g, double alpha, const double* phi, const double* u, double* L) {
-    int cap = 20000;
-    int* S = (int*)malloc(sizeof(int) * 3 * cap);
-    int ns = orc_stencil(g, S, cap);
+    int ns = 0;
+    int* S = orc_stencil_alloc(g, &ns);
     long N = orc_nodes(g);
     int D = g->dim;
     double dV = orc_dv(g);
@@ -163,9 +170,8 @@ void orc_bb_force(const orc_geom* g, double alpha, const double* phi, const doub
  * carries no force (the limit of f, since s + 3/2 s^2 + 1/2 s^3 = 0 at
  * s = -1).  No linearisation: evaluated bond by bond as written. */
 void orc_nbb_force(const orc_geom* g, double alpha, const double* phi, const double* u, double* L) {
-    int cap = 20000;
-    int* S = (int*)malloc(sizeof(int) * 3 * cap);
-    int ns = orc_stencil(g, S, cap);
+    int ns = 0;
+    int* S = orc_stencil_alloc(g, &ns);
     long N = orc_nodes(g);
     int D = g->dim;
     double dV = orc_dv(g);
@@ -203,9 +209,8 @@ void orc_nbb_force(const orc_geom* g, double alpha, const double* phi, const dou
  * for bond-breaking models, Eq. 47/102), in its direct bond form:
  *   W(x) = 1/2 phi(x) sum_o phi(x+o) alpha omega (xi . eta)^2 / r^2 dV      */
 void orc_bb_energy(const orc_geom* g, double alpha, const double* phi, const double* u, double* W) {
-    int cap = 20000;
-    int* S = (int*)malloc(sizeof(int) * 3 * cap);
-    int ns = orc_stencil(g, S, cap);
+    int ns = 0;
+    int* S = orc_stencil_alloc(g, &ns);
     long N = orc_nodes(g);
     int D = g->dim;
     double dV = orc_dv(g);
@@ -236,9 +241,8 @@ void orc_bb_energy(const orc_geom* g, double alpha, const double* phi, const dou
 /* Discrete weighted volume of the full horizon, m0 = sum_o omega r^2 dV
  * (Eq. 35 evaluated with the same one-point quadrature). */
 double orc_m0(const orc_geom* g) {
-    int cap = 20000;
-    int* S = (int*)malloc(sizeof(int) * 3 * cap);
-    int ns = orc_stencil(g, S, cap);
+    int ns = 0;
+    int* S = orc_stencil_alloc(g, &ns);
     double dV = orc_dv(g), m0 = 0;
     for (int s = 0; s < ns; ++s) {
         double r2 = 0;
@@ -264,9 +268,8 @@ double orc_m0(const orc_geom* g) {
  * Eq. 97 gives the local m).  theta_out may be NULL. */
 void orc_lps_force(const orc_geom* g, double E, double nu, const double* chi, const double* u,
                    double* theta_out, double* L) {
-    int cap = 20000;
-    int* S = (int*)malloc(sizeof(int) * 3 * cap);
-    int ns = orc_stencil(g, S, cap);
+    int ns = 0;
+    int* S = orc_stencil_alloc(g, &ns);
     long N = orc_nodes(g);
     double dV = orc_dv(g);
     double m0 = orc_m0(g);
@@ -335,9 +338,8 @@ void orc_lps_force(const orc_geom* g, double E, double nu, const double* chi, co
  *   d(x)    = 1 - chi_B lambda(x) cnt(x) / beta(x)   on chi_B = 1, else 0.
  * beta is the node's own family size within the body (Eq. 12). */
 void orc_damage_index(const orc_geom* g, const uint8_t* chiB, const uint8_t* lam, double* d, int32_t* cnt_out) {
-    int cap = 20000;
-    int* S = (int*)malloc(sizeof(int) * 3 * cap);
-    int ns = orc_stencil(g, S, cap);
+    int ns = 0;
+    int* S = orc_stencil_alloc(g, &ns);
     long N = orc_nodes(g);
 #pragma omp parallel for schedule(static)
     for (long id = 0; id < N; ++id) {
@@ -536,9 +538,8 @@ void orc_bb_force_adjoint(const orc_geom* g, double alpha, const double* phi, co
     int D = g->dim;
     if (ubar) orc_bb_force(g, alpha, phi, gb, ubar);
     if (!phibar) return;
-    int cap = 20000;
-    int* S = (int*)malloc(sizeof(int) * 3 * cap);
-    int ns = orc_stencil(g, S, cap);
+    int ns = 0;
+    int* S = orc_stencil_alloc(g, &ns);
     double dV = orc_dv(g);
 #pragma omp parallel for schedule(static)
     for (long id = 0; id < N; ++id) {
@@ -573,14 +574,17 @@ void orc_bb_force_adjoint(const orc_geom* g, double alpha, const double* phi, co
  *   u' = chi_O (u + dt v + c2 (L u + b)),  v' = chi_O (v + c1 (L u + b + L u' + b)),
  *   c1 = dt/(2 rho), c2 = dt^2/(2 rho).
  * Given ubar, vbar at the final time (overwritten with the cotangents of the
- * initial u0, v0) and returning d/dphi in phibar (accumulated), the
- * trajectory is stored and swept backwards:
+ * initial u0, v0) and returning d/dphi in phibar and d/db in bbar (both
+ * accumulated; bbar may be NULL), the trajectory is stored and swept
+ * backwards:
  *   a = chi_O vbar';  ut = ubar' + c1 L a;
  *   ubar = c1 L a + chi_O ut + c2 L(chi_O ut);  vbar = a + dt chi_O ut;
- *   phibar += c1 dphi<a, L(u + u')> + c2 dphi<chi_O ut, L u>.          */
+ *   phibar += c1 dphi<a, L(u + u')> + c2 dphi<chi_O ut, L u>;
+ *   bbar += c2 chi_O ut + 2 c1 a   (b enters u' once through F = L u + b,
+ *                                   and v' twice, through F and F').    */
 void orc_verlet_adjoint(const orc_geom* g, double alpha, double rho, const uint8_t* chiO,
                         const double* phi, const double* b, const double* u0, const double* v0,
-                        double dt, int nsteps, double* ubar, double* vbar, double* phibar) {
+                        double dt, int nsteps, double* ubar, double* vbar, double* phibar, double* bbar) {
     long N = orc_nodes(g);
     int D = g->dim;
     long n = N * D;
@@ -626,6 +630,7 @@ void orc_verlet_adjoint(const orc_geom* g, double alpha, double rho, const uint8
         for (long i = 0; i < n; ++i) {
             ubar[i] = c1 * La[i] + ut[i] + c2 * Lt[i];
             vbar[i] = a[i] + dt * ut[i];
+            if (bbar) bbar[i] += c2 * ut[i] + 2.0 * c1 * a[i];
         }
     }
     free(a); free(ut); free(La); free(us); free(pb);
@@ -666,9 +671,8 @@ double orc_bond_sc(int dim, int influence, double alpha, double G0, double delta
  *            (u_j(x+o) - u_j(x)) dV                                        */
 void orc_bond_force(const orc_geom* g, double alpha, const uint8_t* chiB, const uint8_t* mu, const double* u,
                     double* L) {
-    int cap = 20000;
-    int* S = (int*)malloc(sizeof(int) * 3 * cap);
-    int ns = orc_stencil(g, S, cap);
+    int ns = 0;
+    int* S = orc_stencil_alloc(g, &ns);
     long N = orc_nodes(g);
     int D = g->dim;
     double dV = orc_dv(g);
@@ -701,9 +705,8 @@ void orc_bond_force(const orc_geom* g, double alpha, const uint8_t* chiB, const 
  * directions of a bond break together.  Returns the number of flags
  * cleared. */
 long orc_bond_break(const orc_geom* g, double s_c, const uint8_t* chiB, uint8_t* mu, const double* u) {
-    int cap = 20000;
-    int* S = (int*)malloc(sizeof(int) * 3 * cap);
-    int ns = orc_stencil(g, S, cap);
+    int ns = 0;
+    int* S = orc_stencil_alloc(g, &ns);
     long N = orc_nodes(g);
     int D = g->dim;
     long broken = 0;
@@ -735,9 +738,8 @@ long orc_bond_break(const orc_geom* g, double s_c, const uint8_t* chiB, uint8_t*
  *   d(x) = 1 - sum_o mu(x, o) chi_B(x+o) / sum_o chi_B(x+o)   on chi_B = 1,
  * 0 off the body and for a node without body partners. */
 void orc_bond_damage(const orc_geom* g, const uint8_t* chiB, const uint8_t* mu, double* d) {
-    int cap = 20000;
-    int* S = (int*)malloc(sizeof(int) * 3 * cap);
-    int ns = orc_stencil(g, S, cap);
+    int ns = 0;
+    int* S = orc_stencil_alloc(g, &ns);
     long N = orc_nodes(g);
 #pragma omp parallel for schedule(static)
     for (long id = 0; id < N; ++id) {

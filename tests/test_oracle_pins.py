@@ -469,3 +469,17 @@ def test_p12_verlet_adjoint_fd(orc):
     fd = (loss(u0, v0, s + eps * ds)[0] - loss(u0, v0, s - eps * ds)[0]) / (2 * eps)
     # phibar is the cotangent of phi = chi s; chi = 1 here
     assert (pb * ds).sum() == pytest.approx(fd, rel=1e-6)
+    # the load: u(T) is affine in b, so the loss is quadratic in b and
+    # central differences are exact up to rounding
+    _, _, _, bb = orc.verlet_adjoint(g, alpha, rho, chiO, chi * s, b, u0, v0, dt, nsteps,
+                                     ubT, np.zeros_like(ubT), want_bbar=True)
+    db = rng.normal(size=b.shape) * 1e7
+
+    def loss_b(bv):
+        o = orc.verlet(g, mdl, chi, chiO, u0, v0, dt, nsteps, b=bv, s=s)
+        return ((o["u"] - target) ** 2).sum()
+
+    eps = 1e-2
+    fd = (loss_b(b + eps * db) - loss_b(b - eps * db)) / (2 * eps)
+    assert (bb * db).sum() == pytest.approx(fd, rel=1e-8)
+    assert np.all(bb[chiO == 0] == 0)
