@@ -193,18 +193,32 @@ typedef struct {
  *   -dV/2 <u, L>, external -dV <u, b>, and the shadow energy
  *   KE + PE + EXT - dt^2/(8 rho) dV |chi_O F|^2 that velocity Verlet
  *   conserves exactly for the linear undamaged operator; FP64 sums.
- * PD_EINVAL if dt <= 0 or dt > dt_max, PD_ENUMERIC if the state became
- * non-finite (checked when energy_out is requested). */
+ * PD_EINVAL if dt <= 0 or dt > dt_max.  PD_ENUMERIC if a new force or
+ * velocity value of any step became NaN or infinite: the velocity-update
+ * epilogue raises a flag, which the call reads once after its last step (it
+ * synchronises the stream for that), and with energy_out also if an energy
+ * sum is not finite. */
 pd_status pd_verlet_step(pd_plan plan, pd_state* state, const void* b, const void* w, double dt,
                          int nsteps, double* energy_out, void* stream);
 
-/* Reverse-mode sweep of one velocity-Verlet step with fixed weights (w = 0,
- * time-independent b): given the states u_n and u_np1 = u_{n+1} and the
- * cotangents (u_bar, v_bar) of step n+1, overwrite u_bar, v_bar with the
- * cotangents of step n and accumulate d/ds into s_bar (SCALE plans, may be
- * NULL).  Uses two force-adjoint evaluations. */
+/* Reverse-mode sweep of one embedded-constraint velocity-Verlet step (the
+ * forward step of Eq. 67 with Eq. 83-84, differentiated by hand; the paper
+ * gives no adjoint) with fixed weights, w = 0 and a time-independent body
+ * force b.  With c1 = dt/(2 rho), c2 = dt^2/(2 rho), a = chi_O v_bar',
+ * ut = chi_O (u_bar' + c1 L a):
+ *   u_bar = c1 L a + ut + c2 L ut,   v_bar = a + dt ut,
+ *   b_bar += c2 ut + 2 c1 a,
+ *   s_bar += d/ds of c1 <a, L(u_n + u_np1)> + c2 <ut, L u_n>.
+ *   u_n, u_np1  [dim][body] the states of steps n and n+1
+ *   s           [body] micromodulus scale (SCALE plans, else NULL)
+ *   u_bar, v_bar [dim][body] in: cotangents of step n+1; out: of step n
+ *   s_bar       [body] accumulated (SCALE plans; NULL to skip)
+ *   b_bar       [dim][body] accumulated cotangent of b (NULL to skip)
+ * All DEVICE buffers of the plan dtype.  PD_EINVAL for NULL states or
+ * cotangents; PD_EUNSUPPORTED for INTEGRITY plans.  Uses two
+ * force-adjoint evaluations. */
 pd_status pd_verlet_adjoint(pd_plan plan, const void* u_n, const void* u_np1, const void* s,
-                            void* u_bar, void* v_bar, void* s_bar, double dt, void* stream);
+                            void* u_bar, void* v_bar, void* s_bar, void* b_bar, double dt, void* stream);
 
 typedef struct {
     int iters_fp64;        /* FP64 CG iterations (FP64 solves) or FP64 residual

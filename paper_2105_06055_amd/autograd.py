@@ -5,7 +5,11 @@
 ``VerletRollout`` nsteps embedded-constraint velocity-Verlet steps from
                  (u0, v0) with checkpoints every ``checkpoint_every`` steps;
                  the backward pass recomputes each segment from its
-                 checkpoint and sweeps it in reverse with pd_verlet_adjoint.
+                 checkpoint and sweeps it in reverse with pd_verlet_adjoint,
+                 giving cotangents for u0, v0, the micromodulus scale s and
+                 the body force b.  A checkpoint holds (u, v, F), so the
+                 recomputation resumes with the force the forward pass
+                 carried and repeats the forward states bit for bit.
 
 Both forward and backward run entirely in the library's kernels; PyTorch only
 provides the tensors and the autograd bookkeeping.  The adjoint assumes fixed
@@ -48,13 +52,14 @@ class VerletRollout(torch.autograd.Function):
               "F": torch.zeros_like(u0), "step": 0}
         if s is not None:
             st["s"] = s.detach().contiguous()
-        ckpts = [(st["u"].clone(), st["v"].clone())]
+        b = None if b is None else b.detach().contiguous()
+        ckpts = [(st["u"].clone(), st["v"].clone(), None)]
         k = max(1, int(checkpoint_every))
         # one library call per segment (the call repeats the same step)
         for k0 in range(0, nsteps, k):
             plan.verlet(st, dt_, min(k, nsteps - k0), b=b)
             if k0 + k < nsteps:
-                ckpts.append((st["u"].clone(), st["v"].clone()))
+                ckpts.append((st["u"].clone(), st["v"].clone(), st["F"].clone()))
         ctx.plan, ctx.dt, ctx.nsteps, ctx.k, ctx.b = plan, dt_, nsteps, k, b
         ctx.ckpts = ckpts
         ctx.s = st.get("s")
@@ -68,12 +73,17 @@ class VerletRollout(torch.autograd.Function):
         vb = torch.zeros_like(ref) if vbT is None else vbT.detach().clone().contiguous()
         s = ctx.s
         sb = torch.zeros_like(s) if s is not None else None
+        bb = torch.zeros_like(b) if (b is not None and ctx.needs_input_grad[7]) else None
         nseg = len(ctx.ckpts)
         for seg in range(nseg - 1, -1, -1):
             k0 = seg * k
             length = min(k, nsteps - k0)
-            u_c, v_c = ctx.ckpts[seg]
-            st = {"u": u_c.clone(), "v": v_c.clone(), "F": torch.zeros_like(u_c), "step": 0}
+            u_c, v_c, F_c = ctx.ckpts[seg]
+            # from the first checkpoint the call forms F itself (step 0), as
+            # the forward pass did; later ones resume with the stored F
+            st = {"u": u_c.clone(), "v": v_c.clone(),
+                  "F": torch.zeros_like(u_c) if F_c is None else F_c.clone(),
+                  "step": 0 if F_c is None else k0}
             if s is not None:
                 st["s"] = s
             us = [st["u"].clone()]
@@ -81,5 +91,5 @@ class VerletRollout(torch.autograd.Function):
                 plan.verlet(st, dt, 1, b=b)
                 us.append(st["u"].clone())
             for i in range(length - 1, -1, -1):
-                plan.verlet_adjoint(us[i], us[i + 1], ub, vb, dt, s=s, s_bar=sb)
-        return None, ub, vb, sb, None, None, None, None
+                plan.verlet_adjoint(us[i], us[i + 1], ub, vb, dt, s=s, s_bar=sb, b_bar=bb)
+        return None, ub, vb, sb, None, None, None, bb

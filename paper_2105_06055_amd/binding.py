@@ -94,7 +94,7 @@ def lib():
     L.pd_force_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.pd_verlet_step.argtypes = [vp, C.POINTER(State), vp, vp, C.c_double, C.c_int,
                                  C.POINTER(C.c_double), vp]
-    L.pd_verlet_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_double, vp]
+    L.pd_verlet_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, vp]
     L.pd_static_solve.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int, C.c_int,
                                   C.POINTER(SolveInfo), vp]
     L.pd_damage_index.argtypes = [vp, vp, vp, vp]
@@ -246,11 +246,11 @@ class Plan:
             return np.array(en, dtype=np.float64).reshape(nsteps, 4)
         return None
 
-    def verlet_adjoint(self, u_n, u_np1, u_bar, v_bar, dt, s=None, s_bar=None):
+    def verlet_adjoint(self, u_n, u_np1, u_bar, v_bar, dt, s=None, s_bar=None, b_bar=None):
         _check(lib().pd_verlet_adjoint(self._h, _ptr(self._vec(u_n, "u_n")), _ptr(self._vec(u_np1, "u_np1")),
                                        _ptr(self._sca(s, "s")), _ptr(self._vec(u_bar, "u_bar")),
                                        _ptr(self._vec(v_bar, "v_bar")), _ptr(self._sca(s_bar, "s_bar")),
-                                       float(dt), _stream()), "pd_verlet_adjoint")
+                                       _ptr(self._vec(b_bar, "b_bar")), float(dt), _stream()), "pd_verlet_adjoint")
 
     def static_solve(self, b, w=None, u0=None, rtol=1e-10, maxit=100000, mixed=False, precond=False,
                      check=True):

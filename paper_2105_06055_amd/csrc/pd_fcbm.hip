@@ -72,14 +72,14 @@ pd_status pd_verlet_step(pd_plan p, pd_state* state, const void* b, const void* 
 }
 
 pd_status pd_verlet_adjoint(pd_plan p, const void* u_n, const void* u_np1, const void* s, void* u_bar, void* v_bar,
-                            void* s_bar, double dt, void* stream) {
+                            void* s_bar, void* b_bar, double dt, void* stream) {
     if (!p) return PD_EINVAL;
     if (p->kern.model == PD_BB_NONLINEAR) return PD_EUNSUPPORTED;
     if (p->dtype == PD_F32)
         return verlet_adjoint_impl<float>(p, (const float*)u_n, (const float*)u_np1, (const float*)s, (float*)u_bar,
-                                          (float*)v_bar, (float*)s_bar, dt, S_(stream));
+                                          (float*)v_bar, (float*)s_bar, (float*)b_bar, dt, S_(stream));
     return verlet_adjoint_impl<double>(p, (const double*)u_n, (const double*)u_np1, (const double*)s, (double*)u_bar,
-                                       (double*)v_bar, (double*)s_bar, dt, S_(stream));
+                                       (double*)v_bar, (double*)s_bar, (double*)b_bar, dt, S_(stream));
 }
 
 pd_status pd_static_solve(pd_plan p, const void* b, const void* w, void* u_inout, double rtol, int maxit, int options,

@@ -888,6 +888,8 @@ inline void plan_free(pd_plan p) {
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->red_host) (void)hipHostFree(p->red_host);
+    for (hipEvent_t e : p->lag_ev)
+        if (e) (void)hipEventDestroy(e);
     if (p->prof) {
         for (ProfRec& r : *p->prof) {
             (void)hipEventDestroy(r.a);
@@ -982,6 +984,9 @@ pd_status plan_alloc(pd_plan p, hipStream_t st, const uint8_t* chiB_h, const uin
             p->red_host_dev = nullptr;
             (void)hipGetLastError();
         }
+        // the solver's lagged residual reads wait on these (created once, so
+        // that a solve creates no runtime objects)
+        for (hipEvent_t& e : p->lag_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
     return PD_OK;
 }
@@ -1342,13 +1347,16 @@ __global__ void k_vva_ut(T* __restrict__ ut, const T* __restrict__ ub, const T* 
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
         ut[k] = chiO[k] ? ub[k] + c1 * La[k] : T(0);
 }
-// ub = c1 La + ut + c2 Lut;  vb = a + dt ut
+// ub = c1 La + ut + c2 Lut;  vb = a + dt ut;  bb += c2 ut + 2 c1 a (bb may be null)
 template <class T>
-__global__ void k_vva_final(T* __restrict__ ub, T* __restrict__ vb, const T* __restrict__ a, const T* __restrict__ ut,
-                            const T* __restrict__ La, const T* __restrict__ Lut, T c1, T c2, T dt, long n) {
+__global__ void k_vva_final(T* __restrict__ ub, T* __restrict__ vb, T* __restrict__ bb, const T* __restrict__ a,
+                            const T* __restrict__ ut, const T* __restrict__ La, const T* __restrict__ Lut, T c1, T c2,
+                            T dt, long n) {
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        ub[k] = c1 * La[k] + ut[k] + c2 * Lut[k];
-        vb[k] = a[k] + dt * ut[k];
+        const T ak = a[k], utk = ut[k];
+        ub[k] = c1 * La[k] + utk + c2 * Lut[k];
+        vb[k] = ak + dt * utk;
+        if (bb) bb[k] += c2 * utk + T(2) * c1 * ak;
     }
 }
 
@@ -1431,7 +1439,7 @@ pd_status precond_apply(pd_plan p, const TR* r, TZ* z, hipStream_t st) {
 }
 
 template <class T, bool ENRED>
-pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, hipStream_t st) {
+pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, double* nanflag, hipStream_t st) {
     const int D = p->dim;
     const T rho = T(p->kern.rho);
     const T c1 = dt / (T(2) * rho), c2 = dt * dt / (T(2) * rho);
@@ -1451,7 +1459,7 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, hipSt
         FinLin<T, 3, 1, ENRED, true> fB{};
         fB.c = ctx<T>(p);
         fB.ka = T(p->ka); fB.u = u; fB.theta = reinterpret_cast<const T*>(p->theta);
-        fB.v = v; fB.F = F; fB.b = b; fB.c1 = c1; fB.rho = rho;
+        fB.v = v; fB.F = F; fB.b = b; fB.c1 = c1; fB.rho = rho; fB.nanflag = nanflag;
         return run_lps<T>(p, gA, fA, mB, fB, st);
     }
     auto go = [&](auto Dc) -> pd_status {
@@ -1463,7 +1471,7 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, hipSt
             gg.u = u; gg.v = v; gg.F = F; gg.w = w; gg.dt = dt; gg.c2 = c2;
             FinLin<T, DD, 1, ENRED, false> ff{};
             ff.c = ctx<T>(p);
-            ff.u = u; ff.v = v; ff.F = F; ff.b = b; ff.c1 = c1; ff.rho = rho;
+            ff.u = u; ff.v = v; ff.F = F; ff.b = b; ff.c1 = c1; ff.rho = rho; ff.nanflag = nanflag;
             return run_chain<T>(p, gg, MulBB<T, DD, false, false>{}, ff, st);
         }
         if constexpr (DD == 3) {
@@ -1480,7 +1488,7 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, hipSt
             FinBB<T, DD, WK, true, E, true, ENRED> ff{};
             ff.c = ctx<T>(p);
             ff.u = u; ff.lam = S->lambda; ff.s = reinterpret_cast<const T*>(S->s); ff.Wout = reinterpret_cast<T*>(S->W);
-            ff.v = v; ff.F = F; ff.b = b; ff.c1 = c1; ff.rho = rho;
+            ff.v = v; ff.F = F; ff.b = b; ff.c1 = c1; ff.rho = rho; ff.nanflag = nanflag;
             return run_chain<T>(p, gg, MulBB<T, DD, true, E>{}, ff, st);
         };
         if (wk == PD_WEIGHT_INTEGRITY) {
@@ -1495,6 +1503,9 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, hipSt
 
 template <class T>
 pd_status force_impl_any(pd_plan p, const T* u, const void* weight, T* L, T* W, hipStream_t st);
+
+// slot of red / red_host holding the Verlet call's non-finite flag
+constexpr int kNanSlot = 12;
 
 template <class T>
 pd_status verlet_impl(pd_plan p, pd_state* S, const T* b, const T* w, double dt, int nsteps, double* energy,
@@ -1516,9 +1527,24 @@ pd_status verlet_impl(pd_plan p, pd_state* S, const T* b, const T* w, double dt,
             HIP_TRY(hipGetLastError());
         }
     }
+    // Non-finite flag of the velocity updates: slot kNanSlot of the pinned
+    // host buffer, written by the epilogue through its mapped address (or a
+    // device slot copied back), cleared here and read once, after the last
+    // step of the call.
+    double* flag = nullptr;
+    if (nsteps > 0) {
+        if (p->red_host_dev) {
+            p->red_host[kNanSlot] = 0.0;
+            flag = p->red_host_dev + kNanSlot;
+        } else {
+            flag = p->red + kNanSlot;
+            hipLaunchKernelGGL(k_fill<double>, dim3(1), dim3(64), 0, st, flag, 1L, 0.0);
+            HIP_TRY(hipGetLastError());
+        }
+    }
     for (int k = 0; k < nsteps; ++k) {
         if (energy) {
-            PD_TRY((verlet_one<T, true>(p, S, b, w, T(dt), st)));
+            PD_TRY((verlet_one<T, true>(p, S, b, w, T(dt), flag, st)));
             double r[4];
             PD_TRY(fetch_red(p, 4, st, r));
             const double dV = p->dV;
@@ -1529,9 +1555,15 @@ pd_status verlet_impl(pd_plan p, pd_state* S, const T* b, const T* w, double dt,
             for (int q = 0; q < 4; ++q)
                 if (!std::isfinite(energy[4 * k + q])) return PD_ENUMERIC;
         } else {
-            PD_TRY((verlet_one<T, false>(p, S, b, w, T(dt), st)));
+            PD_TRY((verlet_one<T, false>(p, S, b, w, T(dt), flag, st)));
         }
         S->step += 1;
+    }
+    if (nsteps > 0) {
+        if (!p->red_host_dev)
+            HIP_TRY(hipMemcpyAsync(p->red_host + kNanSlot, flag, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (p->red_host[kNanSlot] != 0.0) return PD_ENUMERIC;
     }
     return PD_OK;
 }
@@ -1569,8 +1601,8 @@ pd_status adjoint_impl(pd_plan p, const T* u, const T* u2, const void* weight, c
 }
 
 template <class T>
-pd_status verlet_adjoint_impl(pd_plan p, const T* un, const T* unp1, const T* s, T* ub, T* vb, T* sb, double dt,
-                              hipStream_t st) {
+pd_status verlet_adjoint_impl(pd_plan p, const T* un, const T* unp1, const T* s, T* ub, T* vb, T* sb, T* bb,
+                              double dt, hipStream_t st) {
     if (!un || !unp1 || !ub || !vb) return PD_EINVAL;
     if (p->kern.weight == PD_WEIGHT_INTEGRITY) return PD_EUNSUPPORTED;
     if (p->kern.weight == PD_WEIGHT_SCALE && !s) return PD_EINVAL;
@@ -1590,8 +1622,8 @@ pd_status verlet_adjoint_impl(pd_plan p, const T* un, const T* unp1, const T* s,
                        p->chiO, n);
     HIP_TRY(hipGetLastError());
     PD_TRY(adjoint_impl<T>(p, un, nullptr, wgt, ut, Lut, sb, c2, 1, st));
-    hipLaunchKernelGGL(k_vva_final<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, st, ub, vb, (const T*)a, (const T*)ut,
-                       (const T*)La, (const T*)Lut, c1, c2, T(dt), n);
+    hipLaunchKernelGGL(k_vva_final<T>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, st, ub, vb, bb, (const T*)a,
+                       (const T*)ut, (const T*)La, (const T*)Lut, c1, c2, T(dt), n);
     return pdh::check(hipGetLastError());
 }
 
@@ -1602,21 +1634,18 @@ pd_status verlet_adjoint_impl(pd_plan p, const T* un, const T* unp1, const T* s,
 // only after the next iteration is queued, so the device never idles on a
 // host round trip.  Slots 8 and 9 of red_host.
 struct LagRead {
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};   // the plan's events
     double* h = nullptr;
     double* hd = nullptr;   // device address of h (the reduction writes it), or null
     pd_status init(pd_plan p) {
         h = p->red_host + 8;
         hd = p->red_host_dev ? p->red_host_dev + 8 : nullptr;
-        for (hipEvent_t& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        return PD_OK;
+        ev[0] = p->lag_ev[0];
+        ev[1] = p->lag_ev[1];
+        return (ev[0] && ev[1]) ? PD_OK : PD_EDEVICE;
     }
     // host slot of iteration k as the reduction kernel addresses it
     double* dslot(int k) const { return hd ? hd + (k & 1) : nullptr; }
-    ~LagRead() {
-        for (hipEvent_t e : ev)
-            if (e) (void)hipEventDestroy(e);
-    }
     pd_status post(int k, const double* src, hipStream_t st) {
         if (!hd) HIP_TRY(hipMemcpyAsync(h + (k & 1), src, sizeof(double), hipMemcpyDeviceToHost, st));
         return pdh::check(hipEventRecord(ev[k & 1], st));
@@ -1694,31 +1723,58 @@ pd_status cg_run(pd_plan p, TX* x_unused, T* xT, T* r, T* pp, T* Ap, double rr0,
     return PD_OK;
 }
 
+// Device memory a solve needs for its vectors (each one 256-byte aligned):
+// r and t in FP64, then FP64 p and Ap (plain and preconditioned FP64), z
+// (preconditioned FP64), or FP32 p and Ap (mixed) and z (mixed,
+// preconditioned).
+inline size_t solve_vec_bytes(long n, size_t elem) { return ((size_t)n * elem + 255) & ~(size_t)255; }
+inline size_t solve_workspace_bytes(pd_plan p, int options) {
+    const long n = p->nb * p->dim;
+    const bool mixed = (options & PD_SOLVE_MIXED) != 0, pre = (options & PD_SOLVE_PRECOND) != 0;
+    size_t tot = 2 * solve_vec_bytes(n, 8);
+    if (!mixed) tot += (pre ? 3 : 2) * solve_vec_bytes(n, 8);
+    else tot += (pre ? 3 : 2) * solve_vec_bytes(n, 4);
+    return tot;
+}
+
+// The solve's vectors come from hipMalloc (freed before return) or, when ws
+// is non-null, from the ws_bytes of device memory at ws (nothing is
+// allocated; the caller guarantees ws_bytes >= solve_workspace_bytes).
 inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, double* u, double rtol, int maxit,
-                                   int options, pd_solve_info* info, hipStream_t st) {
+                                   int options, pd_solve_info* info, hipStream_t st, void* ws = nullptr,
+                                   size_t ws_bytes = 0) {
     const bool mixed = (options & PD_SOLVE_MIXED) != 0, pre = (options & PD_SOLVE_PRECOND) != 0;
     if (options & ~(PD_SOLVE_MIXED | PD_SOLVE_PRECOND)) return PD_EINVAL;
     if (p->dtype != PD_F64) return PD_EINVAL;
     if (p->kern.weight != PD_WEIGHT_NONE) return PD_EUNSUPPORTED;
     if (!b || !u || !(rtol > 0) || maxit <= 0) return PD_EINVAL;
     if (mixed && !p->sub32) return PD_EINVAL;
+    if (ws && ws_bytes < solve_workspace_bytes(p, options)) return PD_EINVAL;
     const long n = p->nb * p->dim;
     pd_solve_info inf{};
     double *r = nullptr, *pp = nullptr, *Ap = nullptr, *t = nullptr, *z = nullptr;
     float *p32 = nullptr, *Ap32 = nullptr, *z32 = nullptr;
+    size_t ws_off = 0;
     auto cleanup = [&]() {
+        if (ws) return;
         void* bufs[] = {r, pp, Ap, t, z, p32, Ap32, z32};
         for (void* q : bufs)
             if (q) (void)hipFree(q);
     };
     auto fail = [&](pd_status s) { cleanup(); return s; };
+    auto vec = [&](auto** q, size_t elem) -> pd_status {
+        if (!ws) return pdh::check(hipMalloc(q, elem * n));
+        *q = reinterpret_cast<std::remove_pointer_t<decltype(q)>>(static_cast<unsigned char*>(ws) + ws_off);
+        ws_off += solve_vec_bytes(n, elem);
+        return PD_OK;
+    };
 #define SOLVE_TRY(x)                       \
     do {                                   \
         pd_status s2_ = (x);               \
         if (s2_ != PD_OK) return fail(s2_); \
     } while (0)
-    SOLVE_TRY(pdh::check(hipMalloc(&r, sizeof(double) * n)));
-    SOLVE_TRY(pdh::check(hipMalloc(&t, sizeof(double) * n)));
+    SOLVE_TRY(vec(&r, sizeof(double)));
+    SOLVE_TRY(vec(&t, sizeof(double)));
     // x = chi_O u + (1 - chi_O) w ; t = (1 - chi_O) w
     hipLaunchKernelGGL(k_constrain<double>, dim3(ew_blocks(n)), dim3(EW_THREADS), 0, st, u, t, w, p->chiO, n);
     SOLVE_TRY(pdh::check(hipGetLastError()));
@@ -1737,8 +1793,8 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
     pd_status result = PD_OK;
     const unsigned nb = ew_blocks(n);
     if (!mixed && !pre) {
-        SOLVE_TRY(pdh::check(hipMalloc(&pp, sizeof(double) * n)));
-        SOLVE_TRY(pdh::check(hipMalloc(&Ap, sizeof(double) * n)));
+        SOLVE_TRY(vec(&pp, sizeof(double)));
+        SOLVE_TRY(vec(&Ap, sizeof(double)));
         int its = 0, app = 0;
         double rr_end = rr;
         SOLVE_TRY((cg_run<double, double>(p, u, u, r, pp, Ap, rr, stop2, maxit, &its, &app, &rr_end, st)));
@@ -1746,9 +1802,9 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
         inf.applies_fp64 += app;
     } else if (!mixed) {
         // preconditioned CG in FP64
-        SOLVE_TRY(pdh::check(hipMalloc(&pp, sizeof(double) * n)));
-        SOLVE_TRY(pdh::check(hipMalloc(&Ap, sizeof(double) * n)));
-        SOLVE_TRY(pdh::check(hipMalloc(&z, sizeof(double) * n)));
+        SOLVE_TRY(vec(&pp, sizeof(double)));
+        SOLVE_TRY(vec(&Ap, sizeof(double)));
+        SOLVE_TRY(vec(&z, sizeof(double)));
         double* dev = p->red;
         int it = 0;
         if (rr > stop2) {
@@ -1790,9 +1846,9 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
         // late, so a replacement follows the iteration queued behind the one
         // that triggered it.
         pd_plan q = p->sub32;
-        SOLVE_TRY(pdh::check(hipMalloc(&p32, sizeof(float) * n)));
-        SOLVE_TRY(pdh::check(hipMalloc(&Ap32, sizeof(float) * n)));
-        if (pre) SOLVE_TRY(pdh::check(hipMalloc(&z32, sizeof(float) * n)));
+        SOLVE_TRY(vec(&p32, sizeof(float)));
+        SOLVE_TRY(vec(&Ap32, sizeof(float)));
+        if (pre) SOLVE_TRY(vec(&z32, sizeof(float)));
         double* dev = q->red;
         LagRead lag;
         SOLVE_TRY(lag.init(q));
@@ -1981,8 +2037,8 @@ namespace pdi {
     extern template pd_status test_conv_impl<T>(pd_plan, const T*, const int*, int, T*, hipStream_t);             \
     extern template pd_status verlet_impl<T>(pd_plan, pd_state*, const T*, const T*, double, int, double*,        \
                                              hipStream_t);                                                        \
-    extern template pd_status verlet_adjoint_impl<T>(pd_plan, const T*, const T*, const T*, T*, T*, T*, double,   \
-                                                     hipStream_t);                                                \
+    extern template pd_status verlet_adjoint_impl<T>(pd_plan, const T*, const T*, const T*, T*, T*, T*, T*,       \
+                                                     double, hipStream_t);                                        \
     extern template pd_status cg_run<T, T>(pd_plan, T*, T*, T*, T*, T*, double, double, int, int*, int*, double*, \
                                            hipStream_t);                                                          \
     extern template pd_status lin_apply<T, 3>(pd_plan, const T*, T*, const T*, hipStream_t);                      \

@@ -19,7 +19,7 @@ template pd_status verlet_impl<PD_INST_T>(pd_plan, pd_state*, const PD_INST_T*, 
                                           hipStream_t);
 #elif PD_INST_PART == 2
 template pd_status verlet_adjoint_impl<PD_INST_T>(pd_plan, const PD_INST_T*, const PD_INST_T*, const PD_INST_T*,
-                                                  PD_INST_T*, PD_INST_T*, PD_INST_T*, double, hipStream_t);
+                                                  PD_INST_T*, PD_INST_T*, PD_INST_T*, PD_INST_T*, double, hipStream_t);
 template pd_status cg_run<PD_INST_T, PD_INST_T>(pd_plan, PD_INST_T*, PD_INST_T*, PD_INST_T*, PD_INST_T*, PD_INST_T*,
                                                 double, double, int, int*, int*, double*, hipStream_t);
 template pd_status lin_apply<PD_INST_T, 3>(pd_plan, const PD_INST_T*, PD_INST_T*, const PD_INST_T*, hipStream_t);

@@ -68,6 +68,12 @@ __device__ __forceinline__ T ldf(const T* p, Nd n) {
 }
 template <class T>
 struct ident { using type = T; };
+// Raise the step's non-finite flag (a plain store of 1: every writer stores
+// the same value) when a new force or velocity value is NaN or infinite.
+template <class T>
+__device__ __forceinline__ void flag_nonfinite(double* flag, T Fn, T vn) {
+    if (flag && !(__builtin_isfinite(Fn) && __builtin_isfinite(vn))) *flag = 1.0;
+}
 template <class T>
 __device__ __forceinline__ void stf(T* p, Nd n, typename ident<T>::type v) {
     auto b = uniform_base(p + n.base) + n.off * (uint32_t)sizeof(T);
@@ -869,6 +875,7 @@ struct FinBB {
     T* L; T* Wout;
     T* v; T* F; const T* b;   // VV
     T c1, rho;
+    double* nanflag;          // VV: set to 1 on a non-finite F' or v (null: no check)
     __host__ double nbytes() const {
         const double t = sizeof(T);
         double r = D * t + 1 + (WK == WK_LAMBDA ? 1.0 : 0.0) + (WK == WK_SCALE ? t : 0.0);
@@ -941,6 +948,7 @@ struct FinBB {
                 T vn = Q.o[a] ? Q.v[a] + c1 * (Q.F[a] + Fn) : T(0);
                 stf(v + k, i, vn);
                 stf(F + k, i, Fn);
+                flag_nonfinite(nanflag, Fn, vn);
                 if constexpr (ENRED) {
                     red[0] += 0.5 * double(rho) * double(vn) * double(vn);
                     red[1] += -0.5 * double(Q.u[a]) * double(Li[a]);
@@ -1019,6 +1027,7 @@ struct FinLin {
     const T* u; const T* theta;
     T* L; T* v; T* F; const T* b;
     T c1, rho;
+    double* nanflag;   // MODE 1: set to 1 on a non-finite F' or v (null: no check)
     __host__ double nbytes() const {
         const double t = sizeof(T);
         double r = D * t + 1 + nsym(D) * t * c.edge_frac + (LPS ? t + D * t * c.edge_frac : 0.0);
@@ -1089,6 +1098,7 @@ struct FinLin {
                 T vn = Q.o[a] ? Q.v[a] + c1 * (Q.F[a] + Fn) : T(0);
                 stf(v + k, i, vn);
                 stf(F + k, i, Fn);
+                flag_nonfinite(nanflag, Fn, vn);
                 if constexpr (ENRED) {
                     red[0] += 0.5 * double(rho) * double(vn) * double(vn);
                     red[1] += -0.5 * double(Q.u[a]) * double(La);

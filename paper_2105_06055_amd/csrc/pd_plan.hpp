@@ -71,6 +71,7 @@ struct pd_plan_s {
     double* red;                 // final reductions [8]
     double* red_host;            // pinned host copy [16]
     double* red_host_dev;        // device address of red_host (null if not mapped)
+    hipEvent_t lag_ev[2];        // completion events of the solver's lagged residual reads
     int* offs_dev;               // stencil offsets [ns][3]
     double* kval_dev;            // kernel values [ns][ncs]
     size_t bytes;

@@ -1,8 +1,9 @@
-"""pd_force parity against the FP64 direct-summation oracle.
+"""pd_force parity against the FP64 direct-summation oracle, element by
+element over the whole field.
 
-Bar: FP64 relative L2 error <= 1e-12; FP32 error normalised by the operator
-scale, |L32 - L_oracle| / (lambda_max |u|) <= 1e-5 (lambda_max from the
-plan's stability bound), with the plain relative error also checked loosely.
+Bars (tests/parity.py): FP64 max |L - L_oracle| / max |L_oracle| <= 1e-12;
+FP32 max |L32 - L_oracle| / (lambda_max max |u|) <= 1e-5 (lambda_max from
+the plan's stability bound) and max |L32 - L_oracle| / max |L_oracle| <= 1e-4.
 """
 import numpy as np
 import pytest
@@ -10,6 +11,8 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from paper_2105_06055_amd import workloads as wl
+
+import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -23,19 +26,15 @@ def _dev(a, dtype):
     return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
 
 
-def _lam_max(plan, rho):
-    return rho * (2.0 / plan.info["dt_max"]) ** 2
+def _check(L, Lo, u, plan, rho, dtype, tag=""):
+    return parity.check_force(L, Lo, u, plan, rho, dtype == torch.float64, tag)
 
 
-def _check(L, Lo, u, plan, rho, dtype):
-    rel = np.linalg.norm(L - Lo) / np.linalg.norm(Lo)
-    if dtype == torch.float64:
-        assert rel <= 1e-12, rel
-    else:
-        e = np.linalg.norm(L - Lo) / (_lam_max(plan, rho) * np.linalg.norm(u))
-        assert e <= 1e-5, (e, rel)
-        assert rel <= 1e-3, rel
-    return rel
+def _same(La, Lb, Lo, dtype, what):
+    """Two GPU paths on the same plan agree element-wise to rounding."""
+    tol = 1e-13 if dtype == torch.float64 else 1e-5
+    e = float(np.max(np.abs(La - Lb)) / np.max(np.abs(Lo)))
+    assert e <= tol, (what, e)
 
 
 DT = [torch.float64, torch.float32]
@@ -141,12 +140,11 @@ def test_specialised_lastaxis_512(orc, dtype, model, body):
     else:
         Lo = orc.bb_force(g, orc.bb_alpha(D, 70e9, 3 * dx), chi.astype(float), u)
     _check(L, Lo, u, plan, 2700.0, dtype)
-    tol = 1e-13 if dtype == torch.float64 else 1e-5
     for mode in ("fft", "fft_generic", "yfft"):
         plan.set_lastaxis(mode)
         Lg = plan.force(_dev(u, dtype)).cpu().numpy()
         _check(Lg, Lo, u, plan, 2700.0, dtype)
-        assert np.linalg.norm(L - Lg) / np.linalg.norm(Lo) <= tol, mode
+        _same(L, Lg, Lo, dtype, mode)
     plan.close()
 
 
@@ -170,8 +168,18 @@ def test_bb2d_integrity_weights_and_energy(orc, dtype):
     Lo = orc.bb_force(g, alpha, phi, u)
     Wo = orc.bb_energy(g, alpha, phi, u)
     _check(L, Lo, u, plan, w.rho, dtype)
-    relW = np.linalg.norm(W - Wo) / np.linalg.norm(Wo)
-    assert relW <= (1e-11 if dtype == torch.float64 else 1e-2), relW
+    # W by the convolution form cancels terms of order (chi u)^2 against a
+    # result of order (u' - u)^2 (reading A18): its error is measured on the
+    # scale of those terms, lambda_max max|u|^2, and reported
+    lam = parity.lam_max(plan, w.rho)
+    eW = float(np.max(np.abs(W - Wo)) / (lam * np.max(np.abs(u)) ** 2))
+    relW = parity.rel_max(W, Wo)
+    print(f"energy density W: max err / (lambda_max max|u|^2) {eW:.2e}, rel_max {relW:.2e}")
+    if dtype == torch.float64:
+        assert relW <= 1e-11, relW
+    else:
+        assert eW <= 1e-5, eW
+        assert relW <= 1e-2, relW
     plan.close()
 
 
@@ -250,6 +258,32 @@ def test_yz_direct_tiles(orc, dtype, model, body, fft, r):
     plan.set_lastaxis("yfft")
     Ly = plan.force(_dev(u, dtype)).cpu().numpy()
     _check(Ly, Lo, u, plan, 2700.0, dtype)
-    tol = 1e-13 if dtype == torch.float64 else 1e-5
-    assert np.linalg.norm(L - Ly) / np.linalg.norm(Lo) <= tol
+    _same(L, Ly, Lo, dtype, "yfft")
+    plan.close()
+
+
+# The second influence function, omega = 1 (the paper's runs use 1/r): the
+# bond-based micromodulus, the LPS weighted volume and every kernel sample
+# change with it.
+@pytest.mark.parametrize("dtype", DT)
+@pytest.mark.parametrize("model,body,fft,m", [("bb", (37, 45), (64, 64), 3), ("bb", (20, 23, 17), (32, 32, 32), 2),
+                                              ("lps", (20, 17, 23), (32, 32, 32), 3)])
+def test_influence_one(orc, dtype, model, body, fft, m):
+    from paper_2105_06055_amd import binding
+    dx, D = 1e-3, len(body)
+    chi = wl.random_mask(body, 61)
+    u = wl.random_field((D,) + body, 62, 1e-6)
+    nu = 0.3 if model == "lps" else (1 / 3 if D == 2 else 0.25)
+    plan = binding.Plan(fft, body, dx, m * dx, model=model, E=70e9, nu=nu, rho=2700.0, chiB=chi, dtype=dtype,
+                        influence=1)
+    L = plan.force(_dev(u, dtype)).cpu().numpy()
+    g = orc.geom(body, dx, m * dx, influence=1)
+    if model == "lps":
+        Lo, _ = orc.lps_force(g, 70e9, nu, chi.astype(float), u)
+        assert plan.info["m0"] == pytest.approx(orc.m0(g), rel=1e-14)
+    else:
+        alpha = orc.bb_alpha(D, 70e9, m * dx, influence=1)
+        assert plan.info["alpha"] == pytest.approx(alpha, rel=1e-14)
+        Lo = orc.bb_force(g, alpha, chi.astype(float), u)
+    _check(L, Lo, u, plan, 2700.0, dtype, f"omega=1 {model} {body}")
     plan.close()

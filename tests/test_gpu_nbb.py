@@ -5,8 +5,9 @@ displacements large enough for the quadratic and cubic terms to matter, a
 finite rigid rotation (zero force) in 2D and 3D, and the full 512^2 plate
 on sampled nodes.
 
-Bar: FP64 relative L2 error <= 1e-12; FP32 error normalised by
-lambda_max |u| (1 + |u|_inf/dx)^2 (the operator scale, grown by the
+Bars, element by element over the whole field: FP64 max |L - L_oracle| /
+max |L_oracle| <= 1e-12; FP32 max |L - L_oracle| normalised by
+lambda_max max|u| (1 + max|u|/dx)^2 (the operator scale, grown by the
 nonlinear terms) <= 1e-5.
 """
 import numpy as np
@@ -31,13 +32,14 @@ def _plan(fft, body, dx, m, chi, dtype):
 
 
 def _check(L, Lo, u, plan, dx, dtype):
-    rel = np.linalg.norm(L - Lo) / np.linalg.norm(Lo)
+    rel = float(np.max(np.abs(L - Lo)) / np.max(np.abs(Lo)))
+    lam = 2440.0 * (2.0 / plan.info["dt_max"]) ** 2
+    scale = lam * np.abs(u).max() * (1 + np.abs(u).max() / dx) ** 2
+    e = float(np.max(np.abs(L - Lo)) / scale)
+    print(f"nonlinear BB parity {dtype}: rel_max {rel:.2e}, err / nonlinear operator scale {e:.2e}")
     if dtype == torch.float64:
         assert rel <= 1e-12, rel
     else:
-        lam = 2440.0 * (2.0 / plan.info["dt_max"]) ** 2
-        scale = lam * np.linalg.norm(u) * (1 + np.abs(u).max() / dx) ** 2
-        e = np.linalg.norm(L - Lo) / scale
         assert e <= 1e-5, (e, rel)
     return rel
 
@@ -75,8 +77,39 @@ def test_nbb2d_rigid_rotation_zero_force(orc, dtype):
     lam = 2440.0 * (2.0 / plan.info["dt_max"]) ** 2
     scale = lam * np.abs(u).max() * (1 + np.abs(u).max() / dx) ** 2
     err = np.abs(L).max() / scale
-    print(f"rigid rotation, {dtype}: max |L| / operator scale = {err:.2e}")
+    lin = np.abs(L).max() / (lam * np.abs(u).max())
+    print(f"rigid rotation, {dtype}: max |L| / operator scale = {err:.2e}, / linear scale = {lin:.2e}")
     assert err <= (1e-13 if dtype == torch.float64 else 1e-6)
+    assert lin <= (1e-11 if dtype == torch.float64 else 1e-3)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", DT)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nbb_small_rigid_rotation_linear_scale(dtype, dim):
+    """A rotation by 0.02 rad about the body centre (|u| below one spacing,
+    so the quadratic and cubic terms are at most a few times the linear
+    ones): the force vanishes to rounding on the scale of the LINEAR
+    operator, lambda_max max|u|."""
+    dx, m = 1e-3, 3
+    body, fft = ((40, 48), (64, 64)) if dim == 2 else ((14, 17, 19), (32, 32, 32))
+    chi = wl.random_mask(body, 53)
+    X = np.stack(np.meshgrid(*[(np.arange(n) - 0.5 * (n - 1)) * dx for n in body], indexing="ij")[::-1])
+    t = 0.02
+    if dim == 2:
+        R = np.array([[np.cos(t), -np.sin(t)], [np.sin(t), np.cos(t)]])
+    else:
+        k = np.array([1.0, 2.0, 2.0]) / 3.0
+        K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+        R = np.eye(3) + np.sin(t) * K + (1 - np.cos(t)) * K @ K
+    u = np.einsum("ij,j...->i...", R - np.eye(dim), X)
+    plan = _plan(fft, body, dx, m, chi, dtype)
+    L = plan.force(_dev(u, dtype)).cpu().numpy()
+    lam = 2440.0 * (2.0 / plan.info["dt_max"]) ** 2
+    lin = np.abs(L).max() / (lam * np.abs(u).max())
+    print(f"small rotation {dim}D {dtype}: max|u|/dx = {np.abs(u).max() / dx:.2f}, "
+          f"max |L| / linear scale = {lin:.2e}")
+    assert lin <= (1e-13 if dtype == torch.float64 else 1e-5)
     plan.close()
 
 
@@ -96,33 +129,17 @@ def test_nbb_plan_scope():
 
 
 @pytest.mark.parametrize("dtype", DT)
-def test_nbb2d_plate_512_sampled(orc, dtype):
-    """512^2 plate on the 1024^2 grid (delta = 3 dx) with holes: sampled nodes
-    against the oracle on a window of one horizon around each."""
+def test_nbb2d_plate_512_full_field(orc, dtype):
+    """512^2 plate on the 1024^2 grid (delta = 3 dx) with holes: every node
+    against the oracle."""
     body, fft, dx, m = (512, 512), (1024, 1024), 1e-3, 3
     chi = wl.random_mask(body, 44)
     u = wl.random_field((2,) + body, 45, 0.2 * dx)
     plan = _plan(fft, body, dx, m, chi, dtype)
     L = plan.force(_dev(u, dtype)).cpu().numpy()
-    alpha = orc.bb_alpha(2, 72e9, m * dx)
-    rng = np.random.default_rng(46)
-    pts = [tuple(int(v) for v in rng.integers(0, 512, size=2)) for _ in range(40)]
-    pts += [(0, 0), (0, 511), (511, 0), (511, 511)]
-    got, ref = [], []
-    for p in pts:
-        sl = tuple(slice(max(0, c - m), min(512, c + m + 1)) for c in p)
-        ctr = tuple(c - s.start for c, s in zip(p, sl))
-        g = orc.geom(chi[sl].shape, dx, m * dx)
-        Lo = orc.nbb_force(g, alpha, chi[sl].astype(float), u[(slice(None),) + sl])
-        got.append(L[(slice(None),) + p])
-        ref.append(Lo[(slice(None),) + ctr])
-    got, ref = np.array(got), np.array(ref)
-    if dtype == torch.float64:
-        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
-    else:
-        lam = 2440.0 * (2.0 / plan.info["dt_max"]) ** 2
-        scale = lam * np.abs(u).max() * (1 + np.abs(u).max() / dx) ** 2
-        assert np.abs(got - ref).max() <= 1e-5 * scale
+    g = orc.geom(body, dx, m * dx)
+    Lo = orc.nbb_force(g, orc.bb_alpha(2, 72e9, m * dx), chi.astype(float), u)
+    _check(L, Lo, u, plan, dx, dtype)
     plan.close()
 
 
