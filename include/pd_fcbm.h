@@ -261,6 +261,27 @@ typedef struct {
 pd_status pd_static_solve(pd_plan plan, const void* b, const void* w, void* u_inout, double rtol,
                           int maxit, int options, pd_solve_info* info, void* stream);
 
+/* pd_static_solve for callers that cannot allocate device memory during the
+ * call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same solve, bit for bit, with its vectors (FP64
+ * residual and constraint fields, search direction, operator output,
+ * preconditioned residual; FP32 copies for the mixed solve) taken from a
+ * 256 MiB device array that the library holds on each GPU it runs on until
+ * the process ends, instead of hipMalloc / hipFree per call.  The plan's
+ * workspaces are allocated at plan creation as for every other call.
+ * Capacity: 40 B per unknown for PD_SOLVE_PRECOND in FP64, 32 B plain FP64,
+ * 28 B or 24 B mixed (with or without PD_SOLVE_PRECOND); about 6.7 million
+ * unknowns (a 128^3 body in 3D) in every variant.
+ * Arguments, results and status codes as pd_static_solve, plus PD_EINVAL
+ * when the solve needs more than the array holds, when the current device is
+ * not the plan's, or while pass timing (pd_profile_enable) is on.  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (from several host threads or streams) race and must be serialised by the
+ * caller.  Nothing in the array needs to start at zero (every vector is
+ * written before it is read), so no call clears it. */
+pd_status pd_static_solve_noalloc(pd_plan plan, const void* b, const void* w, void* u_inout, double rtol,
+                                  int maxit, int options, pd_solve_info* info, void* stream);
+
 /* Damage index (Eq. 12 as Eq. 49/65): d = 1 - chi_B lambda cnt / beta with
  * cnt the number of intact partners within the horizon including the node
  * itself (convolution with the characteristic influence function omega_0,

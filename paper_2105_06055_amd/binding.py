@@ -69,7 +69,7 @@ SOLVE_MIXED, SOLVE_PRECOND = 1, 2
 
 
 EXPORTS = ["pd_plan_create", "pd_plan_destroy", "pd_plan_query", "pd_force", "pd_force_adjoint",
-           "pd_verlet_step", "pd_verlet_adjoint", "pd_static_solve", "pd_damage_index",
+           "pd_verlet_step", "pd_verlet_adjoint", "pd_static_solve", "pd_static_solve_noalloc", "pd_damage_index",
            "pd_status_str", "pd_test_conv", "pd_test_set_lastaxis"]
 
 _lib = None
@@ -97,6 +97,8 @@ def lib():
     L.pd_verlet_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, vp]
     L.pd_static_solve.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int, C.c_int,
                                   C.POINTER(SolveInfo), vp]
+    L.pd_static_solve_noalloc.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int, C.c_int,
+                                          C.POINTER(SolveInfo), vp]
     L.pd_damage_index.argtypes = [vp, vp, vp, vp]
     L.pd_status_str.argtypes = [C.c_int]
     L.pd_status_str.restype = C.c_char_p
@@ -253,16 +255,26 @@ class Plan:
                                        _ptr(self._vec(b_bar, "b_bar")), float(dt), _stream()), "pd_verlet_adjoint")
 
     def static_solve(self, b, w=None, u0=None, rtol=1e-10, maxit=100000, mixed=False, precond=False,
-                     check=True):
+                     check=True, noalloc=False, out=None):
+        """pd_static_solve (noalloc=True: pd_static_solve_noalloc; ``out``, if
+        given, is the FP64 tensor that receives the solution, initial guess
+        taken from u0 or zero)."""
         b = self._vec(b, "b", torch.float64)
         w = self._vec(w, "w", torch.float64)
-        u = torch.zeros_like(b) if u0 is None else self._vec(u0, "u0", torch.float64).clone()
+        if out is not None:
+            u = self._vec(out, "out", torch.float64)
+            if u0 is None:
+                u.zero_()
+            else:
+                u.copy_(self._vec(u0, "u0", torch.float64))
+        else:
+            u = torch.zeros_like(b) if u0 is None else self._vec(u0, "u0", torch.float64).clone()
         inf = SolveInfo()
         opts = (SOLVE_MIXED if mixed else 0) | (SOLVE_PRECOND if precond else 0)
-        s = lib().pd_static_solve(self._h, _ptr(b), _ptr(w), _ptr(u), float(rtol), int(maxit),
-                                  opts, C.byref(inf), _stream())
+        fn = lib().pd_static_solve_noalloc if noalloc else lib().pd_static_solve
+        s = fn(self._h, _ptr(b), _ptr(w), _ptr(u), float(rtol), int(maxit), opts, C.byref(inf), _stream())
         if check:
-            _check(s, "pd_static_solve")
+            _check(s, "pd_static_solve_noalloc" if noalloc else "pd_static_solve")
         info = {f: getattr(inf, f) for f, _ in SolveInfo._fields_}
         info["status"] = s
         return u, info

@@ -16,6 +16,39 @@ pd_status check(hipError_t e) {
 
 using namespace pdi;
 
+// ------------------------------------------------ allocation-free solve
+// The vectors of pd_static_solve_noalloc live in one file-scope device
+// array.  Each GPU that runs the library holds its own copy until the
+// process ends; its address on the current device comes from
+// hipGetSymbolAddress (in host code `scratch` is only a host-side stand-in),
+// looked up once per device and kept.
+#include <mutex>
+
+static constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+pd_status scratch_on_current_device(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return PD_EDEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return PD_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* q = nullptr;
+        if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return PD_EDEVICE;
+        g_scratch_ptr[dev] = q;
+    }
+    *out = g_scratch_ptr[dev];
+    return PD_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 pd_status pd_plan_create(const pd_grid* grid, const pd_horizon* horizon, const pd_kernel* kernel, const pd_mask* mask,
@@ -88,6 +121,22 @@ pd_status pd_static_solve(pd_plan p, const void* b, const void* w, void* u_inout
     if (p->kern.model == PD_BB_NONLINEAR) return PD_EUNSUPPORTED;
     return static_solve_impl(p, (const double*)b, (const double*)w, (double*)u_inout, rtol, maxit, options, info,
                              S_(stream));
+}
+
+pd_status pd_static_solve_noalloc(pd_plan p, const void* b, const void* w, void* u_inout, double rtol, int maxit,
+                                  int options, pd_solve_info* info, void* stream) {
+    if (!p) return PD_EINVAL;
+    if (p->kern.model == PD_BB_NONLINEAR) return PD_EUNSUPPORTED;
+    if (p->prof || (p->sub32 && p->sub32->prof)) return PD_EINVAL;   // pass timing creates events
+    if (options & ~(PD_SOLVE_MIXED | PD_SOLVE_PRECOND)) return PD_EINVAL;
+    if (solve_workspace_bytes(p, options) > kScratchBytes) return PD_EINVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return PD_EDEVICE;
+    if (dev != p->device) return PD_EINVAL;
+    void* ws = nullptr;
+    PD_TRY(scratch_on_current_device(&ws));
+    return static_solve_impl(p, (const double*)b, (const double*)w, (double*)u_inout, rtol, maxit, options, info,
+                             S_(stream), ws, kScratchBytes);
 }
 
 pd_status pd_damage_index(pd_plan p, const uint8_t* lambda, void* d_out, void* stream) {
