@@ -74,6 +74,55 @@ class ProfileSession:
         return out
 
 
+def pass_roofline(passes, steps):
+    """Dominant pass (largest summed duration) of a profiled run: its
+    algorithmic bytes per launch over its average event-measured duration,
+    and the whole step's algorithmic bytes over the summed pass time."""
+    dom = max(passes, key=lambda p: p["total_ms"])
+    achieved = dom["bytes_per_launch"] / 1e9 / (dom["avg_ms"] / 1e3)
+    step_bytes = sum(p["bytes_per_launch"] * p["launches"] for p in passes) / steps
+    step_ms = sum(p["total_ms"] for p in passes) / steps
+    return {"bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "kernel_avg_ms": dom["avg_ms"], "kernel_bytes": dom["bytes_per_launch"],
+            "step_alg_bytes": step_bytes, "step_kernel_ms": step_ms,
+            "step_alg_GBps": step_bytes / 1e9 / (step_ms / 1e3)}
+
+
+def run_m_crossover(nb, nfft, reps, warmup, ms=(2, 3, 4, 6)):
+    """pd_force (FP32 LPS, the voided block) at horizons of m = delta/dx
+    spacings, on each path the plan offers: the default (the direct (y, z)
+    correlation for m <= 3, else the y transform), the y transform with the
+    direct z line correlation (transform form beyond 4 spacings) and
+    transforms along all three axes."""
+    import torch
+
+    from paper_2105_06055_amd import binding, workloads
+    rows = []
+    for m in ms:
+        w = workloads.block_voids_dynamics(nb=nb, nfft=nfft, m=m)
+        plan = binding.Plan.from_workload(w, dtype=torch.float32)
+        u = torch.tensor(np.random.default_rng(7).normal(0.0, 1e-6, size=(3,) + w.body), dtype=torch.float32,
+                         device="cuda")
+        L = torch.empty_like(u)
+        row = {"m": m, "bonds": plan.info["stencil_size"]}
+        for mode in ("auto", "yfft", "fft"):
+            plan.set_lastaxis(mode)
+            for _ in range(max(1, warmup)):
+                plan.force(u, out=L)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                plan.force(u, out=L)
+            torch.cuda.synchronize()
+            row[f"{mode}_force_ms"] = (time.perf_counter() - t0) / reps * 1e3
+        plan.close()
+        del u, L
+        torch.cuda.empty_cache()
+        rows.append(row)
+        log(f"[bench] m-crossover {row}")
+    return rows
+
+
 def kernel_source_hash():
     """Hash of the HIP sources: HBM counter results taken for other sources
     are not reported."""
@@ -104,31 +153,36 @@ def measured_traffic(pass_name):
 
 
 def run_dynamics(wl, dtype, steps, warmup, with_profile, lastaxis="auto"):
-    """Warm up, then time exactly `steps` Verlet steps between two device
-    synchronisations; with_profile records HIP events around every launch
-    of those same steps (on the launch stream) for the per-pass timings."""
+    """Warm up, then time exactly `steps` Verlet steps (one library call)
+    between two device synchronisations, with no instrumentation; then, if
+    with_profile, run `steps` more steps with a HIP event pair recorded
+    around every launch (on the launch stream) for the per-pass timings.
+    Plan creation is timed on its own."""
     import torch
 
     from paper_2105_06055_amd import binding
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     plan = binding.Plan.from_workload(wl, dtype=dtype)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
     if lastaxis != "auto":
         plan.set_lastaxis(lastaxis)
     dev = lambda a: torch.tensor(a, dtype=dtype, device="cuda").contiguous()
     st = {"u": dev(wl.u0), "v": dev(wl.v0), "F": torch.zeros((wl.dim,) + wl.body, dtype=dtype, device="cuda"),
           "step": 0}
     dt = wl.dt
-    for _ in range(max(1, warmup)):
-        plan.verlet(st, dt, 1)
-    prof = None
+    plan.verlet(st, dt, max(1, warmup))
     torch.cuda.synchronize()
-    if with_profile:
-        prof = ProfileSession(plan)
     t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.verlet(st, dt, 1)
+    plan.verlet(st, dt, steps)
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t0) / steps
+    prof = None
     if with_profile:
+        prof = ProfileSession(plan)
+        plan.verlet(st, dt, steps)
+        torch.cuda.synchronize()
         prof = prof.read()
     # pd_force alone
     L = torch.empty_like(st["u"])
@@ -146,36 +200,53 @@ def run_dynamics(wl, dtype, steps, warmup, with_profile, lastaxis="auto"):
     del st, L
     torch.cuda.empty_cache()
     return {"s_per_step": t_step, "s_per_force": t_force, "passes": prof, "finite": finite,
-            "workspace_GB": info["workspace_bytes"] / 1e9, "lds_per_block": info["lds_per_block"]}
+            "workspace_GB": info["workspace_bytes"] / 1e9, "lds_per_block": info["lds_per_block"],
+            "plan_create_s": t_plan}
 
 
 def run_fracture(steps, warmup):
     """The notched glass plate (1000 x 400 nodes, delta = 4 dx, 512 x 1024
-    grid, +-12 MPa edge tractions) in FP32 with the pointwise energy damage:
-    time `steps` Verlet steps issued as one library call, after `warmup`
-    steps.  Reports the time per step, node-steps/s and the failed nodes."""
+    grid, +-12 MPa edge tractions) with the pointwise energy damage, from
+    rest: `steps` Verlet steps (the configuration's 10,000) issued as one
+    library call, timed, in FP32 and again in FP64 (after `warmup` steps on a
+    scratch state).  Reports the time per step, node-steps/s, the failed
+    nodes and how far the FP32 integrity and damage maps are from FP64's."""
     import torch
 
     from paper_2105_06055_amd import binding, workloads
     w = workloads.notched_plate_fracture()
-    dtype = torch.float32
-    plan = binding.Plan.from_workload(w, dtype=dtype, weight="integrity")
-    dev = lambda a, t=dtype: torch.tensor(np.ascontiguousarray(a), dtype=t, device="cuda")
-    st = {"u": dev(w.u0), "v": dev(w.v0), "F": torch.zeros((2,) + w.body, dtype=dtype, device="cuda"),
-          "lam": dev(w.lam0, torch.uint8), "W": torch.zeros(w.body, dtype=dtype, device="cuda"), "step": 0}
-    b = dev(w.b)
-    plan.verlet(st, w.dt, warmup, b=b)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.verlet(st, w.dt, steps, b=b)
-    torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / steps
-    failed = int((torch.tensor(w.lam0, device="cuda").to(torch.int32) - st["lam"].to(torch.int32)).sum().item())
-    finite = bool(torch.isfinite(st["u"]).all().item())
-    plan.close()
-    return {"workload": "notched plate 1000x400 nodes, delta = 4 dx, 512x1024 grid, +-12 MPa, FP32, "
-                        "energy damage", "steps": steps, "warmup": warmup, "ms_per_step": t * 1e3,
-            "Gnode_steps_s": w.nodes / t / 1e9, "failed_nodes": failed, "finite": finite}
+    out = {"workload": "notched plate 1000x400 nodes, delta = 4 dx, 512x1024 grid, +-12 MPa, energy damage, "
+                       "from rest", "steps": steps}
+    maps = {}
+    for dn, dtype in (("fp32", torch.float32), ("fp64", torch.float64)):
+        plan = binding.Plan.from_workload(w, dtype=dtype, weight="integrity")
+        dev = lambda a, t=dtype: torch.tensor(np.ascontiguousarray(a), dtype=t, device="cuda")
+
+        def fresh():
+            return {"u": dev(w.u0), "v": dev(w.v0), "F": torch.zeros((2,) + w.body, dtype=dtype, device="cuda"),
+                    "lam": dev(w.lam0, torch.uint8), "W": torch.zeros(w.body, dtype=dtype, device="cuda"),
+                    "step": 0}
+        b = dev(w.b)
+        plan.verlet(fresh(), w.dt, warmup, b=b)
+        st = fresh()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.verlet(st, w.dt, steps, b=b)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        lam = st["lam"].cpu().numpy()
+        d = plan.damage_index(st["lam"]).cpu().numpy().astype(np.float64)
+        maps[dn] = (lam, d)
+        out[dn] = {"ms_per_step": t * 1e3, "Gnode_steps_s": w.nodes / t / 1e9,
+                   "failed_nodes": int((w.lam0.astype(int) - lam.astype(int)).sum()),
+                   "finite": bool(torch.isfinite(st["u"]).all().item())}
+        plan.close()
+    (l32, d32), (l64, d64) = maps["fp32"], maps["fp64"]
+    out["fp32_vs_fp64"] = {"integrity_nodes_differing": int((l32 != l64).sum()),
+                           "damage_nodes_differing": int((d32 != d64).sum()),
+                           "damage_max_abs_diff": float(np.abs(d32 - d64).max())}
+    out["ms_per_step"] = out["fp32"]["ms_per_step"]
+    return out
 
 
 def run_adjoint_plate(dtype_name):
@@ -385,12 +456,13 @@ def main():
     ap.add_argument("--no-mconv", action="store_true", help="skip the m-convergence table")
     ap.add_argument("--no-fracture", action="store_true", help="skip the fracture-plate step timing")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint plate timing")
-    ap.add_argument("--fracture-steps", type=int, default=1000)
+    ap.add_argument("--fracture-steps", type=int, default=10000)
     ap.add_argument("--no-fft-variant", action="store_true",
                     help="skip the step timing with FFTs along all three axes")
     ap.add_argument("--no-energy", action="store_true", help="skip the 1000-step energy-drift runs")
     ap.add_argument("--no-c2", action="store_true", help="skip the 128^3/256^3 force rates")
     ap.add_argument("--energy-steps", type=int, default=1000)
+    ap.add_argument("--no-mcross", action="store_true", help="skip the horizon (m) crossover of the force paths")
     ap.add_argument("--cg-size", type=int, default=128)
     ap.add_argument("--cg-fft", type=int, default=256)
     ap.add_argument("--copy-calib", action="store_true",
@@ -431,10 +503,14 @@ def main():
         r32f = run_dynamics(wl, torch.float32, args.steps, args.warmup, with_profile=True, lastaxis="fft")
         log(f"[bench] fp32 step, FFT on all three axes: {r32f['s_per_step'] * 1e3:.3f} ms")
     passes = r32["passes"]
-    dom = max(passes, key=lambda p: p["total_ms"])
-    achieved = dom["bytes_per_launch"] / 1e9 / (dom["avg_ms"] / 1e3)
-    step_bytes = sum(p["bytes_per_launch"] * p["launches"] for p in passes) / args.steps
-    step_kernel_ms = sum(p["total_ms"] for p in passes) / args.steps
+    roof = pass_roofline(passes, args.steps)
+    dom = {"name": roof["kernel"], "avg_ms": roof["kernel_avg_ms"], "bytes_per_launch": roof["kernel_bytes"]}
+    achieved = roof["achieved"]
+    step_bytes, step_kernel_ms = roof["step_alg_bytes"], roof["step_kernel_ms"]
+    mcross = None
+    if not args.no_mcross:
+        mcross = {"workload": f"FP32 LPS pd_force, {args.size}^3 voided block on {args.fft}^3, delta = m dx",
+                  "rows": run_m_crossover(args.size, args.fft, args.steps, args.warmup)}
     c2 = None
     if not args.no_c2:
         w2 = workloads.cube_void_static()
@@ -526,6 +602,7 @@ def main():
                      "step_alg_bytes": step_bytes, "step_kernel_ms": step_kernel_ms,
                      "step_alg_GBps": step_bytes / 1e9 / (step_kernel_ms / 1e3),
                      "workspace_GB": r32["workspace_GB"], "lds_per_block": r32["lds_per_block"],
+                     "plan_create_s": r32["plan_create_s"],
                      "passes": passes},
             "fp64": None if r64 is None else {
                 "step_Gnode_s": nodes / r64["s_per_step"] / 1e9, "ms_per_step": r64["s_per_step"] * 1e3,
@@ -538,7 +615,9 @@ def main():
             "fp32_fft_all_axes": None if r32f is None else {
                 "step_Gnode_s": nodes / r32f["s_per_step"] / 1e9, "ms_per_step": r32f["s_per_step"] * 1e3,
                 "force_Gnode_s": nodes / r32f["s_per_force"] / 1e9, "force_ms": r32f["s_per_force"] * 1e3,
-                "finite": r32f["finite"], "passes": r32f["passes"]},
+                "finite": r32f["finite"], "roofline": pass_roofline(r32f["passes"], args.steps),
+                "passes": r32f["passes"]},
+            "m_crossover": mcross,
             "cg_time_to_1e-10": cg,
             "c2_force": c2,
             "nonlinear_bb_plate_force": nbb,

@@ -287,3 +287,25 @@ def test_influence_one(orc, dtype, model, body, fft, m):
         Lo = orc.bb_force(g, alpha, chi.astype(float), u)
     _check(L, Lo, u, plan, 2700.0, dtype, f"omega=1 {model} {body}")
     plan.close()
+
+
+# Horizons beyond the (y, z) pass's reach (m = 4, 6 spacings): every path
+# the plan offers for them (the y transform with the direct z line
+# correlation or, beyond 4 spacings, the transform form; transforms along all
+# axes), LPS, against the oracle.
+@pytest.mark.parametrize("dtype", DT)
+@pytest.mark.parametrize("m", [4, 6])
+def test_lps3d_long_horizons_all_paths(orc, dtype, m):
+    from paper_2105_06055_amd import binding
+    dx, body = 1e-3, (20, 21, 23)
+    chi = wl.random_mask(body, 63)
+    u = wl.random_field((3,) + body, 64, 1e-6)
+    plan = binding.Plan((32, 32, 32), body, dx, m * dx, model="lps", E=70e9, nu=0.3, rho=2700.0, chiB=chi,
+                        dtype=dtype)
+    g = orc.geom(body, dx, m * dx)
+    Lo, _ = orc.lps_force(g, 70e9, 0.3, chi.astype(float), u)
+    for mode in ("auto", "yfft", "fft", "fft_generic"):
+        plan.set_lastaxis(mode)
+        L = plan.force(_dev(u, dtype)).cpu().numpy()
+        _check(L, Lo, u, plan, 2700.0, dtype, f"LPS m={m} {mode}")
+    plan.close()
