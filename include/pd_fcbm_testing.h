@@ -45,6 +45,19 @@ pd_status pd_test_conv(pd_plan plan, const void* x, const int* shift, int parity
 enum { PD_LASTAXIS_AUTO = 0, PD_LASTAXIS_FFT = 1, PD_LASTAXIS_FFT_GENERIC = 2, PD_LASTAXIS_YFFT = 3 };
 pd_status pd_test_set_lastaxis(pd_plan plan, int mode);
 
+/* How the strain energy density W of the weighted bond-based solid is
+ * evaluated (pd_force's W_out and the energy failure rule of
+ * pd_verlet_step), for A/B tests:
+ *   PD_ENERGY_DIRECT       direct bond sums (Eq. 42 with the weights of
+ *                          Eq. 46), the default
+ *   PD_ENERGY_CONVOLUTION  the convolution form (Eq. 64/102) in the force's
+ *                          chain; its terms of order (chi u)^2 cancel to
+ *                          (u' - u)^2, so in FP32 its error grows with the
+ *                          square of the displacement
+ * PD_EINVAL for a null plan or an unknown form. */
+enum { PD_ENERGY_DIRECT = 0, PD_ENERGY_CONVOLUTION = 1 };
+pd_status pd_test_set_energy_form(pd_plan plan, int form);
+
 #ifdef __cplusplus
 }
 #endif

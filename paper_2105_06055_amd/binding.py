@@ -70,7 +70,7 @@ SOLVE_MIXED, SOLVE_PRECOND = 1, 2
 
 EXPORTS = ["pd_plan_create", "pd_plan_destroy", "pd_plan_query", "pd_force", "pd_force_adjoint",
            "pd_verlet_step", "pd_verlet_adjoint", "pd_static_solve", "pd_static_solve_noalloc", "pd_damage_index",
-           "pd_status_str", "pd_test_conv", "pd_test_set_lastaxis"]
+           "pd_status_str", "pd_test_conv", "pd_test_set_lastaxis", "pd_test_set_energy_form"]
 
 _lib = None
 
@@ -104,6 +104,7 @@ def lib():
     L.pd_status_str.restype = C.c_char_p
     L.pd_test_conv.argtypes = [vp, vp, C.POINTER(C.c_int), C.c_int, vp, vp]
     L.pd_test_set_lastaxis.argtypes = [vp, C.c_int]
+    L.pd_test_set_energy_form.argtypes = [vp, C.c_int]
     for name in EXPORTS:
         if name not in ("pd_plan_destroy", "pd_status_str"):
             getattr(L, name).restype = C.c_int
@@ -301,6 +302,13 @@ class Plan:
         every axis, spectral multiply, specialised where it applies) or
         'fft_generic'."""
         _check(lib().pd_test_set_lastaxis(self._h, self.LASTAXIS[mode]), "pd_test_set_lastaxis")
+
+    ENERGY_FORMS = {"direct": 0, "convolution": 1}
+
+    def set_energy_form(self, form="direct"):
+        """How W is evaluated (A/B tests): 'direct' bond sums (default) or the
+        paper's 'convolution' form in the force chain."""
+        _check(lib().pd_test_set_energy_form(self._h, self.ENERGY_FORMS[form]), "pd_test_set_energy_form")
 
     def close(self):
         if getattr(self, "_h", None):

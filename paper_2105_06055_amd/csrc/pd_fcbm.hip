@@ -221,4 +221,10 @@ pd_status pd_test_set_lastaxis(pd_plan p, int mode) {
     return PD_OK;
 }
 
+pd_status pd_test_set_energy_form(pd_plan p, int form) {
+    if (!p || form < PD_ENERGY_DIRECT || form > PD_ENERGY_CONVOLUTION) return PD_EINVAL;
+    p->energy_form = form;
+    return PD_OK;
+}
+
 }  // extern "C"

@@ -793,6 +793,23 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
         p->pre_s0 = p->pre_k0[0] > 0 ? p->pre_k0[0] : 1.0;
     }
 
+    if (D == 2 && p->kern.model == PD_BB_LINEAR) {
+        // per-bond constants of the direct strain-energy sum (Eq. 42 with the
+        // bond weights of Eq. 46): xi and alpha omega / |xi|^2 dV
+        std::vector<T> et((size_t)ns * 4, T(0));
+        int emt = 0;
+        for (int q = 0; q < ns; ++q) {
+            const Bond& bd = S[q];
+            et[4 * (size_t)q + 0] = T(bd.xi[0]);
+            et[4 * (size_t)q + 1] = T(bd.xi[1]);
+            et[4 * (size_t)q + 2] = T(p->alpha * om(bd.r) / (bd.r * bd.r) * p->dV);
+            emt = std::max(emt, std::max(std::abs(bd.o[0]), std::abs(bd.o[1])));
+        }
+        p->emt = emt;
+        HIP_TRY(hipMalloc(&p->etab, sizeof(T) * et.size()));
+        HIP_TRY(hipMemcpy(p->etab, et.data(), sizeof(T) * et.size(), hipMemcpyHostToDevice));
+        p->bytes += sizeof(T) * et.size();
+    }
     HIP_TRY(hipMalloc(&p->offs_dev, sizeof(int) * offs.size()));
     HIP_TRY(hipMalloc(&p->kval_dev, sizeof(double) * kv.size()));
     uint8_t* par_dev = nullptr;
@@ -884,7 +901,7 @@ inline void plan_free(pd_plan p) {
     if (!p) return;
     if (p->stream0) (void)hipStreamSynchronize(p->stream0);
     void* bufs[] = {p->tw, p->tw64, p->taps, p->taps_d, p->taps_yz, p->stat, p->stat_int, p->chiB, p->chiO, p->SA, p->SB, p->theta,
-                    p->vtmp, p->vtmp2, p->partials, p->red, p->offs_dev, p->kval_dev};
+                    p->vtmp, p->vtmp2, p->partials, p->red, p->offs_dev, p->kval_dev, p->etab};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->red_host) (void)hipHostFree(p->red_host);
@@ -1089,6 +1106,84 @@ inline pd_status plan_create_impl(const pd_grid* grid, const pd_horizon* hz, con
     return PD_OK;
 }
 
+// ------------------------------------------------------- strain energy
+// Strain energy density of the weighted linearized bond-based solid by
+// direct bond sums (Eq. 42 with the bond weights of Eq. 46/100, as Eq. 47
+// defines it before its convolution form, Eq. 64/102):
+//   W(x) = 1/2 phi(x) sum_o phi(x + o) alpha omega (xi . eta)^2 / |xi|^2 dV,
+// eta = u(x + o) - u(x), phi = chi_B lambda or chi_B s, zero beyond the body
+// box.  The convolution form expands (xi . eta)^2 into terms of order
+// (chi u)^2 that cancel down to (u' - u)^2: in FP32, once displacements reach
+// a grid spacing (a split plate), the cancellation error exceeds W_c.  The
+// direct sum forms eta first.  A block takes a tile of EW_TX x EW_TY nodes;
+// u and phi of the tile and a halo of M nodes go through LDS; each thread
+// sums the bonds of one node in stencil order (bond constants are
+// block-uniform: scalar loads).
+constexpr int EW_TX = 64, EW_TY = 4;
+template <class T, int WK>
+__global__ void __launch_bounds__(EW_TX * EW_TY)
+k_energy_bb2d(int b1, int b2, int ns, int M, const int* __restrict__ offs, const T* __restrict__ et,
+              const T* __restrict__ u, const uint8_t* __restrict__ chiB, const uint8_t* __restrict__ lam,
+              const T* __restrict__ s, T* __restrict__ W) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* su0 = reinterpret_cast<T*>(smem_raw);
+    const int PX = EW_TX + 2 * M, PY = EW_TY + 2 * M;
+    T* su1 = su0 + PX * PY;
+    T* sph = su1 + PX * PY;
+    const long nb = (long)b1 * b2;
+    const int x0 = blockIdx.x * EW_TX, y0 = blockIdx.y * EW_TY;
+    for (int q = threadIdx.x; q < PX * PY; q += blockDim.x) {
+        const int gx = x0 - M + q % PX, gy = y0 - M + q / PX;
+        const bool in = gx >= 0 && gx < b1 && gy >= 0 && gy < b2;
+        const long k = in ? (long)gy * b1 + gx : 0;
+        T ph = (in && (chiB[k] & 1)) ? T(1) : T(0);
+        if constexpr (WK == WK_LAMBDA) ph = (in && lam[k]) ? ph : T(0);
+        if constexpr (WK == WK_SCALE) ph *= in ? s[k] : T(0);
+        su0[q] = in ? u[k] : T(0);
+        su1[q] = in ? u[nb + k] : T(0);
+        sph[q] = ph;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % EW_TX, ty = threadIdx.x / EW_TX;
+    const int gx = x0 + tx, gy = y0 + ty;
+    if (gx >= b1 || gy >= b2) return;
+    const int c = (ty + M) * PX + tx + M;
+    const T u0 = su0[c], u1 = su1[c], pc = sph[c];
+    T acc = T(0);
+    for (int q = 0; q < ns; ++q) {
+        const int n = c + offs[3 * q + 1] * PX + offs[3 * q];
+        const T e = et[4 * q] * (su0[n] - u0) + et[4 * q + 1] * (su1[n] - u1);
+        acc += et[4 * q + 2] * e * e * sph[n];
+    }
+    W[(long)gy * b1 + gx] = T(0.5) * pc * acc;
+}
+
+template <class T>
+pd_status launch_energy(pd_plan p, const T* u, const uint8_t* lam, const T* s, T* W, hipStream_t st) {
+    if (p->dim != 2 || !p->etab || !W) return PD_EUNSUPPORTED;
+    const Geo& g = p->geo;
+    const int M = p->emt;
+    const size_t lds = (size_t)3 * (EW_TX + 2 * M) * (EW_TY + 2 * M) * sizeof(T);
+    if (lds > (size_t)p->max_lds) return PD_EUNSUPPORTED;
+    dim3 grid((g.b1 + EW_TX - 1) / EW_TX, (g.b2 + EW_TY - 1) / EW_TY), block(EW_TX * EW_TY);
+    ProfScope ps(p, st);
+    auto go = [&](auto kern) {
+        allow_lds(kern, lds);
+        hipLaunchKernelGGL(kern, grid, block, lds, st, g.b1, g.b2, p->ns, M, p->offs_dev,
+                           reinterpret_cast<const T*>(p->etab), u, p->chiB, lam, s, W);
+    };
+    if (p->kern.weight == PD_WEIGHT_INTEGRITY) go(k_energy_bb2d<T, WK_LAMBDA>);
+    else if (p->kern.weight == PD_WEIGHT_SCALE) go(k_energy_bb2d<T, WK_SCALE>);
+    else go(k_energy_bb2d<T, WK_NONE>);
+    if (p->prof) {
+        const double t = sizeof(T);
+        double per = 2 * t + 1 + t + (p->kern.weight == PD_WEIGHT_INTEGRITY ? 1.0 : 0.0) +
+                     (p->kern.weight == PD_WEIGHT_SCALE ? t : 0.0);
+        ps.done("energy_direct", per * (double)g.nb);
+    }
+    return pdh::check(hipGetLastError());
+}
+
 // ------------------------------------------------------------------ force
 // The two LPS chains: the dilatation (generator gA, epilogue fA writing
 // theta) and the force (multiplier mB, epilogue fB).  With the (y, z) pass
@@ -1179,7 +1274,8 @@ pd_status force_impl(pd_plan p, const T* u, const void* weight, T* L, T* W, hipS
             constexpr int WK = decltype(WKc)::value;
             const uint8_t* lam = (WK == WK_LAMBDA) ? reinterpret_cast<const uint8_t*>(weight) : nullptr;
             const T* s = (WK == WK_SCALE) ? reinterpret_cast<const T*>(weight) : nullptr;
-            if (W) {
+            if (W && p->energy_form == 1) {
+                // the convolution form of W (Eq. 102) in the same chain
                 GenU<T, DD, WK, true, true, false> gg{};
                 gg.c = ctx<T>(p);
                 gg.u = const_cast<T*>(u);
@@ -1198,7 +1294,8 @@ pd_status force_impl(pd_plan p, const T* u, const void* weight, T* L, T* W, hipS
                 FinBB<T, DD, WK, true, false, false, false> ff{};
                 ff.c = ctx<T>(p);
                 ff.u = u; ff.lam = lam; ff.s = s; ff.L = L;
-                return run_chain<T>(p, gg, MulBB<T, DD, true, false>{}, ff, st);
+                PD_TRY(run_chain<T>(p, gg, MulBB<T, DD, true, false>{}, ff, st));
+                return W ? launch_energy<T>(p, u, lam, s, W, st) : PD_OK;
             }
         };
         if (wk == PD_WEIGHT_INTEGRITY) return weighted(std::integral_constant<int, WK_LAMBDA>{});
@@ -1484,7 +1581,7 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, doubl
             gg.c = ctx<T>(p);
             gg.u = u; gg.v = v; gg.F = F; gg.w = w; gg.dt = dt; gg.c2 = c2;
             gg.lam_in = S->lambda; gg.lam_out = S->lambda; gg.s = reinterpret_cast<const T*>(S->s);
-            gg.W = reinterpret_cast<const T*>(S->W); gg.Wc = T(p->Wc); gg.fail = (E && p->Wc > 0) ? 1 : 0;
+            gg.W = reinterpret_cast<const T*>(S->W); gg.Wc = T(p->Wc); gg.fail = (S->W && p->Wc > 0) ? 1 : 0;
             FinBB<T, DD, WK, true, E, true, ENRED> ff{};
             ff.c = ctx<T>(p);
             ff.u = u; ff.lam = S->lambda; ff.s = reinterpret_cast<const T*>(S->s); ff.Wout = reinterpret_cast<T*>(S->W);
@@ -1492,8 +1589,13 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, doubl
             return run_chain<T>(p, gg, MulBB<T, DD, true, E>{}, ff, st);
         };
         if (wk == PD_WEIGHT_INTEGRITY) {
-            if (S->W) return weighted(std::integral_constant<int, WK_LAMBDA>{}, std::true_type{});
-            return weighted(std::integral_constant<int, WK_LAMBDA>{}, std::false_type{});
+            if (S->W && p->energy_form == 1)
+                return weighted(std::integral_constant<int, WK_LAMBDA>{}, std::true_type{});
+            PD_TRY(weighted(std::integral_constant<int, WK_LAMBDA>{}, std::false_type{}));
+            // W of the new state (u, lambda after this step's update) decides
+            // the next step's failures
+            if (S->W) return launch_energy<T>(p, u, S->lambda, nullptr, reinterpret_cast<T*>(S->W), st);
+            return PD_OK;
         }
         return weighted(std::integral_constant<int, WK_SCALE>{}, std::false_type{});
         }

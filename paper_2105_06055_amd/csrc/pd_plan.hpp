@@ -73,6 +73,9 @@ struct pd_plan_s {
     double* red_host_dev;        // device address of red_host (null if not mapped)
     hipEvent_t lag_ev[2];        // completion events of the solver's lagged residual reads
     int* offs_dev;               // stencil offsets [ns][3]
+    void* etab;                  // T [ns][4]: xi_x, xi_y, alpha omega / |xi|^2 dV, 0 (2D bond-based energy)
+    int emt;                     // largest |o_x|, |o_y| of the stencil (halo of the energy kernel)
+    int energy_form;             // 0: W by direct bond sums, 1: by the convolution form (test mode)
     double* kval_dev;            // kernel values [ns][ncs]
     size_t bytes;
     std::vector<ProfRec>* prof;  // non-null while pass timing is enabled

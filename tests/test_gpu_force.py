@@ -309,3 +309,39 @@ def test_lps3d_long_horizons_all_paths(orc, dtype, m):
         L = plan.force(_dev(u, dtype)).cpu().numpy()
         _check(L, Lo, u, plan, 2700.0, dtype, f"LPS m={m} {mode}")
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", DT)
+def test_energy_density_large_displacement(orc, dtype):
+    """W with displacements of two grid spacings (a translated, stretched,
+    noisy plate with integrity weights): the direct bond sums match the
+    oracle to rounding in both precisions; the convolution form (Eq. 102),
+    whose terms of order (chi u)^2 cancel down to (u' - u)^2, loses about
+    (|u| / |u' - u|)^2 of its accuracy and is kept as a test mode only."""
+    from paper_2105_06055_amd import binding
+    body, fft, dx, m = (40, 50), (64, 64), 1e-3, 3
+    w = wl.Workload(name="t", dim=2, body=body, fft=fft, dx=dx, delta=m * dx, model="bb", E=72e9, nu=1 / 3,
+                    G0=3.8)
+    w.chiB = wl.random_mask(body, 65)
+    w.chiO = np.stack([w.chiB] * 2)
+    lam = (np.random.default_rng(66).random(body) > 0.1).astype(np.uint8)
+    w.lam0 = lam
+    y, x = np.meshgrid((np.arange(body[0]) + 0.5) * dx, (np.arange(body[1]) + 0.5) * dx, indexing="ij")
+    u = np.stack([2e-3 + 1e-3 * x, -1.5e-3 + 5e-4 * y]) + wl.random_field((2,) + body, 67, 1e-7)
+    # the oracle sees the values the GPU holds
+    u = u.astype(np.float32 if dtype == torch.float32 else np.float64).astype(np.float64)
+    plan = _plan(w, dtype, weight="integrity")
+    g = orc.geom(body, dx, w.delta)
+    Wo = orc.bb_energy(g, orc.bb_alpha(2, w.E, w.delta), (w.chiB * lam).astype(float), u)
+    res = {}
+    for form in ("direct", "convolution"):
+        plan.set_energy_form(form)
+        _, W = plan.force(_dev(u, dtype), weight=_dev(lam, torch.uint8), energy=True)
+        res[form] = parity.rel_max(W.cpu().numpy(), Wo)
+    print(f"W with |u| ~ 2 dx, {dtype}: rel_max direct {res['direct']:.2e}, convolution {res['convolution']:.2e}")
+    if dtype == torch.float64:
+        assert res["direct"] <= 1e-12 and res["convolution"] <= 1e-5, res
+    else:
+        assert res["direct"] <= 1e-5, res
+        assert res["convolution"] > 100 * res["direct"], res
+    plan.close()
