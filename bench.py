@@ -475,6 +475,7 @@ def main():
     ap.add_argument("--no-c2", action="store_true", help="skip the 128^3/256^3 force rates")
     ap.add_argument("--energy-steps", type=int, default=1000)
     ap.add_argument("--no-mcross", action="store_true", help="skip the horizon (m) crossover of the force paths")
+    ap.add_argument("--no-minpad", action="store_true", help="skip the minimum-padding (mixed-radix) x grids")
     ap.add_argument("--cg-size", type=int, default=128)
     ap.add_argument("--cg-fft", type=int, default=256)
     ap.add_argument("--copy-calib", action="store_true",
@@ -519,6 +520,24 @@ def main():
     dom = {"name": roof["kernel"], "avg_ms": roof["kernel_avg_ms"], "bytes_per_launch": roof["kernel_bytes"]}
     achieved = roof["achieved"]
     step_bytes, step_kernel_ms = roof["step_alg_bytes"], roof["step_kernel_ms"]
+    minpad = None
+    if not args.no_minpad:
+        # minimum-padding x grids (one horizon is all Sec. 4.2.2 needs): the
+        # same step with n1 = 384 = 2*3*2^6, 320 = 2*5*2^5, 288 = 2*9*2^4
+        import dataclasses
+        rows = [{"n1": args.fft, "ms_per_step": r32["s_per_step"] * 1e3,
+                 "Gnode_s": nodes / r32["s_per_step"] / 1e9, "force_ms": r32["s_per_force"] * 1e3,
+                 "step_alg_bytes": roof["step_alg_bytes"], "roofline": roof}]
+        for n1 in (384, 320, 288):
+            wm = dataclasses.replace(wl, fft=(args.fft, args.fft, n1))
+            rm = run_dynamics(wm, torch.float32, args.steps, args.warmup, with_profile=True)
+            rf = pass_roofline(rm["passes"], args.steps)
+            rows.append({"n1": n1, "ms_per_step": rm["s_per_step"] * 1e3, "Gnode_s": nodes / rm["s_per_step"] / 1e9,
+                         "force_ms": rm["s_per_force"] * 1e3, "step_alg_bytes": rf["step_alg_bytes"],
+                         "finite": rm["finite"], "roofline": rf, "passes": rm["passes"]})
+            log(f"[bench] min-padding n1={n1}: step {rm['s_per_step'] * 1e3:.3f} ms")
+        minpad = {"workload": f"FP32 LPS EC Verlet step, {args.size}^3 voided block, x grid n1 (y, z grids "
+                              f"{args.fft}; the (y, z) pass works on the body planes only)", "rows": rows}
     mcross = None
     if not args.no_mcross:
         mcross = {"workload": f"FP32 LPS pd_force, {args.size}^3 voided block on {args.fft}^3, delta = m dx",
@@ -630,6 +649,7 @@ def main():
                 "finite": r32f["finite"], "roofline": pass_roofline(r32f["passes"], args.steps),
                 "passes": r32f["passes"]},
             "m_crossover": mcross,
+            "min_padding_x": minpad,
             "cg_time_to_1e-10": cg,
             "c2_force": c2,
             "nonlinear_bb_plate_force": nbb,

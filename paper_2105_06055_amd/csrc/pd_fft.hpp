@@ -148,9 +148,9 @@ __device__ __forceinline__ void fft_first(const cx<T> (&v)[8], int j, int lgT, l
 // and adds for the index math.
 template <int SIGN, class T>
 __device__ __forceinline__ void fft_r8(cx<T> (&v)[8], int j, int lgN, int lgNs, lds_ptr<const cx<T>> tw,
-                                       int lgtws, lds_ptr<cx<T>> lds, bool last) {
+                                       int lgtws, lds_ptr<cx<T>> lds, bool last, int twmul) {
     const int k = j & ((1 << lgNs) - 1);
-    const int e1 = k << (lgN - lgNs - 3 + lgtws);
+    const int e1 = (k << (lgN - lgNs - 3 + lgtws)) * twmul;
     int e = e1;
 #pragma unroll
     for (int r = 1; r < 8; ++r) {
@@ -168,11 +168,12 @@ __device__ __forceinline__ void fft_r8(cx<T> (&v)[8], int j, int lgN, int lgNs, 
 // Full line transform of N = 2^lgN points (8 <= N <= 2048).  Every thread of
 // the block must call this (it contains block-wide barriers), with the same
 // N.  lds points at this thread's line (fft_lds_len(N) complex slots).  The
-// twiddle exp(-2 pi i e/N) is tw[e << lgtws] (lgtws > 0 reuses the table of
-// a multiple length; the table normally sits in LDS, see stage_twiddles).
+// twiddle exp(-2 pi i e/N) is tw[(e << lgtws) * twmul] (a table of a multiple
+// length: 2^lgtws * twmul times N; the table normally sits in LDS, see
+// stage_twiddles).
 template <int SIGN, class T>
 __device__ __forceinline__ void fft_line(cx<T> (&v)[8], int j, int lgN, const cx<T>* __restrict__ tw_g, int lgtws,
-                                         cx<T>* lds_g) {
+                                         cx<T>* lds_g, int twmul = 1) {
     lds_ptr<const cx<T>> tw = as_lds(tw_g);
     lds_ptr<cx<T>> lds = as_lds(lds_g);
     __syncthreads();  // the caller may still be reading this LDS region
@@ -192,7 +193,7 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[8], int j, int lgN, const cx
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = lds[fft_pad(j + (q << lgT))];
         __syncthreads();
-        fft_r8<SIGN>(v, j, lgN, lgNs, tw, lgtws, lds, st == nst - 1);
+        fft_r8<SIGN>(v, j, lgN, lgNs, tw, lgtws, lds, st == nst - 1, twmul);
         lgNs += 3;
     }
 }
@@ -202,6 +203,74 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[8], int j, int lgN, const cx
 template <class T>
 __device__ __forceinline__ void stage_twiddles(cx<T>* dst, const cx<T>* __restrict__ twb, int N) {
     for (int e = threadIdx.x; e < N; e += blockDim.x) dst[e] = twb[N + e];
+}
+// The same for a table that starts at src.
+template <class T>
+__device__ __forceinline__ void stage_table(cx<T>* dst, const cx<T>* __restrict__ src, int N) {
+    for (int e = threadIdx.x; e < N; e += blockDim.x) dst[e] = src[e];
+}
+
+// Mixed-radix line of Nc = R * M complex points (R = 3, 5 or 9; M = 2^lgM >=
+// 8): one radix-R step and R power-of-two transforms of M points
+// (Cooley-Tukey with n = n2 + M n1, k = k1 + R k2, n1, k1 < R; n2, k2 < M).
+// The line's Nc/8 threads form R groups of M/8: thread t = s (M/8) + j works
+// on sub-line s and holds the points j + (M/8) q, q < 8, of it.
+//   forward  y_s[n2] = sum_n1 x[n2 + M n1] W^{s (n2 + M n1)}  (W = e^{-2 pi i/Nc}),
+//            then the M-point transform of y_s: X[s + R k2], k2 = j + (M/8) q;
+//   inverse  the M-point inverse transform of X[s + R k2] over k2 gives
+//            z_s[n2], then x[n2 + M s] = sum_k1 z_k1[n2] W^{-k1 (n2 + M s)}.
+// Twiddles: W^e = tw[2e mod n1], tw the table of length n1 = 2 Nc in LDS;
+// the M-point transforms take W_M^e = W^{R e} from the same table.  lds
+// points at the line (fft_lds_len(Nc) complex slots); every thread of the
+// block calls these (block-wide barriers), the caller fences its own LDS
+// uses before and after.
+template <class T, class In>
+__device__ __forceinline__ void fft_mixed_fwd(cx<T> (&v)[8], int t, int R, int lgM, In in, const cx<T>* tw_g,
+                                              int n1, cx<T>* lds_g) {
+    const int M = 1 << lgM, Tq = M >> 3;
+    const int s = t >> (lgM - 3), j = t & (Tq - 1);
+    lds_ptr<const cx<T>> tw = as_lds(tw_g);
+    const int de = (2 * s * M) % n1;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int n2 = j + Tq * q;
+        int e = (2 * s * n2) % n1;
+        cx<T> acc = {T(0), T(0)};
+        for (int r = 0; r < R; ++r) {
+            acc = acc + cmul(in(n2 + M * r), tw[e]);
+            e += de;
+            if (e >= n1) e -= n1;
+        }
+        v[q] = acc;
+    }
+    fft_line<-1>(v, j, lgM, tw_g, 1, lds_g + s * fft_lds_len(M), R);
+}
+
+template <class T>
+__device__ __forceinline__ void fft_mixed_inv(cx<T> (&v)[8], int t, int R, int lgM, const cx<T>* tw_g, int n1,
+                                              cx<T>* lds_g) {
+    const int M = 1 << lgM, Tq = M >> 3;
+    const int s = t >> (lgM - 3), j = t & (Tq - 1);
+    fft_line<1>(v, j, lgM, tw_g, 1, lds_g + s * fft_lds_len(M), R);
+    lds_ptr<const cx<T>> tw = as_lds(tw_g);
+    lds_ptr<cx<T>> z = as_lds(lds_g);
+    __syncthreads();   // every sub-line transform is done with its LDS
+#pragma unroll
+    for (int q = 0; q < 8; ++q) z[s * M + j + Tq * q] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int n2 = j + Tq * q;
+        const int de = (2 * (n2 + M * s)) % n1;
+        int e = 0;
+        cx<T> acc = {T(0), T(0)};
+        for (int r = 0; r < R; ++r) {
+            acc = acc + cmul(z[r * M + n2], cconj(tw[e]));
+            e += de;
+            if (e >= n1) e -= n1;
+        }
+        v[q] = acc;
+    }
 }
 
 }  // namespace pdk

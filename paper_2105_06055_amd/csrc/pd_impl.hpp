@@ -42,7 +42,7 @@ constexpr double kPi = 3.14159265358979323846;
 template <class T>
 __global__ void k_taps(int dim, int n1, int n2, int h1, long NP, int ntap, int ns,
                        const int* __restrict__ offs, const double* __restrict__ kval, int kstride,
-                       int nct, const uint8_t* __restrict__ par, const double* __restrict__ tw64,
+                       int nct, const uint8_t* __restrict__ par, const double* __restrict__ tw64, int twn1,
                        double sc0, double sc1, T* __restrict__ taps) {
     long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= NP * ntap) return;
@@ -54,8 +54,8 @@ __global__ void k_taps(int dim, int n1, int n2, int h1, long NP, int ntap, int n
     const int last = dim - 1;
     double acc[12];
     for (int c = 0; c < nct; ++c) acc[c] = 0.0;
-    const double* twx = tw64 + 2 * n1;  // complex FP64 table of length n1 at [n1, 2n1)
-    const double* twy = tw64 + 2 * n2;
+    const double* twx = tw64 + 2 * twn1;  // complex FP64 table of length n1
+    const double* twy = tw64 + 2 * n2;    // of length n2 (a power of two) at [n2, 2 n2)
     for (int s = 0; s < ns; ++s) {
         const int ox = offs[3 * s], oy = offs[3 * s + 1], oz = offs[3 * s + 2];
         const int ol = (last == 1) ? oy : oz;
@@ -90,7 +90,7 @@ __global__ void k_taps(int dim, int n1, int n2, int h1, long NP, int ntap, int n
 template <class T>
 __global__ void k_taps_yz(int n1, int h1, int MT, int nu, int ns, const int* __restrict__ offs,
                           const double* __restrict__ kval, int kstride, int nct, const uint8_t* __restrict__ par,
-                          const double* __restrict__ tw64, double sc, int nx, int x0, double xs,
+                          const double* __restrict__ tw64, int twn1, double sc, int nx, int x0, double xs,
                           T* __restrict__ taps) {
     long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)h1 * nu) return;
@@ -101,7 +101,7 @@ __global__ void k_taps_yz(int n1, int h1, int MT, int nu, int ns, const int* __r
             if (a * a + b * b <= MT * MT && yz_tap(MT, a, b) == u) { ta = a; tb = b; break; }
     double acc[12];
     for (int c = 0; c < nct; ++c) acc[c] = 0.0;
-    const double* twx = tw64 + 2 * n1;
+    const double* twx = tw64 + 2 * twn1;
     for (int s = 0; s < ns; ++s) {
         if (offs[3 * s + 1] != ta || offs[3 * s + 2] != tb) continue;
         int ex = (int)(((long)kx * offs[3 * s]) % n1);
@@ -179,6 +179,15 @@ namespace pdi {
 // ------------------------------------------------------------------ helpers
 
 inline bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Radix R of an x length n1 = 2 R 2^p (R = 3, 5 or 9, 2^p >= 8); 1 for a
+// power of two, 0 for any other length.
+inline int x_radix(long n1) {
+    if (is_pow2(n1)) return 1;
+    for (int R : {3, 5, 9})
+        if (n1 % (2 * R) == 0 && is_pow2(n1 / (2 * R)) && n1 / (2 * R) >= 8) return R;
+    return 0;
+}
 
 template <class T>
 inline cx<T>* SAp(pd_plan p) { return reinterpret_cast<cx<T>*>(p->SA); }
@@ -298,6 +307,7 @@ pd_status launch_xfwd_lg(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
 }
 template <class T, class G>
 pd_status launch_xfwd(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
+    if (p->geo.rad != 1) return launch_xfwd_lg<T, G, -1>(p, gen, SA, st);
     if (p->geo.b1 <= p->geo.Nc) {
         if (p->geo.Nc == (1 << kFastLgX)) return launch_xfwd_lg<T, G, kFastLgX>(p, gen, SA, st);
         if (p->geo.Nc == (1 << kFastLgX2)) return launch_xfwd_lg<T, G, kFastLgX2>(p, gen, SA, st);
@@ -566,6 +576,7 @@ pd_status launch_xinv_lg(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t s
 }
 template <class T, class F>
 pd_status launch_xinv(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st, cx<T>* SAout = nullptr) {
+    if (p->geo.rad != 1) return launch_xinv_lg<T, F, -1>(p, fin, SA, st, SAout);
     if (p->geo.b1 <= p->geo.Nc) {
         if (p->geo.Nc == (1 << kFastLgX)) return launch_xinv_lg<T, F, kFastLgX>(p, fin, SA, st, SAout);
         if (p->geo.Nc == (1 << kFastLgX2)) return launch_xinv_lg<T, F, kFastLgX2>(p, fin, SA, st, SAout);
@@ -662,15 +673,24 @@ inline double bb_alpha(int dim, int influence, double E, double delta) {
     return 2.0 * lam / (A * I);
 }
 
+// Twiddle buffer: exp(-2 pi i e / N) for every power of two N <= P at complex
+// entries [N, 2N), P the largest power-of-two axis length, and, when the x
+// length n1 is not a power of two, the length-n1 table at [2P, 2P + n1)
+// (*twn1 receives the offset of the n1 table either way).
 template <class T>
-void twiddles_host(int nmax, std::vector<T>& out) {
-    out.assign((size_t)4 * nmax, T(0));
-    for (int N = 1; N <= nmax; N <<= 1)
+void twiddles_host(int P, int n1, std::vector<T>& out, int* twn1) {
+    const bool mixed = !is_pow2(n1);
+    *twn1 = mixed ? 2 * P : n1;
+    out.assign((size_t)2 * (2 * P + (mixed ? n1 : 0)), T(0));
+    auto put = [&](int N, size_t at) {
         for (int e = 0; e < N; ++e) {
             long double a = -2.0L * 3.141592653589793238462643383279502884L * (long double)e / (long double)N;
-            out[2 * (size_t)(N + e)] = (T)cosl(a);
-            out[2 * (size_t)(N + e) + 1] = (T)sinl(a);
+            out[2 * (at + e)] = (T)cosl(a);
+            out[2 * (at + e) + 1] = (T)sinl(a);
         }
+    };
+    for (int N = 1; N <= P; N <<= 1) put(N, (size_t)N);
+    if (mixed) put(n1, (size_t)2 * P);
 }
 
 // Largest eigenvalue of the periodic operator's symbol, sampled on a
@@ -827,11 +847,11 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
         long n = NP * p->ntap;
         const double inv = 1.0 / (double)p->nfft, nl = (double)(D == 2 ? g.n2 : g.n3);
         hipLaunchKernelGGL((k_taps<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, D, g.n1, g.n2, g.h1, NP,
-                           p->ntap, ns, p->offs_dev, p->kval_dev, ncs, nct, par_dev, p->tw64,
+                           p->ntap, ns, p->offs_dev, p->kval_dev, ncs, nct, par_dev, p->tw64, g.twn1,
                            inv, 2.0 * inv, reinterpret_cast<T*>(p->taps));
         HIP_TRY(hipGetLastError());
         hipLaunchKernelGGL((k_taps<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, D, g.n1, g.n2, g.h1, NP,
-                           p->ntap, ns, p->offs_dev, p->kval_dev, ncs, nct, par_dev, p->tw64,
+                           p->ntap, ns, p->offs_dev, p->kval_dev, ncs, nct, par_dev, p->tw64, g.twn1,
                            nl * inv, nl * inv, reinterpret_cast<T*>(p->taps_d));
         HIP_TRY(hipGetLastError());
     }
@@ -854,7 +874,7 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
             HIP_TRY(hipMalloc(&p->taps_yz, sizeof(T) * n * p->nct_yz));
             p->bytes += sizeof(T) * n * p->nct_yz;
             hipLaunchKernelGGL((k_taps_yz<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.n1, g.h1, mt,
-                               p->yz_nu, ns, p->offs_dev, p->kval_dev, ncs, nct, par_dev, p->tw64,
+                               p->yz_nu, ns, p->offs_dev, p->kval_dev, ncs, nct, par_dev, p->tw64, g.twn1,
                                1.0 / (double)g.n1, nx, 6, p->ka, reinterpret_cast<T*>(p->taps_yz));
             HIP_TRY(hipGetLastError());
         }
@@ -923,14 +943,17 @@ pd_status plan_alloc(pd_plan p, hipStream_t st, const uint8_t* chiB_h, const uin
     const Geo& g = p->geo;
     const int D = p->dim;
     // twiddles
-    int nmax = std::max(std::max(g.n1, g.n2), g.n3);
+    int P = 1;
+    while (P < std::max(std::max(g.n2, g.n3), is_pow2(g.n1) ? g.n1 : 1)) P <<= 1;
     {
         std::vector<T> tw;
-        twiddles_host<T>(nmax, tw);
+        int off = 0;
+        twiddles_host<T>(P, g.n1, tw, &off);
         HIP_TRY(hipMalloc(&p->tw, sizeof(T) * tw.size()));
         HIP_TRY(hipMemcpyAsync(p->tw, tw.data(), sizeof(T) * tw.size(), hipMemcpyHostToDevice, st));
         std::vector<double> tw64;
-        twiddles_host<double>(nmax, tw64);
+        twiddles_host<double>(P, g.n1, tw64, &off);
+        p->geo.twn1 = off;
         HIP_TRY(hipMalloc(&p->tw64, sizeof(double) * tw64.size()));
         HIP_TRY(hipMemcpyAsync(p->tw64, tw64.data(), sizeof(double) * tw64.size(), hipMemcpyHostToDevice, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -1033,7 +1056,10 @@ inline pd_status plan_create_impl(const pd_grid* grid, const pd_horizon* hz, con
         }
         if (!(grid->dx[d] > 0)) return PD_EINVAL;
         if (b < 1 || n < 1) return PD_EINVAL;
-        if (!is_pow2(n)) return PD_EUNSUPPORTED;
+        // x: a power of two, or 2 R 2^p with R = 3, 5, 9 and 2^p >= 8 (the
+        // complex half-length is transformed by one radix-R step and R
+        // power-of-two transforms); y and z: powers of two
+        if (!is_pow2(n) && !(d == 0 && x_radix(n) > 1)) return PD_EUNSUPPORTED;
         const long lo = 16, hi = (d == 0) ? 2048 : 1024;
         if (n < lo || n > hi) return PD_EUNSUPPORTED;
         const long m = (long)std::ceil(hz->delta / grid->dx[d] * (1.0 - 1e-12));
@@ -1064,6 +1090,12 @@ inline pd_status plan_create_impl(const pd_grid* grid, const pd_horizon* hz, con
     g.b1 = p->b[0]; g.b2 = p->b[1]; g.b3 = p->b[2];
     g.Nc = g.n1 / 2;
     g.h1 = g.Nc + 1;
+    g.rad = x_radix(g.n1);
+    {
+        int lg = 0;
+        while ((g.rad << (lg + 1)) <= g.Nc) ++lg;
+        g.lgM = lg;   // Nc = rad 2^lgM
+    }
     g.P2 = ((g.b2 + 15) / 16) * 16;
     g.nb = (long)g.b1 * g.b2 * g.b3;
     g.saf = (long)g.b3 * g.h1 * g.P2;
@@ -2099,7 +2131,7 @@ pd_status test_conv_impl(pd_plan p, const T* x, const int* sh, int parity, T* ou
         (void)hipMemcpyAsync(pd, par, 3, hipMemcpyHostToDevice, st);
         long nn = NP * ntap;
         hipLaunchKernelGGL((k_taps<T>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, D, g.n1, g.n2, g.h1, NP, ntap,
-                           ns, od, kd, 1, 1, pd, p->tw64, 1.0 / (double)p->nfft, 2.0 / (double)p->nfft, taps);
+                           ns, od, kd, 1, 1, pd, p->tw64, g.twn1, 1.0 / (double)p->nfft, 2.0 / (double)p->nfft, taps);
         s = pdh::check(hipGetLastError());
     }
     if (s == PD_OK) {

@@ -65,6 +65,8 @@ struct Geo {
     int n1, n2, n3;     // FFT grid
     int b1, b2, b3;     // body box
     int h1, Nc, P2;     // n1/2+1, n1/2, row pitch of SA (>= b2)
+    int rad, lgM;       // Nc = rad * 2^lgM: rad = 1 (power of two) or 3, 5, 9 (mixed radix)
+    int twn1;           // offset (complex entries) of the length-n1 table in the twiddle buffer
     long nb;            // body nodes
     long saf;           // field stride of SA: b3*h1*P2
     long sbf;           // b3*h1*n2 (spectral points of the body planes)
@@ -96,14 +98,21 @@ __device__ __forceinline__ void block_reduce_store(double (&red)[NR], double* ou
     }
 }
 
+// Line length of the x passes: LG > 0 fixes Nc = 2^LG at compile time, LG = 0
+// takes a power of two from g, LG < 0 the mixed-radix Nc = rad 2^lgM of g.
+template <int LG>
+__device__ __forceinline__ int x_len(const Geo& g) { return LG > 0 ? (1 << LG) : g.Nc; }
+template <int LG>
+__device__ __forceinline__ int x_lg(const Geo& g) { return LG > 0 ? LG : (LG == 0 ? 31 - __clz(g.Nc) : g.lgM); }
+
 // r2c along x of NF real fields held in the flat node mapping (thread tid
 // holds nodes tid + nthr r of the block's run, r < RN) and transposed store
 // into SA (field f at SA + f*saf).  The twiddles of length n1 must be staged
 // in LDS after the Lt row buffers; every LDS use is fenced here.
-template <class T, int NF, int RN>
+template <class T, int NF, int RN, int LG>
 __device__ __forceinline__ void r2c_store(const Geo& g, const T (&gv)[NF][RN], cx<T>* __restrict__ SA, cx<T>* lds,
-                                          int lgNc, int nthr, int nval) {
-    const int Nc = 1 << lgNc, Tc = Nc >> 3, Lt = nthr / Tc;
+                                          int nthr, int nval) {
+    const int Nc = x_len<LG>(g), lgNc = x_lg<LG>(g), Tc = Nc >> 3, Lt = nthr / Tc;
     const int tid = threadIdx.x, j = tid % Tc, l = tid / Tc;
     const int z = blockIdx.y;
     const int y0 = blockIdx.x * Lt;
@@ -126,24 +135,34 @@ __device__ __forceinline__ void r2c_store(const Geo& g, const T (&gv)[NF][RN], c
         }
         __syncthreads();
         cx<T> v[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int x0 = 2 * (j + Tc * q);
+        // packed pair (2n, 2n + 1) of the row's real samples
+        auto pair = [&](int n) -> cx<T> {
+            const int x0 = 2 * n;
             const T a = (rowok && x0 < g.b1) ? flat[l * g.b1 + x0] : T(0);
             const T b = (rowok && x0 + 1 < g.b1) ? flat[l * g.b1 + x0 + 1] : T(0);
-            v[q] = {a, b};
-        }
-        fft_line<-1>(v, j, lgNc, twn1, 1, row);
-        __syncthreads();
+            return cx<T>{a, b};
+        };
+        if constexpr (LG >= 0) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) rowv[j + Tc * q] = v[q];
+            for (int q = 0; q < 8; ++q) v[q] = pair(j + Tc * q);
+            fft_line<-1>(v, j, lgNc, twn1, 1, row);
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 8; ++q) rowv[j + Tc * q] = v[q];
+        } else {
+            fft_mixed_fwd<T>(v, j, g.rad, lgNc, pair, twn1, g.n1, row);
+            __syncthreads();
+            const int Tq = 1 << (lgNc - 3), s = j >> (lgNc - 3), jj = j & (Tq - 1);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) rowv[s + g.rad * (jj + Tq * q)] = v[q];
+        }
         __syncthreads();
         cx<T> X[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int k = j + Tc * q;
             cx<T> A = rowv[k];
-            cx<T> B = cconj(rowv[(Nc - k) & (Nc - 1)]);
+            cx<T> B = cconj(rowv[k ? Nc - k : 0]);
             cx<T> E = cscale(A + B, T(0.5));
             cx<T> Dm = A - B;
             cx<T> O = {T(0.5) * Dm.i, T(-0.5) * Dm.r};
@@ -180,7 +199,7 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int NF = G::NIN, NG = 4;
-    const int lgNc = LG > 0 ? LG : 31 - __clz(g.Nc), Nc = 1 << lgNc, Tc = Nc >> 3;
+    const int Nc = x_len<LG>(g), Tc = Nc >> 3;
     const int nthr = LG > 0 ? xblock_threads<T>() : (int)blockDim.x;
     const int Lt = nthr / Tc;
     const int tid = threadIdx.x;
@@ -231,8 +250,8 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
     if (nval == RN * nthr) run_gen(std::true_type{});
     else run_gen(std::false_type{});
     // twiddles of length n1 in LDS after the rows; W_Nc^e = W_n1^(2e)
-    stage_twiddles(lds + Lt * row_pitch(Nc), twb, g.n1);
-    r2c_store<T, NF, RN>(g, gv, SA, lds, lgNc, nthr, nval);
+    stage_table(lds + Lt * row_pitch(Nc), twb + g.twn1, g.n1);
+    r2c_store<T, NF, RN, LG>(g, gv, SA, lds, nthr, nval);
 }
 
 // Output O of the spectral multiply for the 8 wavenumbers of thread j along
@@ -1179,7 +1198,7 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int NO = F::NOUT, NG = node_group<T>();
-    const int lgNc = LG > 0 ? LG : 31 - __clz(g.Nc), Nc = 1 << lgNc, Tc = Nc >> 3;
+    const int Nc = x_len<LG>(g), lgNc = x_lg<LG>(g), Tc = Nc >> 3;
     const int nthr = LG > 0 ? xblock_threads<T>() : (int)blockDim.x;
     const int Lt = nthr / Tc;
     const int tid = threadIdx.x, j = tid % Tc, l = tid / Tc;
@@ -1189,7 +1208,7 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     const int pitch = row_pitch(Nc);
     cx<T>* row = lds + l * pitch;
     cx<T>* twn1 = lds + Lt * pitch;
-    stage_twiddles(twn1, twb, g.n1);
+    stage_table(twn1, twb + g.twn1, g.n1);
     // transposed load: thread (ll, kk < Tc) fetches the columns kk + Tc*i
     // (i < 8) and, for kk == 0, the Nyquist column Nc; the next field's
     // values are fetched while this field is transformed
@@ -1237,13 +1256,35 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
             cx<T> Dm = cmul(w, A - B);
             v[q] = (A + B) + cx<T>{-Dm.i, Dm.r};
         }
-        fft_line<1>(v, j, lgNc, twn1, 1, row);
+        if constexpr (LG >= 0) {
+            fft_line<1>(v, j, lgNc, twn1, 1, row);
+        } else {
+            // natural order in the row, then each thread takes its sub-line
+            // s: X[s + rad k2], k2 = jj + Tq q
+            const int Tq = 1 << (lgNc - 3), s = j >> (lgNc - 3), jj = j & (Tq - 1);
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 8; ++q) rowv[j + Tc * q] = v[q];
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = rowv[s + g.rad * (jj + Tq * q)];
+            fft_mixed_inv<T>(v, j, g.rad, lgNc, twn1, g.n1, row);
+        }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             val[o][2 * q] = v[q].r;
             val[o][2 * q + 1] = v[q].i;
         }
     }
+    // complex point held in v[q] by this thread: j + Tc q (powers of two),
+    // s M + jj + (M/8) q (mixed radix, sub-line s)
+    auto xpt = [&](int q) -> int {
+        if constexpr (LG >= 0) return j + Tc * q;
+        else {
+            const int Tq = 1 << (lgNc - 3);
+            return (j >> (lgNc - 3)) * (Tq << 3) + (j & (Tq - 1)) + Tq * q;
+        }
+    };
     // epilogue over the block's run of body nodes with consecutive threads on
     // consecutive nodes, the values passing through a flat [Lt][b1] staging
     // area over the row buffers (node slots per thread as in k_xfwd)
@@ -1257,7 +1298,7 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
             for (int q = 0; q < 8; ++q)
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
-                    const int x = 2 * (j + Tc * q) + e;
+                    const int x = 2 * xpt(q) + e;
                     if (x < g.b1) flat[l * g.b1 + x] = val[o][2 * q + e];
                 }
         }
@@ -1310,7 +1351,7 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     if constexpr (NCH > 0) {
         // the twiddles are still in LDS after the row buffers
         static_assert(F::NRED == 0, "a chained epilogue has no reductions");
-        r2c_store<T, NCH, RN>(g, chv, SAout, lds, lgNc, nthr, nval);
+        r2c_store<T, NCH, RN, LG>(g, chv, SAout, lds, nthr, nval);
     }
     if constexpr (F::NRED > 0) {
         __syncthreads();

@@ -38,6 +38,11 @@ CASES_2D = [((16, 32), (13, 21)), ((64, 128), (40, 100)), ((128, 64), (100, 40))
             ((512, 1024), (400, 1000)), ((32, 2048), (9, 1700)), ((1024, 64), (1000, 33))]
 CASES_3D = [((16, 16, 32), (9, 11, 20)), ((16, 32, 16), (12, 20, 12)), ((32, 64, 32), (20, 50, 17)), ((64, 32, 128), (50, 21, 100)),
             ((256, 16, 64), (200, 5, 40))]
+# x lengths n1 = 2 R 2^p (R = 3, 5, 9): the mixed-radix x transforms
+CASES_MIXED = [((16, 48), (13, 21)), ((64, 80), (40, 60)), ((32, 144), (20, 100)), ((16, 96), (9, 50)),
+               ((16, 384), (9, 256)), ((16, 320), (9, 256)), ((16, 288), (9, 256)), ((64, 2 * 9 * 64), (40, 1000)),
+               ((16, 16, 48), (9, 11, 20)), ((32, 64, 80), (20, 50, 60)), ((16, 32, 288), (9, 20, 256)),
+               ((16, 16, 384), (10, 12, 256))]
 
 
 def _plan(fft, body, dtype):
@@ -46,7 +51,7 @@ def _plan(fft, body, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("fft,body", CASES_2D + CASES_3D)
+@pytest.mark.parametrize("fft,body", CASES_2D + CASES_3D + CASES_MIXED)
 def test_conv_shift_kernels(fft, body, dtype):
     dim = len(fft)
     td = torch.float64 if dtype == "f64" else torch.float32

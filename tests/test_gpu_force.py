@@ -345,3 +345,67 @@ def test_energy_density_large_displacement(orc, dtype):
         assert res["direct"] <= 1e-5, res
         assert res["convolution"] > 100 * res["direct"], res
     plan.close()
+
+
+# Minimum-padding x grids (Sec. 4.2.2 needs only one horizon of padding):
+# x lengths n1 = 2 R 2^p with R = 3, 5, 9, through every chain and path the
+# plan runs, against the oracle (which does not depend on the grid).
+MIXED = [(48, 3), (80, 5), (144, 9), (96, 3)]
+
+
+@pytest.mark.parametrize("dtype", DT)
+@pytest.mark.parametrize("n1,R", MIXED)
+def test_mixed_radix_x_bb2d(orc, dtype, n1, R):
+    from paper_2105_06055_amd import binding
+    dx, m = 1e-3, 3
+    body = (37, n1 - m - 1)
+    chi = wl.random_mask(body, 71)
+    u = wl.random_field((2,) + body, 72, 1e-6)
+    plan = binding.Plan((64, n1), body, dx, m * dx, model="bb", E=72e9, nu=1 / 3, chiB=chi, dtype=dtype)
+    L = plan.force(_dev(u, dtype)).cpu().numpy()
+    g = orc.geom(body, dx, m * dx)
+    Lo = orc.bb_force(g, orc.bb_alpha(2, 72e9, m * dx), chi.astype(float), u)
+    _check(L, Lo, u, plan, 2440.0, dtype, f"mixed x n1={n1} bb2d")
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", DT)
+@pytest.mark.parametrize("n1,R", MIXED)
+def test_mixed_radix_x_lps3d_all_paths(orc, dtype, n1, R):
+    from paper_2105_06055_amd import binding
+    dx, m = 1e-3, 3
+    body = (17, 21, n1 - m - 2)
+    chi = wl.random_mask(body, 73)
+    u = wl.random_field((3,) + body, 74, 1e-6)
+    plan = binding.Plan((32, 32, n1), body, dx, m * dx, model="lps", E=70e9, nu=0.3, rho=2700.0, chiB=chi,
+                        dtype=dtype)
+    g = orc.geom(body, dx, m * dx)
+    Lo, _ = orc.lps_force(g, 70e9, 0.3, chi.astype(float), u)
+    for mode in ("auto", "yfft", "fft"):
+        plan.set_lastaxis(mode)
+        L = plan.force(_dev(u, dtype)).cpu().numpy()
+        _check(L, Lo, u, plan, 2700.0, dtype, f"mixed x n1={n1} lps {mode}")
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", DT)
+def test_mixed_radix_x_weighted_energy_2d(orc, dtype):
+    """Integrity weights and W (the fracture chain) on an x grid of 80."""
+    from paper_2105_06055_amd import binding
+    body, fft, dx, m = (40, 75), (64, 80), 1e-3, 3
+    w = wl.Workload(name="t", dim=2, body=body, fft=fft, dx=dx, delta=m * dx, model="bb", E=72e9, nu=1 / 3,
+                    G0=3.8)
+    w.chiB = wl.random_mask(body, 75)
+    w.chiO = np.stack([w.chiB] * 2)
+    lam = (np.random.default_rng(76).random(body) > 0.1).astype(np.uint8)
+    w.lam0 = lam
+    u = wl.random_field((2,) + body, 77, 1e-6)
+    plan = _plan(w, dtype, weight="integrity")
+    L, W = plan.force(_dev(u, dtype), weight=_dev(lam, torch.uint8), energy=True)
+    g = orc.geom(body, dx, w.delta)
+    alpha = orc.bb_alpha(2, w.E, w.delta)
+    phi = (w.chiB * lam).astype(float)
+    _check(L.cpu().numpy(), orc.bb_force(g, alpha, phi, u), u, plan, w.rho, dtype, "mixed x weighted")
+    assert parity.rel_max(W.cpu().numpy(), orc.bb_energy(g, alpha, phi, u)) <= (1e-12 if dtype == torch.float64
+                                                                                 else 1e-5)
+    plan.close()

@@ -170,3 +170,21 @@ def test_hetero_plate_512_scale_force(orc, dtype):
     else:
         assert e <= parity.FP32_OP and r <= parity.FP32_REL, (r, e)
     plan.close()
+
+
+@pytest.mark.parametrize("n1", [384, 320, 288])
+def test_lps_block_256_mixed_radix_x_full_field(orc, n1):
+    """The benchmark workload on minimum-padding x grids (n1 = 384 = 2 3 2^6,
+    320 = 2 5 2^5, 288 = 2 9 2^4; y and z keep 512): FP32 pd_force and one
+    Verlet step over every node against the oracle (whose sums do not depend
+    on the grid)."""
+    from paper_2105_06055_amd import binding
+    w, u = _c5()
+    dtype = torch.float32
+    plan = binding.Plan((512, 512, n1), w.body, w.dx, w.delta, model="lps", E=w.E, nu=w.nu, rho=w.rho,
+                        chiB=w.chiB, dtype=dtype)
+    print(f"full field: LPS 256^3 on a 512 x 512 x {n1} grid", flush=True)
+    L = plan.force(_dev(u, dtype)).cpu().numpy()
+    plan.close()
+    torch.cuda.empty_cache()
+    parity.check_force(L, _c5_oracle_force(orc), u, plan, w.rho, False, f"LPS 256^3 n1={n1}")
