@@ -476,6 +476,7 @@ def main():
     ap.add_argument("--energy-steps", type=int, default=1000)
     ap.add_argument("--no-mcross", action="store_true", help="skip the horizon (m) crossover of the force paths")
     ap.add_argument("--no-minpad", action="store_true", help="skip the minimum-padding (mixed-radix) x grids")
+    ap.add_argument("--no-refine", action="store_true", help="skip the static and fracture refinement studies")
     ap.add_argument("--cg-size", type=int, default=128)
     ap.add_argument("--cg-fft", type=int, default=256)
     ap.add_argument("--copy-calib", action="store_true",
@@ -579,6 +580,17 @@ def main():
                                  "delta = 3e-3 m, m = delta/dx; FP64; relative error vs the continuum Navier operator",
                      "rows": mconv.run()}
         log(f"[bench] m-convergence {json.dumps(mconv_tab['rows'])}")
+    refine = None
+    if not args.no_refine:
+        from paper_2105_06055_amd import mconv
+        refine = {"static_eq99": dict(mconv.static_refinement(),
+                                      workload="LPS cube, edge 16 delta, delta = 3 mm, centred spherical void r = "
+                                               "0.2 L, clamped z < 3 delta, uniform body force 1e8 N/m^3, E = 60 "
+                                               "GPa, nu = 0.4; FP64 PCG to 1e-10; Eq. 99 on the coarse nodes"),
+                  "fracture": dict(mconv.fracture_refinement(),
+                                   workload="notched glass plate 10 x 4 cm, delta = 1 mm, sigma = 4 MPa, 50 us "
+                                            "(dt 25 ns), FP32, energy failure rule")}
+        log(f"[bench] refinement eq99 {json.dumps(refine['static_eq99']['eq99'])}")
     energy = None
     if not args.no_energy:
         log(f"[bench] energy drift over {args.energy_steps} steps (FP32 and FP64)")
@@ -654,6 +666,7 @@ def main():
             "c2_force": c2,
             "nonlinear_bb_plate_force": nbb,
             "m_convergence": mconv_tab,
+            "refinement": refine,
             "fracture_plate": frac,
             "adjoint_plate": adj,
             "energy_drift": energy,

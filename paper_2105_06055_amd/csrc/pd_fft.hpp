@@ -215,60 +215,70 @@ __device__ __forceinline__ void stage_table(cx<T>* dst, const cx<T>* __restrict_
 // (Cooley-Tukey with n = n2 + M n1, k = k1 + R k2, n1, k1 < R; n2, k2 < M).
 // The line's Nc/8 threads form R groups of M/8: thread t = s (M/8) + j works
 // on sub-line s and holds the points j + (M/8) q, q < 8, of it.
-//   forward  y_s[n2] = sum_n1 x[n2 + M n1] W^{s (n2 + M n1)}  (W = e^{-2 pi i/Nc}),
-//            then the M-point transform of y_s: X[s + R k2], k2 = j + (M/8) q;
-//   inverse  the M-point inverse transform of X[s + R k2] over k2 gives
-//            z_s[n2], then x[n2 + M s] = sum_k1 z_k1[n2] W^{-k1 (n2 + M s)}.
-// Twiddles: W^e = tw[2e mod n1], tw the table of length n1 = 2 Nc in LDS;
-// the M-point transforms take W_M^e = W^{R e} from the same table.  lds
-// points at the line (fft_lds_len(Nc) complex slots); every thread of the
-// block calls these (block-wide barriers), the caller fences its own LDS
-// uses before and after.
-template <class T, class In>
-__device__ __forceinline__ void fft_mixed_fwd(cx<T> (&v)[8], int t, int R, int lgM, In in, const cx<T>* tw_g,
-                                              int n1, cx<T>* lds_g) {
+//   forward  y_s[n2] = W^{s n2} sum_n1 x[n2 + M n1] W_R^{s n1}  (W = e^{-2 pi i/Nc},
+//            W_R = W^M), then the M-point transform of y_s gives X[s + R k2],
+//            k2 = j + (M/8) q;
+//   inverse  the M-point inverse transform of X[s + R k2] over k2 gives z_s[n2],
+//            z_s[n2] W^{-s n2} goes through LDS, and
+//            x[n2 + M s] = sum_k1 (z_k1[n2] W^{-k1 n2}) W_R^{-k1 s}.
+// Twiddles: W^e = tw[2e], tw the table of length n1 = 2 Nc in LDS (every
+// index used is below n1); the M-point transforms take W_M^e = W^{R e} from
+// the same table; the R factors W_R^{s n1} of a thread are read once.  lds
+// points at the line (fft_lds_len(Nc) complex slots).  Every thread of the
+// block calls these (block-wide barriers); the caller fences its own LDS
+// uses before and after.  RC > 0 and LGM > 0 fix R and lgM at compile time.
+template <int RC, int LGM, class T, class In>
+__device__ __forceinline__ void fft_mixed_fwd(cx<T> (&v)[8], int t, int Rr, int lgMr, In in, const cx<T>* tw_g,
+                                              cx<T>* lds_g) {
+    const int R = RC > 0 ? RC : Rr, lgM = LGM > 0 ? LGM : lgMr;
     const int M = 1 << lgM, Tq = M >> 3;
     const int s = t >> (lgM - 3), j = t & (Tq - 1);
     lds_ptr<const cx<T>> tw = as_lds(tw_g);
-    const int de = (2 * s * M) % n1;
+    constexpr int RMAX = RC > 0 ? RC : 9;
+    cx<T> wr[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+        if (r < R) wr[r] = tw[(2 * M * ((s * r) % R))];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int n2 = j + Tq * q;
-        int e = (2 * s * n2) % n1;
-        cx<T> acc = {T(0), T(0)};
-        for (int r = 0; r < R; ++r) {
-            acc = acc + cmul(in(n2 + M * r), tw[e]);
-            e += de;
-            if (e >= n1) e -= n1;
-        }
-        v[q] = acc;
+        cx<T> acc = in(n2);
+#pragma unroll
+        for (int r = 1; r < RMAX; ++r)
+            if (r < R) acc = acc + cmul(in(n2 + M * r), wr[r]);
+        v[q] = cmul(acc, tw[2 * s * n2]);
     }
     fft_line<-1>(v, j, lgM, tw_g, 1, lds_g + s * fft_lds_len(M), R);
 }
 
-template <class T>
-__device__ __forceinline__ void fft_mixed_inv(cx<T> (&v)[8], int t, int R, int lgM, const cx<T>* tw_g, int n1,
+template <int RC, int LGM, class T>
+__device__ __forceinline__ void fft_mixed_inv(cx<T> (&v)[8], int t, int Rr, int lgMr, const cx<T>* tw_g,
                                               cx<T>* lds_g) {
+    const int R = RC > 0 ? RC : Rr, lgM = LGM > 0 ? LGM : lgMr;
     const int M = 1 << lgM, Tq = M >> 3;
     const int s = t >> (lgM - 3), j = t & (Tq - 1);
     fft_line<1>(v, j, lgM, tw_g, 1, lds_g + s * fft_lds_len(M), R);
     lds_ptr<const cx<T>> tw = as_lds(tw_g);
     lds_ptr<cx<T>> z = as_lds(lds_g);
+    constexpr int RMAX = RC > 0 ? RC : 9;
+    cx<T> wr[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+        if (r < R) wr[r] = cconj(tw[(2 * M * ((s * r) % R))]);
     __syncthreads();   // every sub-line transform is done with its LDS
 #pragma unroll
-    for (int q = 0; q < 8; ++q) z[s * M + j + Tq * q] = v[q];
+    for (int q = 0; q < 8; ++q) {
+        const int n2 = j + Tq * q;
+        z[s * M + n2] = cmul(v[q], cconj(tw[2 * s * n2]));
+    }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int n2 = j + Tq * q;
-        const int de = (2 * (n2 + M * s)) % n1;
-        int e = 0;
-        cx<T> acc = {T(0), T(0)};
-        for (int r = 0; r < R; ++r) {
-            acc = acc + cmul(z[r * M + n2], cconj(tw[e]));
-            e += de;
-            if (e >= n1) e -= n1;
-        }
+        cx<T> acc = z[n2];
+#pragma unroll
+        for (int r = 1; r < RMAX; ++r)
+            if (r < R) acc = acc + cmul(z[r * M + n2], wr[r]);
         v[q] = acc;
     }
 }

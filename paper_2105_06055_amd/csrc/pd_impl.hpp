@@ -292,7 +292,7 @@ template <class T, class G, int LG>
 pd_status launch_xfwd_lg(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
     const Geo& g = p->geo;
     const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
-    if (LG > 0 && Tc * Lt != xblock_threads<T>()) return PD_EUNSUPPORTED;
+    if (x_block_fixed<T, LG>() > 0 && Tc * Lt != x_block_fixed<T, LG>()) return PD_EUNSUPPORTED;
     dim3 grid((g.b2 + Lt - 1) / Lt, g.b3), block(Tc * Lt);
     size_t lds = ((size_t)Lt * row_pitch(g.Nc) + tw_lds_len(g.n1)) * sizeof(cx<T>);
     allow_lds(k_xfwd<T, G, LG>, lds);
@@ -305,9 +305,39 @@ pd_status launch_xfwd_lg(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
     }
     return pdh::check(hipGetLastError());
 }
+// Mixed-radix x lengths with compile-time kernels (the minimum-padding x
+// grids of a 256-node body: n1 = 384, 320, 288; FP32): the launch
+// configuration must have the fixed block shape, else the runtime-length
+// kernel runs.
+template <class T>
+int x_mixed_lg(pd_plan p) {
+    const Geo& g = p->geo;
+    const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
+    auto fits = [&](int R, int lgM) {
+        const int rn = R == 3 ? 11 : (R == 5 ? 13 : 15);   // x_rn of the specialisation
+        return g.rad == R && g.lgM == lgM && Tc * Lt == ((R << lgM) / 8) * (sizeof(T) == 4 ? 16 : 8) &&
+               8 * g.b1 <= rn * g.Nc;
+    };
+    if (fits(3, 6)) return mix_lg(3, 6);
+    if (fits(5, 5)) return mix_lg(5, 5);
+    if (fits(9, 4)) return mix_lg(9, 4);
+    return -1;
+}
+
 template <class T, class G>
 pd_status launch_xfwd(pd_plan p, const G& gen, cx<T>* SA, hipStream_t st) {
-    if (p->geo.rad != 1) return launch_xfwd_lg<T, G, -1>(p, gen, SA, st);
+    if (p->geo.rad != 1) {
+        // compile-time mixed lengths in FP32 only (FP64 takes the runtime kernel)
+        if constexpr (sizeof(T) == 4) {
+            switch (x_mixed_lg<T>(p)) {
+                case mix_lg(3, 6): return launch_xfwd_lg<T, G, mix_lg(3, 6)>(p, gen, SA, st);
+                case mix_lg(5, 5): return launch_xfwd_lg<T, G, mix_lg(5, 5)>(p, gen, SA, st);
+                case mix_lg(9, 4): return launch_xfwd_lg<T, G, mix_lg(9, 4)>(p, gen, SA, st);
+                default: break;
+            }
+        }
+        return launch_xfwd_lg<T, G, -1>(p, gen, SA, st);
+    }
     if (p->geo.b1 <= p->geo.Nc) {
         if (p->geo.Nc == (1 << kFastLgX)) return launch_xfwd_lg<T, G, kFastLgX>(p, gen, SA, st);
         if (p->geo.Nc == (1 << kFastLgX2)) return launch_xfwd_lg<T, G, kFastLgX2>(p, gen, SA, st);
@@ -548,7 +578,7 @@ template <class T, class F, int LG>
 pd_status launch_xinv_lg(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st, cx<T>* SAout = nullptr) {
     const Geo& g = p->geo;
     const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
-    if (LG > 0 && Tc * Lt != xblock_threads<T>()) return PD_EUNSUPPORTED;
+    if (x_block_fixed<T, LG>() > 0 && Tc * Lt != x_block_fixed<T, LG>()) return PD_EUNSUPPORTED;
     dim3 grid((g.b2 + Lt - 1) / Lt, g.b3), block(Tc * Lt);
     size_t lds = ((size_t)Lt * row_pitch(g.Nc) + tw_lds_len(g.n1)) * sizeof(cx<T>);
     size_t red_lds = (size_t)((Tc * Lt + 63) / 64) * 8 * sizeof(double);
@@ -576,7 +606,17 @@ pd_status launch_xinv_lg(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t s
 }
 template <class T, class F>
 pd_status launch_xinv(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st, cx<T>* SAout = nullptr) {
-    if (p->geo.rad != 1) return launch_xinv_lg<T, F, -1>(p, fin, SA, st, SAout);
+    if (p->geo.rad != 1) {
+        if constexpr (sizeof(T) == 4) {
+            switch (x_mixed_lg<T>(p)) {
+                case mix_lg(3, 6): return launch_xinv_lg<T, F, mix_lg(3, 6)>(p, fin, SA, st, SAout);
+                case mix_lg(5, 5): return launch_xinv_lg<T, F, mix_lg(5, 5)>(p, fin, SA, st, SAout);
+                case mix_lg(9, 4): return launch_xinv_lg<T, F, mix_lg(9, 4)>(p, fin, SA, st, SAout);
+                default: break;
+            }
+        }
+        return launch_xinv_lg<T, F, -1>(p, fin, SA, st, SAout);
+    }
     if (p->geo.b1 <= p->geo.Nc) {
         if (p->geo.Nc == (1 << kFastLgX)) return launch_xinv_lg<T, F, kFastLgX>(p, fin, SA, st, SAout);
         if (p->geo.Nc == (1 << kFastLgX2)) return launch_xinv_lg<T, F, kFastLgX2>(p, fin, SA, st, SAout);

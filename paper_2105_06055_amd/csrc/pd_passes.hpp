@@ -99,11 +99,45 @@ __device__ __forceinline__ void block_reduce_store(double (&red)[NR], double* ou
 }
 
 // Line length of the x passes: LG > 0 fixes Nc = 2^LG at compile time, LG = 0
-// takes a power of two from g, LG < 0 the mixed-radix Nc = rad 2^lgM of g.
+// takes a power of two from g, LG = -1 the mixed-radix Nc = rad 2^lgM of g,
+// and LG = mix_lg(R, lgM) < -1 fixes a mixed-radix Nc = R 2^lgM at compile
+// time.
+__host__ __device__ constexpr int mix_lg(int R, int lgM) { return -(16 * R + lgM); }
 template <int LG>
-__device__ __forceinline__ int x_len(const Geo& g) { return LG > 0 ? (1 << LG) : g.Nc; }
+__host__ __device__ constexpr int mix_R() { return LG < -1 ? (-LG) / 16 : 0; }
 template <int LG>
-__device__ __forceinline__ int x_lg(const Geo& g) { return LG > 0 ? LG : (LG == 0 ? 31 - __clz(g.Nc) : g.lgM); }
+__host__ __device__ constexpr int mix_lgM() { return LG < -1 ? (-LG) % 16 : 0; }
+template <int LG>
+__device__ __forceinline__ int x_len(const Geo& g) {
+    if constexpr (LG > 0) return 1 << LG;
+    else if constexpr (LG < -1) return mix_R<LG>() << mix_lgM<LG>();
+    else return g.Nc;
+}
+template <int LG>
+__device__ __forceinline__ int x_lg(const Geo& g) {
+    if constexpr (LG > 0) return LG;
+    else if constexpr (LG < -1) return mix_lgM<LG>();
+    else if constexpr (LG == 0) return 31 - __clz(g.Nc);
+    else return g.lgM;
+}
+// Body-node slots per thread of the x passes (the block's run of Lt rows of
+// b1 nodes over its Lt Nc / 8 threads): 8 for the compile-time powers of two
+// (b1 <= Nc), 11, 13, 15 for the compile-time mixed lengths of a 256-node
+// body (b1 <= x_rn Nc / 8), 16 otherwise (b1 < 2 Nc).
+template <int LG>
+__host__ __device__ constexpr int x_rn() {
+    if constexpr (LG > 0) return 8;
+    else if constexpr (LG < -1) return mix_R<LG>() == 3 ? 11 : (mix_R<LG>() == 5 ? 13 : 15);
+    else return 16;
+}
+// Threads of an x-pass block: fixed for the compile-time lengths (16 rows in
+// FP32, 8 in FP64), else the launch's block size.
+template <class T, int LG>
+__host__ __device__ constexpr int x_block_fixed() {
+    if constexpr (LG > 0) return xblock_threads<T>();
+    else if constexpr (LG < -1) return ((mix_R<LG>() << mix_lgM<LG>()) / 8) * (sizeof(T) == 4 ? 16 : 8);
+    else return 0;
+}
 
 // r2c along x of NF real fields held in the flat node mapping (thread tid
 // holds nodes tid + nthr r of the block's run, r < RN) and transposed store
@@ -150,11 +184,12 @@ __device__ __forceinline__ void r2c_store(const Geo& g, const T (&gv)[NF][RN], c
 #pragma unroll
             for (int q = 0; q < 8; ++q) rowv[j + Tc * q] = v[q];
         } else {
-            fft_mixed_fwd<T>(v, j, g.rad, lgNc, pair, twn1, g.n1, row);
+            fft_mixed_fwd<mix_R<LG>(), mix_lgM<LG>(), T>(v, j, g.rad, lgNc, pair, twn1, row);
             __syncthreads();
             const int Tq = 1 << (lgNc - 3), s = j >> (lgNc - 3), jj = j & (Tq - 1);
+            const int R = LG < -1 ? mix_R<LG>() : g.rad;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) rowv[s + g.rad * (jj + Tq * q)] = v[q];
+            for (int q = 0; q < 8; ++q) rowv[s + R * (jj + Tq * q)] = v[q];
         }
         __syncthreads();
         cx<T> X[8];
@@ -200,7 +235,7 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int NF = G::NIN, NG = 4;
     const int Nc = x_len<LG>(g), Tc = Nc >> 3;
-    const int nthr = LG > 0 ? xblock_threads<T>() : (int)blockDim.x;
+    const int nthr = x_block_fixed<T, LG>() > 0 ? x_block_fixed<T, LG>() : (int)blockDim.x;
     const int Lt = nthr / Tc;
     const int tid = threadIdx.x;
     const int z = blockIdx.y;
@@ -212,7 +247,7 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
     // x pairs 2(j + Tc q), +1) through a flat [Lt][b1] staging area that
     // overlays the row buffers.  Nodes per thread: Lt*b1/nthr = 8 b1/Nc,
     // at most 8 when b1 <= Nc (required for LG > 0), else at most 16.
-    constexpr int RN = LG > 0 ? 8 : 16;
+    constexpr int RN = x_rn<LG>();
     const long nbase = ((long)z * g.b2 + y0) * g.b1;
     const int nval = min(Lt, g.b2 - y0) * g.b1;
     T gv[NF][RN];
@@ -232,11 +267,13 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
             typename G::Ld ld[NG];
 #pragma unroll
             for (int q = 0; q < NG; ++q) {
+                if (r0 + q >= RN) break;   // the last group of an RN that NG does not divide
                 const int e = tid + nthr * (r0 + q);
                 if (decltype(full)::value || e < nval) ld[q] = gen.load(Nd{nbase, (uint32_t)e}, cbv[r0 + q]);
             }
 #pragma unroll
             for (int q = 0; q < NG; ++q) {
+                if (r0 + q >= RN) break;
                 const int e = tid + nthr * (r0 + q);
                 T a[NF];
 #pragma unroll
@@ -1199,7 +1236,7 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int NO = F::NOUT, NG = node_group<T>();
     const int Nc = x_len<LG>(g), lgNc = x_lg<LG>(g), Tc = Nc >> 3;
-    const int nthr = LG > 0 ? xblock_threads<T>() : (int)blockDim.x;
+    const int nthr = x_block_fixed<T, LG>() > 0 ? x_block_fixed<T, LG>() : (int)blockDim.x;
     const int Lt = nthr / Tc;
     const int tid = threadIdx.x, j = tid % Tc, l = tid / Tc;
     const int z = blockIdx.y;
@@ -1225,7 +1262,7 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     fetch(0);
     // flags of this thread's epilogue nodes, loaded ahead of the transforms
     // (the epilogue's static-field addresses depend on them)
-    constexpr int RN = LG > 0 ? 8 : 16;
+    constexpr int RN = x_rn<LG>();
     const long nbase = ((long)z * g.b2 + y0) * g.b1;
     const int nval = min(Lt, g.b2 - y0) * g.b1;
     uint8_t cbv[RN];
@@ -1234,10 +1271,24 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
         const int e = tid + nthr * r;
         cbv[r] = e < nval ? node_flags(fin, Nd{nbase, (uint32_t)e}) : uint8_t(0);
     }
-    T val[NO][16];
     lds_ptr<cx<T>> rowv = as_lds(row);
     lds_ptr<cx<T>> ldsv = as_lds(lds);
     lds_ptr<const cx<T>> twv = as_lds(twn1);
+    // complex point held in v[q] by this thread after the inverse transform:
+    // j + Tc q (powers of two), s M + jj + (M/8) q (mixed radix, sub-line s)
+    auto xpt = [&](int q) -> int {
+        if constexpr (LG >= 0) return j + Tc * q;
+        else {
+            const int Tq = 1 << (lgNc - 3);
+            return (j >> (lgNc - 3)) * (Tq << 3) + (j & (Tq - 1)) + Tq * q;
+        }
+    };
+    // Each field: transposed spectra into the rows, c2r, then straight to the
+    // epilogue layout (consecutive threads on consecutive nodes of the
+    // block's run) through a flat [Lt][b1] staging area over the row
+    // buffers, so only the per-node values nv stay in registers.
+    lds_ptr<T> flat = as_lds(reinterpret_cast<T*>(lds));
+    T nv[NO][RN];
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
         __syncthreads();
@@ -1246,61 +1297,37 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
         if (kk == 0) ldsv[ll * pitch + Nc] = pre[8];
         if (o + 1 < NO) fetch(o + 1);
         __syncthreads();
-        cx<T> v[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int k = j + Tc * q;
+        // the complex half-spectrum point k of the packed c2r input, from the
+        // r2c spectrum points k and Nc - k
+        auto c2r_pre = [&](int k) -> cx<T> {
             cx<T> A = rowv[k];
             cx<T> B = cconj(rowv[Nc - k]);
             cx<T> w = cconj(twv[k]);
             cx<T> Dm = cmul(w, A - B);
-            v[q] = (A + B) + cx<T>{-Dm.i, Dm.r};
-        }
+            return (A + B) + cx<T>{-Dm.i, Dm.r};
+        };
+        cx<T> v[8];
         if constexpr (LG >= 0) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = c2r_pre(j + Tc * q);
             fft_line<1>(v, j, lgNc, twn1, 1, row);
         } else {
-            // natural order in the row, then each thread takes its sub-line
-            // s: X[s + rad k2], k2 = jj + Tq q
+            // each thread forms the points of its sub-line s directly:
+            // X[s + rad k2], k2 = jj + Tq q
             const int Tq = 1 << (lgNc - 3), s = j >> (lgNc - 3), jj = j & (Tq - 1);
-            __syncthreads();
+            const int R = LG < -1 ? mix_R<LG>() : g.rad;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) rowv[j + Tc * q] = v[q];
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = rowv[s + g.rad * (jj + Tq * q)];
-            fft_mixed_inv<T>(v, j, g.rad, lgNc, twn1, g.n1, row);
+            for (int q = 0; q < 8; ++q) v[q] = c2r_pre(s + R * (jj + Tq * q));
+            fft_mixed_inv<mix_R<LG>(), mix_lgM<LG>(), T>(v, j, g.rad, lgNc, twn1, row);
         }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            val[o][2 * q] = v[q].r;
-            val[o][2 * q + 1] = v[q].i;
-        }
-    }
-    // complex point held in v[q] by this thread: j + Tc q (powers of two),
-    // s M + jj + (M/8) q (mixed radix, sub-line s)
-    auto xpt = [&](int q) -> int {
-        if constexpr (LG >= 0) return j + Tc * q;
-        else {
-            const int Tq = 1 << (lgNc - 3);
-            return (j >> (lgNc - 3)) * (Tq << 3) + (j & (Tq - 1)) + Tq * q;
-        }
-    };
-    // epilogue over the block's run of body nodes with consecutive threads on
-    // consecutive nodes, the values passing through a flat [Lt][b1] staging
-    // area over the row buffers (node slots per thread as in k_xfwd)
-    lds_ptr<T> flat = as_lds(reinterpret_cast<T*>(lds));
-    T nv[NO][RN];
-#pragma unroll
-    for (int o = 0; o < NO; ++o) {
-        __syncthreads();
+        __syncthreads();   // every row transform is done with its LDS
         if (y < g.b2) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    const int x = 2 * xpt(q) + e;
-                    if (x < g.b1) flat[l * g.b1 + x] = val[o][2 * q + e];
-                }
+            for (int q = 0; q < 8; ++q) {
+                const int x = 2 * xpt(q);
+                if (x < g.b1) flat[l * g.b1 + x] = v[q].r;
+                if (x + 1 < g.b1) flat[l * g.b1 + x + 1] = v[q].i;
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -1324,11 +1351,13 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
             typename F::Ld ld[NG];
 #pragma unroll
             for (int q = 0; q < NG; ++q) {
+                if (r0 + q >= RN) break;   // the last group of an RN that NG does not divide
                 const int e = tid + nthr * (r0 + q);
                 if (decltype(full)::value || e < nval) ld[q] = fin.load(Nd{nbase, (uint32_t)e}, cbv[r0 + q]);
             }
 #pragma unroll
             for (int q = 0; q < NG; ++q) {
+                if (r0 + q >= RN) break;
                 const int e = tid + nthr * (r0 + q);
                 if (decltype(full)::value || e < nval) {
                     T vv[NO];

@@ -205,3 +205,73 @@ def random_mask(shape, seed, p_hole=0.15, blobs=3):
         chi[tuple(slice(l, h) for l, h in zip(lo, hi))] = 0
     chi[rng.random(shape) < p_hole * 0.1] = 0
     return chi
+
+
+def _grid_len(n, m, mixed_ok=False):
+    """Smallest supported FFT length >= n + m: a power of two (>= 16), or for
+    the x axis also 2 R 2^p with R = 3, 5, 9 and 2^p >= 8."""
+    need = max(16, n + m)
+    best = 16
+    while best < need:
+        best *= 2
+    if mixed_ok:
+        for R in (3, 5, 9):
+            p = 8
+            while 2 * R * p < need:
+                p *= 2
+            best = min(best, 2 * R * p)
+    return best
+
+
+def cube_void_refined(m, delta=3e-3, edge_horizons=16, E=60e9, nu=0.4, b0=1e8):
+    """The static cube of the refinement study (Sec. 5.1, Eq. 99): edge
+    L = edge_horizons * delta, nodes at x = i dx (i = 0 .. N, N = L/dx), so
+    that halving dx keeps every node (the coarse nodes are the even fine
+    ones); a centred spherical void of radius 0.2 L, clamped (u = 0) on the
+    layer z < 3 delta, a uniform body force -b0 along z on the unknowns.
+    Same physical problem for every m = delta/dx; deterministic."""
+    dx = delta / m
+    N = edge_horizons * m
+    n = N + 1
+    L = N * dx
+    c = np.arange(n) * dx
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    r2 = (x - L / 2) ** 2 + (y - L / 2) ** 2 + (z - L / 2) ** 2
+    chiB = (r2 > (0.2 * L) ** 2).astype(np.uint8)
+    omega = chiB.copy()
+    omega[z < 3 * delta - 1e-12 * dx] = 0
+    chiO = np.stack([omega, omega, omega])
+    b = np.zeros((3, n, n, n))
+    b[2] = -b0 * omega
+    f = _grid_len(n, m)
+    return Workload(name=f"lps3d_static_refined_m{m}", dim=3, body=(n, n, n),
+                    fft=(f, f, _grid_len(n, m, mixed_ok=True)), dx=dx, delta=delta, model="lps", E=E, nu=nu,
+                    chiB=chiB, chiO=chiO, u0=np.zeros((3, n, n, n)), b=b, w=np.zeros((3, n, n, n)),
+                    extra={"m": m})
+
+
+def notched_plate_refined(m, delta=1e-3, Lx=0.1, Ly=0.04, E=72e9, rho=2440.0, G0=3.8, sigma=4e6,
+                          notch=0.05, dt=2.5e-8, steps=2000):
+    """The notched glass plate of the fracture refinement study (Sec. 5.2,
+    Fig. 15: sigma = 4 MPa, delta = 1 mm): a fixed horizon delta,
+    dx = delta/m, nodes at x = i dx (i = 0 .. Lx/dx, so halving dx keeps
+    every node), integrity 0 on a delta-thick notch layer on the mid-line for
+    x < notch, tractions +-sigma as body forces sigma/delta on the
+    delta-thick top and bottom layers, 50 us of loading.  Same physical
+    problem for every m; deterministic."""
+    dx = delta / m
+    nx, ny = int(round(Lx / dx)) + 1, int(round(Ly / dx)) + 1
+    xc, yc = np.arange(nx) * dx, np.arange(ny) * dx
+    Y, X = np.meshgrid(yc, xc, indexing="ij")
+    body = (ny, nx)
+    chiB = np.ones(body, np.uint8)
+    lam0 = np.ones(body, np.uint8)
+    lam0[(X < notch) & (np.abs(Y - Ly / 2) < delta / 2)] = 0
+    b = np.zeros((2,) + body)
+    b[1][Y > Ly - delta] = sigma / delta
+    b[1][Y < delta] = -sigma / delta
+    fft = (_grid_len(ny, m), _grid_len(nx, m, mixed_ok=True))
+    return Workload(name=f"bb2d_fracture_refined_m{m}", dim=2, body=body, fft=fft, dx=dx, delta=delta,
+                    model="bb", E=E, nu=1.0 / 3.0, rho=rho, G0=G0, dt=dt, steps=steps, chiB=chiB,
+                    chiO=np.stack([chiB, chiB]), u0=np.zeros((2,) + body), v0=np.zeros((2,) + body), b=b,
+                    w=np.zeros((2,) + body), lam0=lam0, extra={"sigma": sigma, "m": m})
