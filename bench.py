@@ -250,6 +250,18 @@ def run_fracture(steps, warmup, chunk=1000):
         out[dn] = {"ms_per_step": t * 1e3, "Gnode_steps_s": w.nodes / t / 1e9,
                    "failed_nodes": int((w.lam0.astype(int) - st["lam"].cpu().numpy().astype(int)).sum()),
                    "finite": bool(torch.isfinite(st["u"]).all().item())}
+    # pass durations of 200 FP32 steps from a scratch state (a separate,
+    # instrumented run): their sum per step against the uninstrumented time
+    # per step shows the gaps between launches
+    r = runs["fp32"]
+    prof = ProfileSession(r["plan"])
+    st = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in r["st"].items()}
+    r["plan"].verlet(st, w.dt, 200, b=r["b"])
+    torch.cuda.synchronize()
+    passes = prof.read()
+    out["fp32"]["passes"] = passes
+    out["fp32"]["kernel_ms_per_step"] = sum(p["total_ms"] for p in passes) / 200
+    del st
     d32 = runs["fp32"]["plan"].damage_index(runs["fp32"]["st"]["lam"]).double()
     d64 = runs["fp64"]["plan"].damage_index(runs["fp64"]["st"]["lam"])
     out["fp32_vs_fp64"] = {"integrity_nodes_differing_after_steps": diff,

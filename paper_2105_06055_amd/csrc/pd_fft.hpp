@@ -265,11 +265,14 @@ __device__ __forceinline__ void fft_mixed_inv(cx<T> (&v)[8], int t, int Rr, int 
 #pragma unroll
     for (int r = 0; r < RMAX; ++r)
         if (r < R) wr[r] = cconj(tw[(2 * M * ((s * r) % R))]);
+    // z_s at the sub-line's own slots (pitch fft_lds_len(M), so that the
+    // groups of threads of different s meet different banks)
+    const int zp = fft_lds_len(M);
     __syncthreads();   // every sub-line transform is done with its LDS
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int n2 = j + Tq * q;
-        z[s * M + n2] = cmul(v[q], cconj(tw[2 * s * n2]));
+        z[s * zp + n2] = cmul(v[q], cconj(tw[2 * s * n2]));
     }
     __syncthreads();
 #pragma unroll
@@ -278,7 +281,7 @@ __device__ __forceinline__ void fft_mixed_inv(cx<T> (&v)[8], int t, int Rr, int 
         cx<T> acc = z[n2];
 #pragma unroll
         for (int r = 1; r < RMAX; ++r)
-            if (r < R) acc = acc + cmul(z[r * M + n2], wr[r]);
+            if (r < R) acc = acc + cmul(z[r * zp + n2], wr[r]);
         v[q] = acc;
     }
 }

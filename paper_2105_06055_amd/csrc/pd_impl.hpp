@@ -225,10 +225,7 @@ template <class T>
 int rows_per_block(pd_plan p) {
     const Geo& g = p->geo;
     const int Tc = g.Nc / 8;
-    int Lt = (sizeof(T) == 4) ? 16 : 8;
-    // 128-point rows (the 256-point x box): as many rows as fill the
-    // specialised block (32 in FP32, 16 in FP64)
-    if (g.Nc == 128) Lt = xblock_threads<T>() / Tc;
+    int Lt = xrows<T>();
     while (Lt > 1 && Tc * Lt > 512) Lt >>= 1;
     // few rows (2D plates, small blocks): fewer rows per block, down to two
     // (16-byte runs in the transposed stores), until the grid has a block for
@@ -315,7 +312,7 @@ int x_mixed_lg(pd_plan p) {
     const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
     auto fits = [&](int R, int lgM) {
         const int rn = R == 3 ? 11 : (R == 5 ? 13 : 15);   // x_rn of the specialisation
-        return g.rad == R && g.lgM == lgM && Tc * Lt == ((R << lgM) / 8) * (sizeof(T) == 4 ? 16 : 8) &&
+        return g.rad == R && g.lgM == lgM && Tc * Lt == ((R << lgM) / 8) * xrows<T>() &&
                8 * g.b1 <= rn * g.Nc;
     };
     if (fits(3, 6)) return mix_lg(3, 6);

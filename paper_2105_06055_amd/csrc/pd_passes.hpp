@@ -37,10 +37,10 @@ __host__ __device__ constexpr int row_pitch(int Nc) { return (fft_lds_len(Nc) + 
 // LDS pitch of an N-point line used by the y and last-axis passes.
 __host__ __device__ constexpr int line_pitch(int N) { return (fft_lds_len(N) + 1) | 1; }
 
-// Block size of the specialised (LG > 0, Nc = 256) x passes: 16 rows of 32
-// threads in FP32, 8 rows in FP64.
+// Rows per block of the x passes: 16 in FP32 and 8 in FP64 (runs of 128 B in
+// the transposed spectra accesses).
 template <class T>
-__host__ __device__ constexpr int xblock_threads() { return sizeof(T) == 4 ? 512 : 256; }
+__host__ __device__ constexpr int xrows() { return sizeof(T) == 4 ? 16 : 8; }
 
 // Body nodes whose loads the x passes issue together (see k_xfwd): four,
 // and two in the FP64 c2r pass (the epilogues' loads of four FP64 nodes do
@@ -130,12 +130,12 @@ __host__ __device__ constexpr int x_rn() {
     else if constexpr (LG < -1) return mix_R<LG>() == 3 ? 11 : (mix_R<LG>() == 5 ? 13 : 15);
     else return 16;
 }
-// Threads of an x-pass block: fixed for the compile-time lengths (16 rows in
-// FP32, 8 in FP64), else the launch's block size.
+// Threads of an x-pass block: fixed for the compile-time lengths (xrows rows
+// of Nc / 8 threads), else the launch's block size.
 template <class T, int LG>
 __host__ __device__ constexpr int x_block_fixed() {
-    if constexpr (LG > 0) return xblock_threads<T>();
-    else if constexpr (LG < -1) return ((mix_R<LG>() << mix_lgM<LG>()) / 8) * (sizeof(T) == 4 ? 16 : 8);
+    if constexpr (LG > 0) return ((1 << LG) / 8) * xrows<T>();
+    else if constexpr (LG < -1) return ((mix_R<LG>() << mix_lgM<LG>()) / 8) * xrows<T>();
     else return 0;
 }
 
@@ -1058,35 +1058,56 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
             // to arrive)
             load(std::integral_constant<int, PS>{}, zi + PF);
             if (act) {
-                // per output, the terms even (G = 0) and odd (G = 1) along z of
-                // inputs J0 .. J1-1 summed, then added to the planes they reach
+                // per output and z-offset b, the terms of inputs J0 .. J1-1
+                // even (G = 0) and odd (G = 1) along z: q0 and q1 reach output
+                // plane zi - b as q0 + q1 and (b > 0) plane zi + b as q0 - q1.
+                // The sums are chained to save adds: at b = 0 the G = 0 chain
+                // starts from the accumulator itself; with both parities the
+                // G = 1 chain starts from q0, giving s = q0 + q1, and the
+                // other plane takes 2 q0 - s.
                 auto terms = [&](auto j0c, auto j1c, const cx<T>(*pe)[MT + 1], const cx<T>(*po)[MT + 1]) {
                     constexpr int J0 = decltype(j0c)::value, J1 = decltype(j1c)::value;
                     OutLoop<0, NO>::run([&](auto Oc) {
                         constexpr int O = decltype(Oc)::value;
-                        OutLoop<0, 2>::run([&](auto Gc) {
-                            constexpr int G = decltype(Gc)::value;
-                            if constexpr (yz_group_used<M, O, G, J0, J1>()) {
-                                OutLoop<G, MT + 1>::run([&](auto bc) {
-                                    constexpr int b = decltype(bc)::value;
-                                    cx<T> q = {T(0), T(0)};
-                                    OutLoop<J0, J1>::run([&](auto Jc) {
-                                        constexpr int J = decltype(Jc)::value;
-                                        constexpr DTerm tm = yz_dterm<M>(O, J);
-                                        if constexpr (tm.coef != 0 && ((M::par3(tm.c) >> 2) & 1) == G) {
-                                            yz_term<T, MT, NU, tm.c, M::par3(tm.c), yz_factor<M>(tm), tm.ka, b>(
-                                                q, tk, pe[J - J0], po[J - J0], ka);
-                                        }
-                                    });
-                                    // input plane zi reaches output plane zi - b with oz = +b
-                                    // and, for b > 0, plane zi + b with oz = -b (sign (-1)^G)
-                                    constexpr int sm = (rr - b + RR) % RR, sp = (rr + b) % RR;
-                                    acc[sm][O] = acc[sm][O] + q;
-                                    if constexpr (b > 0) {
-                                        if constexpr (G == 0) acc[sp][O] = acc[sp][O] + q;
-                                        else acc[sp][O] = acc[sp][O] - q;
-                                    }
-                                });
+                        constexpr bool U0 = yz_group_used<M, O, 0, J0, J1>(), U1 = yz_group_used<M, O, 1, J0, J1>();
+                        auto chain = [&](auto Gc, auto bc, cx<T>& q) {
+                            constexpr int G = decltype(Gc)::value, b = decltype(bc)::value;
+                            OutLoop<J0, J1>::run([&](auto Jc) {
+                                constexpr int J = decltype(Jc)::value;
+                                constexpr DTerm tm = yz_dterm<M>(O, J);
+                                if constexpr (tm.coef != 0 && ((M::par3(tm.c) >> 2) & 1) == G) {
+                                    yz_term<T, MT, NU, tm.c, M::par3(tm.c), yz_factor<M>(tm), tm.ka, b>(
+                                        q, tk, pe[J - J0], po[J - J0], ka);
+                                }
+                            });
+                        };
+                        OutLoop<0, MT + 1>::run([&](auto bc) {
+                            constexpr int b = decltype(bc)::value;
+                            // input plane zi reaches output plane zi - b with oz = +b
+                            // and, for b > 0, plane zi + b with oz = -b
+                            constexpr int sm = (rr - b + RR) % RR, sp = (rr + b) % RR;
+                            using I0 = std::integral_constant<int, 0>;
+                            using I1 = std::integral_constant<int, 1>;
+                            if constexpr (b == 0) {
+                                if constexpr (U0) chain(I0{}, bc, acc[sm][O]);
+                            } else if constexpr (U0 && U1) {
+                                cx<T> q0 = {T(0), T(0)};
+                                chain(I0{}, bc, q0);
+                                cx<T> s = q0;
+                                chain(I1{}, bc, s);
+                                acc[sm][O] = acc[sm][O] + s;
+                                acc[sp][O].r = (acc[sp][O].r + T(2) * q0.r) - s.r;
+                                acc[sp][O].i = (acc[sp][O].i + T(2) * q0.i) - s.i;
+                            } else if constexpr (U0) {
+                                cx<T> q0 = {T(0), T(0)};
+                                chain(I0{}, bc, q0);
+                                acc[sm][O] = acc[sm][O] + q0;
+                                acc[sp][O] = acc[sp][O] + q0;
+                            } else if constexpr (U1) {
+                                cx<T> q1 = {T(0), T(0)};
+                                chain(I1{}, bc, q1);
+                                acc[sm][O] = acc[sm][O] + q1;
+                                acc[sp][O] = acc[sp][O] - q1;
                             }
                         });
                     });
@@ -1322,11 +1343,21 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
         }
         __syncthreads();   // every row transform is done with its LDS
         if (y < g.b2) {
+            if ((g.b1 & 1) == 0) {
+                // one 2T store per pair (even b1: pairs start at even slots)
+                lds_ptr<cx<T>> flat2 = (lds_ptr<cx<T>>)flat;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int x = 2 * xpt(q);
-                if (x < g.b1) flat[l * g.b1 + x] = v[q].r;
-                if (x + 1 < g.b1) flat[l * g.b1 + x + 1] = v[q].i;
+                for (int q = 0; q < 8; ++q) {
+                    const int x = 2 * xpt(q);
+                    if (x < g.b1) flat2[(l * g.b1 + x) >> 1] = v[q];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int x = 2 * xpt(q);
+                    if (x < g.b1) flat[l * g.b1 + x] = v[q].r;
+                    if (x + 1 < g.b1) flat[l * g.b1 + x + 1] = v[q].i;
+                }
             }
         }
         __syncthreads();
