@@ -491,6 +491,10 @@ def main():
     ap.add_argument("--no-refine", action="store_true", help="skip the static and fracture refinement studies")
     ap.add_argument("--cg-size", type=int, default=128)
     ap.add_argument("--cg-fft", type=int, default=256)
+    ap.add_argument("--lastaxis", choices=("auto", "yfft", "fft"), default="auto",
+                    help="force path of the headline step (for profiling the transform paths on their own): "
+                         "auto = the (y, z) correlation pass, yfft = y transform + direct z line correlation, "
+                         "fft = transforms on all three axes")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -514,8 +518,9 @@ def main():
     log(f"[bench] workload: LPS {args.size}^3 nodes in {args.fft}^3 FFT grid")
     wl = workloads.block_voids_dynamics(nb=args.size, nfft=args.fft)
     nodes = wl.nodes
-    r32 = run_dynamics(wl, torch.float32, args.steps, args.warmup, with_profile=True)
-    log(f"[bench] fp32 step {r32['s_per_step'] * 1e3:.3f} ms, force {r32['s_per_force'] * 1e3:.3f} ms")
+    r32 = run_dynamics(wl, torch.float32, args.steps, args.warmup, with_profile=True, lastaxis=args.lastaxis)
+    log(f"[bench] fp32 step {r32['s_per_step'] * 1e3:.3f} ms, force {r32['s_per_force'] * 1e3:.3f} ms"
+        + ("" if args.lastaxis == "auto" else f" (path {args.lastaxis})"))
     r64 = None
     if not args.no_fp64:
         r64 = run_dynamics(wl, torch.float64, args.steps, args.warmup, with_profile=True)
@@ -644,9 +649,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"3D LPS EC velocity-Verlet step, {args.size}^3 body nodes (8 seeded ellipsoidal "
                                f"voids) on a {args.fft}^3 FFT grid, delta=3dx, E=70GPa, nu=0.25",
-                   "body_nodes": nodes, "fft_grid": args.fft ** 3, "parallelism": "single GPU"},
+                   "body_nodes": nodes, "fft_grid": args.fft ** 3, "parallelism": "single GPU",
+                   "path": {"auto": "x transform + (y, z) correlation", "yfft": "x, y transforms + z line correlation",
+                            "fft": "transforms on all three axes"}[args.lastaxis]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom["name"]),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom["name"]) if args.lastaxis == "auto" else None,
                      "kernel": dom["name"], "kernel_avg_ms": dom["avg_ms"],
                      "kernel_bytes": dom["bytes_per_launch"]},
         "cpu_baseline": cpu,

@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdfcbm.so")
 HEADERS = ["pd_fft.hpp", "pd_ops.hpp", "pd_passes.hpp", "pd_plan.hpp", "pd_impl.hpp"]
 UNITS = [("pd_fcbm.hip", [])] + [
-    ("pd_inst.hip", ["-DPD_INST_T=%s" % t, "-DPD_INST_PART=%d" % part])
+    ("pd_inst.hip", ["-DPD_INST_T=%s" % t, "-DPD_INST_PART=%d" % part, "-DPD_INST_F32=%d" % (t == "float")])
     for t in ("float", "double") for part in range(6)]
 
 HIPCC_FLAGS = [

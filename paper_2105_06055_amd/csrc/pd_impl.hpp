@@ -1456,29 +1456,35 @@ static __global__ void k_cgm_start(float* __restrict__ p32, const double* __rest
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
         p32[k] = float(r[k]);
 }
-// x += a p32;  r -= a Ap32  (FP64 accumulation of the FP32 operator output);
-// partial |r|^2, a = num / den
-static __global__ void k_cgm_update(double* __restrict__ x, const float* __restrict__ p32, double* __restrict__ r,
+// x += a p32 (FP64 iterate);  r32 -= a Ap32 (formed in FP64, stored in
+// FP32: the recursively updated residual is replaced by the FP64 one before
+// its rounding accumulates); partial |r32|^2 in FP64, a = num / den
+static __global__ void k_cgm_update(double* __restrict__ x, const float* __restrict__ p32, float* __restrict__ r32,
                                     const float* __restrict__ Ap32, const double* __restrict__ num,
                                     const double* __restrict__ den, long n, double* __restrict__ part) {
     const double a = dev_ratio(num, den);
     double acc[1] = {0.0};
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
         x[k] += a * double(p32[k]);
-        const double rk = r[k] - a * double(Ap32[k]);
-        r[k] = rk;
-        acc[0] += rk * rk;
+        const float rk = float(double(r32[k]) - a * double(Ap32[k]));
+        r32[k] = rk;
+        acc[0] += double(rk) * double(rk);
     }
     ew_block_reduce<1>(acc, part);
 }
 // p32 = (float) (r + b p32), b = num / den
-static __global__ void k_cgm_dir(float* __restrict__ p32, const double* __restrict__ r,
+static __global__ void k_cgm_dir(float* __restrict__ p32, const float* __restrict__ r32,
                                  const double* __restrict__ num, const double* __restrict__ den,
                                  double* __restrict__ save, long n) {
     const double b = dev_ratio(num, den);
     keep_rho(save, num);
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
-        p32[k] = float(r[k] + b * double(p32[k]));
+        p32[k] = float(double(r32[k]) + b * double(p32[k]));
+}
+// r32 = (float) r (the FP64 residual of a replacement)
+static __global__ void k_to32(float* __restrict__ r32, const double* __restrict__ r, long n) {
+    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+        r32[k] = float(r[k]);
 }
 
 // Preconditioned CG directions: p = z + b p, b = num / den
@@ -1896,7 +1902,7 @@ pd_status cg_run(pd_plan p, TX* x_unused, T* xT, T* r, T* pp, T* Ap, double rr0,
 
 // Device memory a solve needs for its vectors (each one 256-byte aligned):
 // r and t in FP64, then FP64 p and Ap (plain and preconditioned FP64), z
-// (preconditioned FP64), or FP32 p and Ap (mixed) and z (mixed,
+// (preconditioned FP64), or FP32 p, Ap and r (mixed) and z (mixed,
 // preconditioned).
 inline size_t solve_vec_bytes(long n, size_t elem) { return ((size_t)n * elem + 255) & ~(size_t)255; }
 inline size_t solve_workspace_bytes(pd_plan p, int options) {
@@ -1904,7 +1910,7 @@ inline size_t solve_workspace_bytes(pd_plan p, int options) {
     const bool mixed = (options & PD_SOLVE_MIXED) != 0, pre = (options & PD_SOLVE_PRECOND) != 0;
     size_t tot = 2 * solve_vec_bytes(n, 8);
     if (!mixed) tot += (pre ? 3 : 2) * solve_vec_bytes(n, 8);
-    else tot += (pre ? 3 : 2) * solve_vec_bytes(n, 4);
+    else tot += (pre ? 4 : 3) * solve_vec_bytes(n, 4);
     return tot;
 }
 
@@ -1924,11 +1930,11 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
     const long n = p->nb * p->dim;
     pd_solve_info inf{};
     double *r = nullptr, *pp = nullptr, *Ap = nullptr, *t = nullptr, *z = nullptr;
-    float *p32 = nullptr, *Ap32 = nullptr, *z32 = nullptr;
+    float *p32 = nullptr, *Ap32 = nullptr, *z32 = nullptr, *r32 = nullptr;
     size_t ws_off = 0;
     auto cleanup = [&]() {
         if (ws) return;
-        void* bufs[] = {r, pp, Ap, t, z, p32, Ap32, z32};
+        void* bufs[] = {r, pp, Ap, t, z, p32, Ap32, z32, r32};
         for (void* q : bufs)
             if (q) (void)hipFree(q);
     };
@@ -2006,27 +2012,30 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
         inf.iters_fp64 = it;
     } else {
         // CG with the operator (and the preconditioner, if any) applied in
-        // FP32 (sub32 plan), with the iterate and residual updated and every
-        // inner product accumulated in FP64 and the direction kept in FP32
-        // (the precision the operator reads it in); the
-        // recursively updated residual is replaced by the FP64 residual
-        // chi_O (L x + b) whenever it has dropped by a factor 10 since the
-        // last replacement and at the end (residual replacement keeps the
-        // FP32 operator's errors from accumulating in r), so the returned
+        // FP32 (sub32 plan), with the iterate updated and every inner
+        // product accumulated in FP64, and the direction and the recursively
+        // updated residual kept in FP32 (the precision the operator reads
+        // the direction in; each residual update is formed in FP64).  The
+        // residual is replaced by the FP64 residual chi_O (L x + b) whenever
+        // it has dropped by a factor 10 since the last replacement and at
+        // the end (residual replacement keeps the FP32 operator's errors and
+        // the residual's rounding from accumulating), so the returned
         // iterate meets rtol in FP64.  The host sees |r|^2 one iteration
         // late, so a replacement follows the iteration queued behind the one
         // that triggered it.
         pd_plan q = p->sub32;
         SOLVE_TRY(vec(&p32, sizeof(float)));
         SOLVE_TRY(vec(&Ap32, sizeof(float)));
+        SOLVE_TRY(vec(&r32, sizeof(float)));
         if (pre) SOLVE_TRY(vec(&z32, sizeof(float)));
         double* dev = q->red;
         LagRead lag;
         SOLVE_TRY(lag.init(q));
+        hipLaunchKernelGGL(k_to32, dim3(nb), dim3(EW_THREADS), 0, st, r32, (const double*)r, n);
         // rho = r.z (preconditioned) or r.r; the direction starts from z or r
         if (pre) {
             if (rr > stop2) {
-                SOLVE_TRY((precond_apply<float, double, float>(q, r, z32, st)));   // q->red[0] = r.z
+                SOLVE_TRY((precond_apply<float, float, float>(q, r32, z32, st)));   // q->red[0] = r.z
                 inf.precond_applies += 1;
                 SOLVE_TRY(pdh::check(hipMemcpyAsync(dev + kRedRho, dev, sizeof(double), hipMemcpyDeviceToDevice, st)));
             }
@@ -2042,16 +2051,16 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
             double* rho = dev + kRedRho + (k & 1);
             double* rho_new = dev + kRedRho + ((k + 1) & 1);
             PD_TRY((lin_apply<float, 2>(q, p32, Ap32, nullptr, st)));   // q->red[0] = p32 . Ap32
-            hipLaunchKernelGGL(k_cgm_update, dim3(nb), dim3(EW_THREADS), 0, st, u, (const float*)p32, r,
+            hipLaunchKernelGGL(k_cgm_update, dim3(nb), dim3(EW_THREADS), 0, st, u, (const float*)p32, r32,
                                (const float*)Ap32, (const double*)rho, (const double*)dev, n, q->partials);
             PD_TRY(ew_finish<1>(q, nb, dev + kRedRR, st, lag.dslot(k)));
             PD_TRY(lag.post(k, dev + kRedRR, st));
             if (pre) {
-                PD_TRY((precond_apply<float, double, float>(q, r, z32, st)));   // q->red[0] = r.z
+                PD_TRY((precond_apply<float, float, float>(q, r32, z32, st)));   // q->red[0] = r.z
                 hipLaunchKernelGGL(k_pcgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, p32, (const float*)z32,
                                    (const double*)dev, (const double*)rho, rho_new, n);
             } else {
-                hipLaunchKernelGGL(k_cgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, p32, (const double*)r,
+                hipLaunchKernelGGL(k_cgm_dir, dim3(nb), dim3(EW_THREADS), 0, st, p32, (const float*)r32,
                                    (const double*)(dev + kRedRR), (const double*)rho, rho_new, n);
             }
             return pdh::check(hipGetLastError());
@@ -2070,6 +2079,7 @@ inline pd_status static_solve_impl(pd_plan p, const double* b, const double* w, 
             if (rr_lag <= stop2 || rr_lag <= 1e-2 * rr_rep) {
                 // residual replacement in FP64, after the queued iteration
                 SOLVE_TRY((lin_apply<double, 3>(p, u, r, b, st)));
+                hipLaunchKernelGGL(k_to32, dim3(nb), dim3(EW_THREADS), 0, st, r32, (const double*)r, n);
                 SOLVE_TRY(fetch_red(p, 1, st, v));
                 inf.applies_fp64 += 1;
                 inf.iters_fp64 += 1;
@@ -2216,6 +2226,7 @@ namespace pdi {
     extern template pd_status lin_apply<T, 2>(pd_plan, const T*, T*, const T*, hipStream_t);                      \
     extern template pd_status precond_apply<T, double, T>(pd_plan, const double*, T*, hipStream_t);
 PD_EXTERN(float)
+extern template pd_status precond_apply<float, float, float>(pd_plan, const float*, float*, hipStream_t);
 PD_EXTERN(double)
 #undef PD_EXTERN
 }  // namespace pdi

@@ -25,6 +25,9 @@ template pd_status cg_run<PD_INST_T, PD_INST_T>(pd_plan, PD_INST_T*, PD_INST_T*,
 template pd_status lin_apply<PD_INST_T, 3>(pd_plan, const PD_INST_T*, PD_INST_T*, const PD_INST_T*, hipStream_t);
 template pd_status lin_apply<PD_INST_T, 2>(pd_plan, const PD_INST_T*, PD_INST_T*, const PD_INST_T*, hipStream_t);
 template pd_status precond_apply<PD_INST_T, double, PD_INST_T>(pd_plan, const double*, PD_INST_T*, hipStream_t);
+#if PD_INST_F32
+template pd_status precond_apply<float, float, float>(pd_plan, const float*, float*, hipStream_t);
+#endif
 #elif PD_INST_PART == 4
 #define PD_YZ_DEF(T, M) template pd_status launch_yzconv<T, M>(pd_plan, const M&, int, int, hipStream_t);
 PD_YZ_LIST_A(PD_YZ_DEF, PD_INST_T)
