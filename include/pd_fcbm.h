@@ -75,8 +75,10 @@ typedef enum {
 
 typedef struct {
     int dim;              /* 2 or 3 */
-    int64_t fft_n[3];     /* FFT grid (x, y, z), powers of two: x in [16, 2048],
-                             y and z in [16, 1024]; fft_n[2] = 1 when dim == 2 */
+    int64_t fft_n[3];     /* FFT grid (x, y, z): y and z powers of two in [16, 1024];
+                             x in [16, 2048], a power of two or 2 R 2^p with
+                             R = 3, 5 or 9 and 2^p >= 8 (minimum padding, Sec.
+                             4.2.2); fft_n[2] = 1 when dim == 2 */
     int64_t body_n[3];    /* body box (x, y, z), >= 1; body_n[2] = 1 when dim == 2.
                              Requires fft_n[d] - body_n[d] >= ceil(delta/dx[d]) so
                              that no bond wraps around the periodic box (Sec. 4.2.2:
@@ -186,7 +188,14 @@ typedef struct {
  *   lambda <- lambda AND [W <= W_c]          (INTEGRITY with G0 > 0)
  *   F' <- L(u) + b   (W' <- W(u))
  *   v <- chi_O [v + dt/(2 rho) (F + F')]
- * When state->step == 0 the initial F (and W) are computed first.
+ * When state->step == 0 the initial F (and W) are computed first.  Between
+ * the steps of one call, PD_WEIGHT_NONE plans without energy_out keep the
+ * half-step velocity v + dt/(2 rho) F in state->v and leave state->F as it
+ * was (the same steps regrouped, so inner steps neither read nor write F);
+ * on return state->v and state->F hold v and F of the last step.  A call of
+ * n steps therefore equals n calls of one step up to rounding, not bit for
+ * bit; on an error return in the middle of such a call state->v may hold
+ * the half-step velocity.
  *   b [dim][body] body force density or NULL (zero); w [dim][body] values
  *   on the constrained components or NULL (zero); both time independent.
  *   energy_out HOST FP64 [nsteps][4] or NULL: kinetic, internal

@@ -55,9 +55,16 @@ class VerletRollout(torch.autograd.Function):
         b = None if b is None else b.detach().contiguous()
         ckpts = [(st["u"].clone(), st["v"].clone(), None)]
         k = max(1, int(checkpoint_every))
-        # one library call per segment (the call repeats the same step)
+        # one library call per segment (the call repeats the same step); on
+        # unweighted plans a multi-step call regroups its inner steps around
+        # the half-step velocity, so there the forward pass steps one call at
+        # a time, as the backward pass's recompute does, and the two
+        # trajectories agree bit for bit
+        per_step = plan.weight == "none"
         for k0 in range(0, nsteps, k):
-            plan.verlet(st, dt_, min(k, nsteps - k0), b=b)
+            n = min(k, nsteps - k0)
+            for _ in range(n if per_step else 1):
+                plan.verlet(st, dt_, 1 if per_step else n, b=b)
             if k0 + k < nsteps:
                 ckpts.append((st["u"].clone(), st["v"].clone(), st["F"].clone()))
         ctx.plan, ctx.dt, ctx.nsteps, ctx.k, ctx.b = plan, dt_, nsteps, k, b

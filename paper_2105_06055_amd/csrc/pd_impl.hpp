@@ -1610,8 +1610,12 @@ pd_status precond_apply(pd_plan p, const TR* r, TZ* z, hipStream_t st) {
     return p->dim == 2 ? go(std::integral_constant<int, 2>{}) : go(std::integral_constant<int, 3>{});
 }
 
+// One EC velocity-Verlet step.  vh_in / vh_out (unweighted plans, inside a
+// multi-step call): v holds the half-step velocity v + dt/(2 rho) F on entry /
+// is left holding it on exit, and F is then neither read nor written.
 template <class T, bool ENRED>
-pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, double* nanflag, hipStream_t st) {
+pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, double* nanflag, int vh_in, int vh_out,
+                     hipStream_t st) {
     const int D = p->dim;
     const T rho = T(p->kern.rho);
     const T c1 = dt / (T(2) * rho), c2 = dt * dt / (T(2) * rho);
@@ -1621,7 +1625,7 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, doubl
     if (p->kern.model == PD_LPS_LINEAR) {
         GenU<T, 3, WK_NONE, false, false, true> gA{};
         gA.c = ctx<T>(p);
-        gA.u = u; gA.v = v; gA.F = F; gA.w = w; gA.dt = dt; gA.c2 = c2;
+        gA.u = u; gA.v = v; gA.F = F; gA.w = w; gA.dt = dt; gA.c2 = c2; gA.vhalf = vh_in;
         FinTheta<T> fA{};
         fA.c = ctx<T>(p);
         fA.u = u;
@@ -1632,6 +1636,7 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, doubl
         fB.c = ctx<T>(p);
         fB.ka = T(p->ka); fB.u = u; fB.theta = reinterpret_cast<const T*>(p->theta);
         fB.v = v; fB.F = F; fB.b = b; fB.c1 = c1; fB.rho = rho; fB.nanflag = nanflag;
+        fB.vh_in = vh_in; fB.vh_out = vh_out;
         return run_lps<T>(p, gA, fA, mB, fB, st);
     }
     auto go = [&](auto Dc) -> pd_status {
@@ -1640,12 +1645,14 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, doubl
         if (wk == PD_WEIGHT_NONE) {
             GenU<T, DD, WK_NONE, false, false, true> gg{};
             gg.c = ctx<T>(p);
-            gg.u = u; gg.v = v; gg.F = F; gg.w = w; gg.dt = dt; gg.c2 = c2;
+            gg.u = u; gg.v = v; gg.F = F; gg.w = w; gg.dt = dt; gg.c2 = c2; gg.vhalf = vh_in;
             FinLin<T, DD, 1, ENRED, false> ff{};
             ff.c = ctx<T>(p);
             ff.u = u; ff.v = v; ff.F = F; ff.b = b; ff.c1 = c1; ff.rho = rho; ff.nanflag = nanflag;
+            ff.vh_in = vh_in; ff.vh_out = vh_out;
             return run_chain<T>(p, gg, MulBB<T, DD, false, false>{}, ff, st);
         }
+        if (vh_in || vh_out) return PD_EINVAL;   // the weighted steps keep (v, F)
         if constexpr (DD == 3) {
             return PD_EUNSUPPORTED;
         } else {
@@ -1719,9 +1726,17 @@ pd_status verlet_impl(pd_plan p, pd_state* S, const T* b, const T* w, double dt,
             HIP_TRY(hipGetLastError());
         }
     }
+    // Between the steps of one call, unweighted plans carry the half-step
+    // velocity vh = v + dt/(2 rho) F in v instead of (v, F): the position
+    // update is u + dt vh and the velocity update vh' = vh + dt/rho F'
+    // (the same Verlet step, Eq. 83-84, regrouped), so the inner steps read
+    // and write no F; the first step reads (v, F) and the last writes them.
+    // Steps with energy output keep (v, F) throughout.
+    const bool kdk = p->kern.weight == PD_WEIGHT_NONE && !energy;
     for (int k = 0; k < nsteps; ++k) {
+        const int vh_in = (kdk && k > 0) ? 1 : 0, vh_out = (kdk && k + 1 < nsteps) ? 1 : 0;
         if (energy) {
-            PD_TRY((verlet_one<T, true>(p, S, b, w, T(dt), flag, st)));
+            PD_TRY((verlet_one<T, true>(p, S, b, w, T(dt), flag, 0, 0, st)));
             double r[4];
             PD_TRY(fetch_red(p, 4, st, r));
             const double dV = p->dV;
@@ -1732,7 +1747,7 @@ pd_status verlet_impl(pd_plan p, pd_state* S, const T* b, const T* w, double dt,
             for (int q = 0; q < 4; ++q)
                 if (!std::isfinite(energy[4 * k + q])) return PD_ENUMERIC;
         } else {
-            PD_TRY((verlet_one<T, false>(p, S, b, w, T(dt), flag, st)));
+            PD_TRY((verlet_one<T, false>(p, S, b, w, T(dt), flag, vh_in, vh_out, st)));
         }
         S->step += 1;
     }

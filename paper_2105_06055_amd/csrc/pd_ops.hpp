@@ -149,6 +149,9 @@ struct GenU {
     const T* v; const T* F; const T* w; const T* W;
     T dt, c2, Wc;
     int fail;                  // VV: apply the failure rule
+    // VV: v holds the half-step velocity v + dt/(2 rho) F (a step inside a
+    // multi-step call), so the position update needs no F
+    int vhalf;
     // algorithmic bytes moved per body node (reads + writes)
     __host__ double nbytes() const {
         const double t = sizeof(T);
@@ -156,7 +159,7 @@ struct GenU {
         if (WK == WK_LAMBDA) b += 1;
         if (WK == WK_SCALE) b += t;
         if (VV) {
-            b += D * (3 * t + 1) + (w ? D * t : 0.0);
+            b += D * ((vhalf ? 2 : 3) * t + 1) + (w ? D * t : 0.0);
             if (WK == WK_LAMBDA && fail) b += t + 1;
         }
         return b;
@@ -175,7 +178,10 @@ struct GenU {
             L.u[d] = ldf(u + k, i);
             if constexpr (VV) {
                 L.v[d] = ldf(v + k, i);
-                L.F[d] = ldf(F + k, i);
+                // no branch around a load (it would hold back the loads of the
+                // node group): with vhalf the F slot re-reads v (a cache hit)
+                // and is not used
+                L.F[d] = ldf((vhalf ? v : F) + k, i);
                 L.w[d] = ldf((w ? w : u) + k, i);
                 L.o[d] = ldf(c.chiO + k, i);
             }
@@ -192,7 +198,9 @@ struct GenU {
         for (int d = 0; d < D; ++d) {
             T x = L.u[d];
             if constexpr (VV) {
-                x = L.o[d] ? x + dt * L.v[d] + c2 * L.F[d] : (w ? L.w[d] : T(0));
+                const T Fs = vhalf ? T(0) : L.F[d];
+                const T xn = x + dt * L.v[d] + c2 * Fs;
+                x = L.o[d] ? xn : (w ? L.w[d] : T(0));
                 stf(u + d * c.nb, i, x);
             }
             ud[d] = x;
@@ -1028,11 +1036,15 @@ struct FinLin {
     T* L; T* v; T* F; const T* b;
     T c1, rho;
     double* nanflag;   // MODE 1: set to 1 on a non-finite F' or v (null: no check)
+    // MODE 1, steps inside a multi-step call: v holds the half-step velocity
+    // vh = v + c1 F on entry (vh_in; F is not read) and receives
+    // vh' = v' + c1 F' on exit (vh_out; F is not written)
+    int vh_in, vh_out;
     __host__ double nbytes() const {
         const double t = sizeof(T);
         double r = D * t + 1 + nsym(D) * t * c.edge_frac + (LPS ? t + D * t * c.edge_frac : 0.0);
         if (MODE == 0) r += D * t;
-        else if (MODE == 1) r += D * (4 * t + 1) + (b ? D * t : 0.0);
+        else if (MODE == 1) r += D * ((2 + (vh_in ? 0 : 1) + (vh_out ? 0 : 1)) * t + 1) + (b ? D * t : 0.0);
         else if (MODE == 2) r += D * (t + 1);
         else r += D * (2 * t + 1);
         return r;
@@ -1068,7 +1080,7 @@ struct FinLin {
             if constexpr (HAS_O) Q.o[d] = ldf(c.chiO + k, i);
             if constexpr (MODE == 1) {
                 Q.v[d] = ldf(v + k, i);
-                Q.F[d] = ldf(F + k, i);
+                Q.F[d] = ldf((vh_in ? v : F) + k, i);   // with vh_in: a cache hit, unused
             }
             if constexpr (MODE == 3) Q.b[d] = ldf(b + k, i);
         }
@@ -1095,9 +1107,15 @@ struct FinLin {
             } else if constexpr (MODE == 1) {
                 const T bk = b ? Q.b[a] : T(0);
                 T Fn = La + bk;
-                T vn = Q.o[a] ? Q.v[a] + c1 * (Q.F[a] + Fn) : T(0);
-                stf(v + k, i, vn);
-                stf(F + k, i, Fn);
+                const T Fo = vh_in ? T(0) : Q.F[a];
+                const T vf = Q.v[a] + c1 * (Fo + Fn);
+                T vn = Q.o[a] ? vf : T(0);
+                if (vh_out) {
+                    stf(v + k, i, Q.o[a] ? vn + c1 * Fn : T(0));
+                } else {
+                    stf(v + k, i, vn);
+                    stf(F + k, i, Fn);
+                }
                 flag_nonfinite(nanflag, Fn, vn);
                 if constexpr (ENRED) {
                     red[0] += 0.5 * double(rho) * double(vn) * double(vn);
