@@ -181,7 +181,14 @@ typedef struct {
     uint8_t* lambda;   /* [body] integrity (INTEGRITY plans), else NULL */
     void* s;           /* [body] micromodulus scale (SCALE plans), else NULL */
     int64_t step;      /* steps taken; 0 means F (and W) are not yet valid */
+    int32_t flags;     /* PD_STATE_* bits (0 for the default) */
 } pd_state;
+
+/* pd_state.flags: every step of a pd_verlet_step call reads and writes
+ * (v, F), so that a call of n steps equals n calls of one step bit for bit
+ * (for callers that replay a trajectory step by step, such as checkpointed
+ * adjoints). */
+#define PD_STATE_EXACT_STEPS 1
 
 /* Advance nsteps embedded-constraint velocity-Verlet steps (Eq. 67, 83-84):
  *   u <- chi_O [u + dt v + dt^2/(2 rho) F] + (1 - chi_O) w
@@ -189,13 +196,13 @@ typedef struct {
  *   F' <- L(u) + b   (W' <- W(u))
  *   v <- chi_O [v + dt/(2 rho) (F + F')]
  * When state->step == 0 the initial F (and W) are computed first.  Between
- * the steps of one call, PD_WEIGHT_NONE plans without energy_out keep the
- * half-step velocity v + dt/(2 rho) F in state->v and leave state->F as it
- * was (the same steps regrouped, so inner steps neither read nor write F);
- * on return state->v and state->F hold v and F of the last step.  A call of
- * n steps therefore equals n calls of one step up to rounding, not bit for
- * bit; on an error return in the middle of such a call state->v may hold
- * the half-step velocity.
+ * the steps of one call without energy_out and without PD_STATE_EXACT_STEPS
+ * the half-step velocity v + dt/(2 rho) F is kept in state->v and state->F
+ * is left as it was (the same steps regrouped, so inner steps neither read
+ * nor write F); on return state->v and state->F hold v and F of the last
+ * step.  A call of n steps then equals n calls of one step up to rounding,
+ * not bit for bit; on an error return in the middle of such a call
+ * state->v may hold the half-step velocity.
  *   b [dim][body] body force density or NULL (zero); w [dim][body] values
  *   on the constrained components or NULL (zero); both time independent.
  *   energy_out HOST FP64 [nsteps][4] or NULL: kinetic, internal

@@ -55,16 +55,11 @@ class VerletRollout(torch.autograd.Function):
         b = None if b is None else b.detach().contiguous()
         ckpts = [(st["u"].clone(), st["v"].clone(), None)]
         k = max(1, int(checkpoint_every))
-        # one library call per segment (the call repeats the same step); on
-        # unweighted plans a multi-step call regroups its inner steps around
-        # the half-step velocity, so there the forward pass steps one call at
-        # a time, as the backward pass's recompute does, and the two
-        # trajectories agree bit for bit
-        per_step = plan.weight == "none"
+        # one library call per segment, its steps exactly those of the
+        # backward pass's one-step recompute (no regrouping around the
+        # half-step velocity), so the two trajectories agree bit for bit
         for k0 in range(0, nsteps, k):
-            n = min(k, nsteps - k0)
-            for _ in range(n if per_step else 1):
-                plan.verlet(st, dt_, 1 if per_step else n, b=b)
+            plan.verlet(st, dt_, min(k, nsteps - k0), b=b, exact_steps=True)
             if k0 + k < nsteps:
                 ckpts.append((st["u"].clone(), st["v"].clone(), st["F"].clone()))
         ctx.plan, ctx.dt, ctx.nsteps, ctx.k, ctx.b = plan, dt_, nsteps, k, b

@@ -57,7 +57,10 @@ class PlanInfo(C.Structure):
 
 class State(C.Structure):
     _fields_ = [("u", C.c_void_p), ("v", C.c_void_p), ("F", C.c_void_p), ("W", C.c_void_p),
-                ("lam", C.c_void_p), ("s", C.c_void_p), ("step", C.c_int64)]
+                ("lam", C.c_void_p), ("s", C.c_void_p), ("step", C.c_int64), ("flags", C.c_int32)]
+
+
+STATE_EXACT_STEPS = 1
 
 
 class SolveInfo(C.Structure):
@@ -230,8 +233,10 @@ class Plan:
                "pd_force_adjoint")
         return (ub, wb) if want_weight_bar else ub
 
-    def verlet(self, state, dt, nsteps, b=None, w=None, energy=False):
-        """Advance ``state`` (dict with u, v, F and optionally W, lam, s, step)."""
+    def verlet(self, state, dt, nsteps, b=None, w=None, energy=False, exact_steps=False):
+        """Advance ``state`` (dict with u, v, F and optionally W, lam, s, step).
+        exact_steps: every step reads and writes (v, F), so the call equals
+        nsteps one-step calls bit for bit (PD_STATE_EXACT_STEPS)."""
         for k in ("u", "v", "F"):
             self._vec(state[k], k)
         b = self._vec(b, "b")
@@ -240,7 +245,7 @@ class Plan:
                    W=None if state.get("W") is None else self._sca(state["W"], "W").data_ptr(),
                    lam=None if state.get("lam") is None else self._sca(state["lam"], "lam", torch.uint8).data_ptr(),
                    s=None if state.get("s") is None else self._sca(state["s"], "s").data_ptr(),
-                   step=int(state.get("step", 0)))
+                   step=int(state.get("step", 0)), flags=STATE_EXACT_STEPS if exact_steps else 0)
         en = (C.c_double * (4 * nsteps))() if energy else None
         _check(lib().pd_verlet_step(self._h, C.byref(st), _ptr(b), _ptr(w), float(dt), int(nsteps),
                                     en, _stream()), "pd_verlet_step")

@@ -1610,9 +1610,9 @@ pd_status precond_apply(pd_plan p, const TR* r, TZ* z, hipStream_t st) {
     return p->dim == 2 ? go(std::integral_constant<int, 2>{}) : go(std::integral_constant<int, 3>{});
 }
 
-// One EC velocity-Verlet step.  vh_in / vh_out (unweighted plans, inside a
-// multi-step call): v holds the half-step velocity v + dt/(2 rho) F on entry /
-// is left holding it on exit, and F is then neither read nor written.
+// One EC velocity-Verlet step.  vh_in / vh_out (inside a multi-step call): v
+// holds the half-step velocity v + dt/(2 rho) F on entry / is left holding
+// it on exit, and F is then neither read nor written.
 template <class T, bool ENRED>
 pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, double* nanflag, int vh_in, int vh_out,
                      hipStream_t st) {
@@ -1652,7 +1652,6 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, doubl
             ff.vh_in = vh_in; ff.vh_out = vh_out;
             return run_chain<T>(p, gg, MulBB<T, DD, false, false>{}, ff, st);
         }
-        if (vh_in || vh_out) return PD_EINVAL;   // the weighted steps keep (v, F)
         if constexpr (DD == 3) {
             return PD_EUNSUPPORTED;
         } else {
@@ -1661,13 +1660,14 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, doubl
             constexpr bool E = decltype(Ec)::value;
             GenU<T, DD, WK, true, E, true> gg{};
             gg.c = ctx<T>(p);
-            gg.u = u; gg.v = v; gg.F = F; gg.w = w; gg.dt = dt; gg.c2 = c2;
+            gg.u = u; gg.v = v; gg.F = F; gg.w = w; gg.dt = dt; gg.c2 = c2; gg.vhalf = vh_in;
             gg.lam_in = S->lambda; gg.lam_out = S->lambda; gg.s = reinterpret_cast<const T*>(S->s);
             gg.W = reinterpret_cast<const T*>(S->W); gg.Wc = T(p->Wc); gg.fail = (S->W && p->Wc > 0) ? 1 : 0;
             FinBB<T, DD, WK, true, E, true, ENRED> ff{};
             ff.c = ctx<T>(p);
             ff.u = u; ff.lam = S->lambda; ff.s = reinterpret_cast<const T*>(S->s); ff.Wout = reinterpret_cast<T*>(S->W);
             ff.v = v; ff.F = F; ff.b = b; ff.c1 = c1; ff.rho = rho; ff.nanflag = nanflag;
+            ff.vh_in = vh_in; ff.vh_out = vh_out;
             return run_chain<T>(p, gg, MulBB<T, DD, true, E>{}, ff, st);
         };
         if (wk == PD_WEIGHT_INTEGRITY) {
@@ -1726,13 +1726,14 @@ pd_status verlet_impl(pd_plan p, pd_state* S, const T* b, const T* w, double dt,
             HIP_TRY(hipGetLastError());
         }
     }
-    // Between the steps of one call, unweighted plans carry the half-step
-    // velocity vh = v + dt/(2 rho) F in v instead of (v, F): the position
+    // Between the steps of one call the half-step velocity
+    // vh = v + dt/(2 rho) F is carried in v instead of (v, F): the position
     // update is u + dt vh and the velocity update vh' = vh + dt/rho F'
     // (the same Verlet step, Eq. 83-84, regrouped), so the inner steps read
     // and write no F; the first step reads (v, F) and the last writes them.
-    // Steps with energy output keep (v, F) throughout.
-    const bool kdk = p->kern.weight == PD_WEIGHT_NONE && !energy;
+    // Steps with energy output, and calls with PD_STATE_EXACT_STEPS, keep
+    // (v, F) throughout.
+    const bool kdk = !energy && !(S->flags & PD_STATE_EXACT_STEPS);
     for (int k = 0; k < nsteps; ++k) {
         const int vh_in = (kdk && k > 0) ? 1 : 0, vh_out = (kdk && k + 1 < nsteps) ? 1 : 0;
         if (energy) {

@@ -884,12 +884,13 @@ struct FinBB {
     T* v; T* F; const T* b;   // VV
     T c1, rho;
     double* nanflag;          // VV: set to 1 on a non-finite F' or v (null: no check)
+    int vh_in, vh_out;        // VV: half-step velocity in / out (as FinLin)
     __host__ double nbytes() const {
         const double t = sizeof(T);
         double r = D * t + 1 + (WK == WK_LAMBDA ? 1.0 : 0.0) + (WK == WK_SCALE ? t : 0.0);
         if (!WPHI) r += nsym(D) * t * c.edge_frac;
         if (ENERGY) r += t;
-        if (VV) r += D * (4 * t + 1) + (b ? D * t : 0.0);
+        if (VV) r += D * ((2 + (vh_in ? 0 : 1) + (vh_out ? 0 : 1)) * t + 1) + (b ? D * t : 0.0);
         else r += D * t;
         return r;
     }
@@ -910,7 +911,7 @@ struct FinBB {
             for (int d = 0; d < D; ++d) {
                 const long k = d * c.nb;
                 Q.v[d] = ldf(v + k, i);
-                Q.F[d] = ldf(F + k, i);
+                Q.F[d] = ldf((vh_in ? v : F) + k, i);   // with vh_in: a cache hit, unused
                 Q.o[d] = ldf(c.chiO + k, i);
             }
             if (b) {   // kernel-uniform
@@ -953,9 +954,14 @@ struct FinBB {
                 const long k = a * c.nb;
                 const T bk = b ? Q.b[a] : T(0);
                 T Fn = Li[a] + bk;
-                T vn = Q.o[a] ? Q.v[a] + c1 * (Q.F[a] + Fn) : T(0);
-                stf(v + k, i, vn);
-                stf(F + k, i, Fn);
+                const T Fo = vh_in ? T(0) : Q.F[a];
+                T vn = Q.o[a] ? Q.v[a] + c1 * (Fo + Fn) : T(0);
+                if (vh_out) {
+                    stf(v + k, i, Q.o[a] ? vn + c1 * Fn : T(0));
+                } else {
+                    stf(v + k, i, vn);
+                    stf(F + k, i, Fn);
+                }
                 flag_nonfinite(nanflag, Fn, vn);
                 if constexpr (ENRED) {
                     red[0] += 0.5 * double(rho) * double(vn) * double(vn);
