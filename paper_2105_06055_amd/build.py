@@ -2,8 +2,8 @@
 
 Called by ``__graft_entry__.build()``; also runnable as
 ``python -m paper_2105_06055_amd.build``.  The C entry points (pd_fcbm.hip)
-and twelve instantiation units of the per-dtype implementation (pd_inst.hip
-with PD_INST_T = float / double and PD_INST_PART = 0 .. 5) compile in
+and fourteen instantiation units of the per-dtype implementation (pd_inst.hip
+with PD_INST_T = float / double and PD_INST_PART = 0 .. 6) compile in
 parallel to objects, which are linked into the library, written in-tree next
 to this file so it travels with the source tree.
 """
@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libpdfcbm.so")
 HEADERS = ["pd_fft.hpp", "pd_ops.hpp", "pd_passes.hpp", "pd_plan.hpp", "pd_impl.hpp"]
 UNITS = [("pd_fcbm.hip", [])] + [
     ("pd_inst.hip", ["-DPD_INST_T=%s" % t, "-DPD_INST_PART=%d" % part, "-DPD_INST_F32=%d" % (t == "float")])
-    for t in ("float", "double") for part in range(6)]
+    for t in ("float", "double") for part in range(7)]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -225,7 +225,7 @@ template <class T>
 int rows_per_block(pd_plan p) {
     const Geo& g = p->geo;
     const int Tc = g.Nc / 8;
-    int Lt = xrows<T>();
+    int Lt = g.rad != 1 ? xrows_mixed<T>() : xrows<T>();
     while (Lt > 1 && Tc * Lt > 512) Lt >>= 1;
     // few rows (2D plates, small blocks): fewer rows per block, down to two
     // (16-byte runs in the transposed stores), until the grid has a block for
@@ -312,7 +312,7 @@ int x_mixed_lg(pd_plan p) {
     const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
     auto fits = [&](int R, int lgM) {
         const int rn = R == 3 ? 11 : (R == 5 ? 13 : 15);   // x_rn of the specialisation
-        return g.rad == R && g.lgM == lgM && Tc * Lt == ((R << lgM) / 8) * xrows<T>() &&
+        return g.rad == R && g.lgM == lgM && Tc * Lt == ((R << lgM) / 8) * xrows_mixed<T>() &&
                8 * g.b1 <= rn * g.Nc;
     };
     if (fits(3, 6)) return mix_lg(3, 6);
@@ -442,10 +442,29 @@ template <class T, class M, int MT>
 constexpr bool yz_fits() {
     return M::NOUT * (2 * MT + 1) * 2 * (int)(sizeof(T) / 4) <= 128;
 }
+// Outputs O0 .. O1-1 of a multiplier: a (y, z) pass holds the accumulators
+// of all its outputs in registers, so a chain with many outputs (the 3D
+// nonlinear model's 13) runs the pass once per group of outputs, each
+// reading all the inputs.
+template <class M, int O0, int O1>
+struct MulOutRange {
+    static constexpr int NIN = M::NIN, NOUT = O1 - O0, C0 = M::C0, NC = M::NC;
+    static constexpr bool RT_ODD = M::RT_ODD;
+    static constexpr uint32_t ODD = M::ODD;
+    M m;
+    __device__ __forceinline__ auto ka_value() const { return m.ka_value(); }
+    __host__ __device__ static constexpr int par3(int c) { return M::par3(c); }
+    __host__ __device__ static constexpr DTerm dterm(int O, int J) { return M::dterm(O0 + O, J); }
+};
+template <class T, class M>
+struct is_nbb3_range : std::false_type {};
+template <class T, int O0, int O1>
+struct is_nbb3_range<T, MulOutRange<MulNBB<T, 3>, O0, O1>> : std::true_type {};
+
 template <class T, class M>
 constexpr bool yz_capable() {
     return std::is_same<M, MulLPSA<T>>::value || std::is_same<M, MulLPSB<T>>::value ||
-           std::is_same<M, MulBB<T, 3, false, false>>::value;
+           std::is_same<M, MulBB<T, 3, false, false>>::value || is_nbb3_range<T, M>::value;
 }
 
 template <class T, class M, int MT, int YT>
@@ -513,6 +532,31 @@ PD_YZ_LIST_A(PD_YZ_DECL, float)
 PD_YZ_LIST_A(PD_YZ_DECL, double)
 PD_YZ_LIST_B(PD_YZ_DECL, float)
 PD_YZ_LIST_B(PD_YZ_DECL, double)
+#endif
+
+// The 3D nonlinear chain's (y, z) pass: the 13 outputs in groups of 7 (FP32)
+// or 3 (FP64), whose accumulators fit the registers of one pass; inputs in
+// SA slots [0, 13), outputs to [out_off, out_off + 13).  Instantiated in its
+// own unit (pd_inst.hip, part 6).
+template <class T, int O0, int O1> using YzNBB = MulOutRange<MulNBB<T, 3>, O0, O1>;
+template <class T>
+constexpr int nbb_yz_group() { return sizeof(T) == 4 ? 7 : 3; }
+template <class T, int O0>
+pd_status nbb_yz_from(pd_plan p, int out_off, hipStream_t st) {
+    constexpr int NO = MulNBB<T, 3>::NOUT;
+    if constexpr (O0 >= NO) {
+        return PD_OK;
+    } else {
+        constexpr int O1 = (O0 + nbb_yz_group<T>() < NO) ? O0 + nbb_yz_group<T>() : NO;
+        PD_TRY((launch_yzconv<T, YzNBB<T, O0, O1>>(p, YzNBB<T, O0, O1>{}, 0, out_off + O0, st)));
+        return nbb_yz_from<T, O1>(p, out_off, st);
+    }
+}
+template <class T>
+pd_status nbb_yz(pd_plan p, int out_off, hipStream_t st) { return nbb_yz_from<T, 0>(p, out_off, st); }
+#if !defined(PD_INST_PART) || PD_INST_PART != 6
+extern template pd_status nbb_yz<float>(pd_plan, int, hipStream_t);
+extern template pd_status nbb_yz<double>(pd_plan, int, hipStream_t);
 #endif
 
 // Whether a chain takes the (y, z) direct pass: 3D plan tables, the default
@@ -1026,9 +1070,14 @@ pd_status plan_alloc(pd_plan p, hipStream_t st, const uint8_t* chiB_h, const uin
         capA = std::max(capA, D + 1 + nsym(D));
     }
     if (p->kern.model == PD_BB_NONLINEAR) {
-        // 8 inputs and 8 outputs in 2D, 13 and 13 in 3D (y transform path)
+        // 8 inputs and 8 outputs in 2D, 13 and 13 in 3D (the (y, z) pass
+        // keeps the inputs and writes the outputs after them; the y
+        // transform path works in place)
         capA = std::max(capA, 2 * D + 1 + nsym(D));
-        if (D == 3) capB = std::max(capB, 2 * D + 1 + nsym(D));
+        if (D == 3) {
+            capA = std::max(capA, 2 * (2 * D + 1 + nsym(D)));
+            capB = std::max(capB, 2 * D + 1 + nsym(D));
+        }
     }
     p->saf_cap = capA;
     p->sbf_cap = std::max(capB, capC);
@@ -1319,6 +1368,16 @@ pd_status force_impl(pd_plan p, const T* u, const void* weight, T* L, T* W, hipS
             ff.c = ctx<T>(p);
             ff.u = u;
             ff.L = L;
+            if constexpr (DD == 3) {
+                // x transform, the (y, z) pass in output groups, inverse x
+                // transform (the y-transform path otherwise)
+                constexpr int NI = MulNBB<T, 3>::NIN, NO = MulNBB<T, 3>::NOUT;
+                if (use_yz<T, YzNBB<T, 0, nbb_yz_group<T>()>>(p) && p->saf_cap >= NI + NO) {
+                    PD_TRY(launch_xfwd<T>(p, gg, SAp<T>(p), st));
+                    PD_TRY(nbb_yz<T>(p, NI, st));
+                    return launch_xinv<T>(p, ff, SAp<T>(p) + (long)NI * p->geo.saf, st);
+                }
+            }
             return run_chain<T>(p, gg, MulNBB<T, DD>{}, ff, st);
         };
         return p->dim == 2 ? nbb(std::integral_constant<int, 2>{}) : nbb(std::integral_constant<int, 3>{});

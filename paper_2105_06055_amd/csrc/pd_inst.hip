@@ -1,6 +1,6 @@
 // pd_inst.hip -- explicit instantiation of the per-dtype implementation
 // (PD_INST_T = float or double; PD_INST_PART selects a share of it: 0 .. 3
-// the entry-point implementations, 4 and 5 the (y, z) pass kernels), so that
+// the entry-point implementations, 4 .. 6 the (y, z) pass kernels), so that
 // the library's device code compiles in parallel units.
 #include "pd_impl.hpp"
 
@@ -8,7 +8,7 @@
 #error "PD_INST_T must be defined (float or double)"
 #endif
 #ifndef PD_INST_PART
-#error "PD_INST_PART must be defined (0 .. 5)"
+#error "PD_INST_PART must be defined (0 .. 6)"
 #endif
 
 namespace pdi {
@@ -34,6 +34,8 @@ PD_YZ_LIST_A(PD_YZ_DEF, PD_INST_T)
 #elif PD_INST_PART == 5
 #define PD_YZ_DEF(T, M) template pd_status launch_yzconv<T, M>(pd_plan, const M&, int, int, hipStream_t);
 PD_YZ_LIST_B(PD_YZ_DEF, PD_INST_T)
+#elif PD_INST_PART == 6
+template pd_status nbb_yz<PD_INST_T>(pd_plan, int, hipStream_t);
 #else
 template pd_status plan_alloc<PD_INST_T>(pd_plan, hipStream_t, const uint8_t*, const uint8_t*);
 template pd_status build_device_tables<PD_INST_T>(pd_plan, const std::vector<Bond>&, hipStream_t);

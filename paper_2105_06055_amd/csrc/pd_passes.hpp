@@ -41,6 +41,10 @@ __host__ __device__ constexpr int line_pitch(int N) { return (fft_lds_len(N) + 1
 // the transposed spectra accesses).
 template <class T>
 __host__ __device__ constexpr int xrows() { return sizeof(T) == 4 ? 16 : 8; }
+// Rows per block of the mixed-radix x passes: 8, which ran the 256^3 step on
+// 384- and 320-point x grids faster than 16 or 4 rows.
+template <class T>
+__host__ __device__ constexpr int xrows_mixed() { return 8; }
 
 // Body nodes whose loads the x passes issue together (see k_xfwd): four,
 // and two in the FP64 c2r pass (the epilogues' loads of four FP64 nodes do
@@ -135,7 +139,7 @@ __host__ __device__ constexpr int x_rn() {
 template <class T, int LG>
 __host__ __device__ constexpr int x_block_fixed() {
     if constexpr (LG > 0) return ((1 << LG) / 8) * xrows<T>();
-    else if constexpr (LG < -1) return ((mix_R<LG>() << mix_lgM<LG>()) / 8) * xrows<T>();
+    else if constexpr (LG < -1) return ((mix_R<LG>() << mix_lgM<LG>()) / 8) * xrows_mixed<T>();
     else return 0;
 }
 
@@ -956,7 +960,9 @@ __device__ __forceinline__ void yz_term(cx<T>& q, const T* __restrict__ tk, cons
 template <class T, class M, int MT, int YT>
 __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const T* __restrict__ taps) {
     constexpr int NI = M::NIN, NO = M::NOUT, R = 2 * MT + 1, W = YT + 2 * MT, NU = yz_ntap(MT);
-    constexpr bool YZ_GROUP = sizeof(T) == 4;
+    // FP32 sums the terms of all inputs at once (their neighbour sums held
+    // together) when there are few inputs; otherwise one input at a time
+    constexpr bool YZ_GROUP = sizeof(T) == 4 && NI <= 4;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     lds_ptr<cx<T>> lds = as_lds(reinterpret_cast<cx<T>*>(smem_raw));
     // block -> (kx, y tile, z chunk): consecutive chunks of one (kx, tile) on one XCD
@@ -999,7 +1005,9 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
     // PF register sets of prefetched inputs (planes zi+1 .. zi+PF in flight):
     // four for the light dilatation-type passes in FP64 (NI * NO <= 4), else
     // two (in FP32 the extra registers cost more occupancy than they gain)
-    constexpr int PF = (sizeof(T) == 8 && NI * NO <= 4 && RR % 4 == 0) ? 4 : 2;
+    // (one set for chains with many inputs, whose sets would crowd out the
+    // accumulators)
+    constexpr int PF = NI > 4 ? 1 : ((sizeof(T) == 8 && NI * NO <= 4 && RR % 4 == 0) ? 4 : 2);
     cx<T> nv[PF][NI], nh[PF][NI];   // row y, halo row yh
 #pragma unroll
     for (int k = 0; k < PF; ++k)

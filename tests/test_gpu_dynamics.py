@@ -113,6 +113,7 @@ def test_clamped_layer_and_body_force(orc):
     o = orc.verlet(g, mdl, chi, chiO, u0, v0, 2e-8, 40, b=b, w=wv)
     assert _rel(st["u"].cpu().numpy(), o["u"]) <= 1e-11
     assert _rel(st["v"].cpu().numpy(), o["v"]) <= 1e-11
+    assert _rel(st["F"].cpu().numpy(), o["F"]) <= 1e-11
     assert np.array_equal(st["u"].cpu().numpy()[:, :3], wv[:, :3])
     plan.close()
 
@@ -156,6 +157,41 @@ def test_fracture_subcase_damage_bit_exact(orc):
     d = plan.damage_index(st["lam"]).cpu().numpy()
     do, _ = orc.damage_index(g, w.chiB, o["lam"])
     assert np.array_equal(d, do)
+    plan.close()
+
+
+@pytest.mark.parametrize("case", ["lps", "integrity"])
+def test_regrouped_steps_against_single_steps(case):
+    """Inside one call the steps carry the half-step velocity v + dt/(2 rho) F
+    instead of (v, F): after 30 steps in one call u, v, F (and lambda, W) agree
+    with 30 one-step calls to FP64 rounding; with exact_steps
+    (PD_STATE_EXACT_STEPS) the call equals the one-step calls bit for bit."""
+    from paper_2105_06055_amd import binding
+    dtype, n = torch.float64, 30
+    if case == "lps":
+        w = wl.block_voids_dynamics(nb=24, nfft=32, nvoids=3, steps=n, nu=0.3)
+        plan = binding.Plan.from_workload(w, dtype=dtype)
+        mk = lambda: _state(w, dtype)
+        b = None
+        keys = ("u", "v", "F")
+    else:
+        w = wl.notched_plate_fracture(nx=100, ny=40, fft=(64, 128), steps=n, sigma=12e6)
+        plan = binding.Plan.from_workload(w, dtype=dtype, weight="integrity")
+        mk = lambda: _state(w, dtype, lam=w.lam0, W=True)
+        b = _dev(w.b, dtype)
+        keys = ("u", "v", "F", "W")
+    one = mk()
+    for _ in range(n):
+        plan.verlet(one, w.dt, 1, b=b)
+    grouped, exact = mk(), mk()
+    plan.verlet(grouped, w.dt, n, b=b)
+    plan.verlet(exact, w.dt, n, b=b, exact_steps=True)
+    for k in keys:
+        a, g_, e = (x[k].cpu().numpy() for x in (one, grouped, exact))
+        assert np.array_equal(a, e), k
+        assert _rel(g_, a) <= 1e-12, (k, _rel(g_, a))
+    if case == "integrity":
+        assert torch.equal(one["lam"], exact["lam"]) and torch.equal(one["lam"], grouped["lam"])
     plan.close()
 
 

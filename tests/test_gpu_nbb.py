@@ -161,6 +161,31 @@ def test_nbb3d_masked(orc, dtype, body, fft, m, amp):
 
 
 @pytest.mark.parametrize("dtype", DT)
+@pytest.mark.parametrize("m", [2, 3])
+def test_nbb3d_yz_pass_against_y_transform_path(orc, dtype, m):
+    """The 3D chain's default (y, z) pass (13 outputs in groups, each group
+    reading all 13 inputs) on a body with two y-tiles of 256 rows and ragged
+    z-chunks, against the y-transform path element by element and against
+    the oracle on the whole field."""
+    body, fft, dx = (23, 300, 9), (32, 512, 16), 1e-3
+    chi = wl.random_mask(body, 61)
+    u = wl.random_field((3,) + body, 62, 0.1 * dx)
+    plan = _plan(fft, body, dx, m, chi, dtype)
+    ud = _dev(u, dtype)
+    La = plan.force(ud).cpu().numpy()
+    plan.set_lastaxis("yfft")
+    Ly = plan.force(ud).cpu().numpy()
+    plan.set_lastaxis("auto")
+    r = float(np.max(np.abs(La - Ly)) / np.max(np.abs(Ly)))
+    print(f"nonlinear 3D (y, z) pass vs y transform, m = {m}, {dtype}: rel_max {r:.2e}")
+    assert r <= (1e-12 if dtype == torch.float64 else 1e-5), r
+    g = orc.geom(body, dx, m * dx)
+    Lo = orc.nbb_force(g, orc.bb_alpha(3, 72e9, m * dx), chi.astype(float), u)
+    _check(La, Lo, u, plan, dx, dtype)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", DT)
 def test_nbb3d_rigid_rotation_zero_force(orc, dtype):
     body, fft, dx, m = (14, 17, 19), (32, 32, 32), 1e-3, 3
     chi = wl.random_mask(body, 49)
