@@ -455,6 +455,11 @@ struct MulOutRange {
     __device__ __forceinline__ auto ka_value() const { return m.ka_value(); }
     __host__ __device__ static constexpr int par3(int c) { return M::par3(c); }
     __host__ __device__ static constexpr DTerm dterm(int O, int J) { return M::dterm(O0 + O, J); }
+    // the transform forms of the last-axis pass
+    template <int O>
+    __host__ __device__ static constexpr uint32_t need() { return M::template need<O0 + O>(); }
+    template <int O, class TK, class TI>
+    __device__ __forceinline__ auto one(const TK* K, const TI* in) const { return m.template one<O0 + O>(K, in); }
 };
 template <class T, class M>
 struct is_nbb3_range : std::false_type {};
@@ -558,6 +563,24 @@ pd_status nbb_yz(pd_plan p, int out_off, hipStream_t st) { return nbb_yz_from<T,
 extern template pd_status nbb_yz<float>(pd_plan, int, hipStream_t);
 extern template pd_status nbb_yz<double>(pd_plan, int, hipStream_t);
 #endif
+
+// The 2D nonlinear chain's line correlation along y in groups of 2 outputs
+// (FP64), inputs in SA slots [0, 8), outputs to [out_off, out_off + 8).
+template <class T, int O0>
+pd_status nbb2_lines_from(pd_plan p, int out_off, hipStream_t st) {
+    constexpr int NO = MulNBB<T, 2>::NOUT;
+    if constexpr (O0 >= NO) {
+        return PD_OK;
+    } else {
+        constexpr int O1 = O0 + 2 < NO ? O0 + 2 : NO;
+        const Geo& g = p->geo;
+        Lines ln{(long)g.h1, (long)g.P2, g.saf, g.b2, g.n2, out_off + O0};
+        PD_TRY((launch_lastmul<T>(p, ln, MulOutRange<MulNBB<T, 2>, O0, O1>{}, SAp<T>(p),
+                                  reinterpret_cast<const T*>(p->taps), reinterpret_cast<const T*>(p->taps_d),
+                                  p->ntap, p->nct, p->oddmask, st)));
+        return nbb2_lines_from<T, O1>(p, out_off, st);
+    }
+}
 
 // Whether a chain takes the (y, z) direct pass: 3D plan tables, the default
 // kernel choice, and a multiplier that qualifies at the plan's radius.
@@ -1070,14 +1093,11 @@ pd_status plan_alloc(pd_plan p, hipStream_t st, const uint8_t* chiB_h, const uin
         capA = std::max(capA, D + 1 + nsym(D));
     }
     if (p->kern.model == PD_BB_NONLINEAR) {
-        // 8 inputs and 8 outputs in 2D, 13 and 13 in 3D (the (y, z) pass
-        // keeps the inputs and writes the outputs after them; the y
-        // transform path works in place)
-        capA = std::max(capA, 2 * D + 1 + nsym(D));
-        if (D == 3) {
-            capA = std::max(capA, 2 * (2 * D + 1 + nsym(D)));
-            capB = std::max(capB, 2 * D + 1 + nsym(D));
-        }
+        // 8 inputs and 8 outputs in 2D, 13 and 13 in 3D (the (y, z) pass and
+        // the grouped FP64 line correlation keep the inputs and write the
+        // outputs after them; the y transform path works in place)
+        capA = std::max(capA, 2 * (2 * D + 1 + nsym(D)));
+        if (D == 3) capB = std::max(capB, 2 * D + 1 + nsym(D));
     }
     p->saf_cap = capA;
     p->sbf_cap = std::max(capB, capC);
@@ -1375,6 +1395,17 @@ pd_status force_impl(pd_plan p, const T* u, const void* weight, T* L, T* W, hipS
                 if (use_yz<T, YzNBB<T, 0, nbb_yz_group<T>()>>(p) && p->saf_cap >= NI + NO) {
                     PD_TRY(launch_xfwd<T>(p, gg, SAp<T>(p), st));
                     PD_TRY(nbb_yz<T>(p, NI, st));
+                    return launch_xinv<T>(p, ff, SAp<T>(p) + (long)NI * p->geo.saf, st);
+                }
+            } else if constexpr (sizeof(T) == 8) {
+                // FP64 2D: the line correlation in four groups of 2 outputs
+                // (with more outputs per group the points of the 8 inputs and
+                // the outputs exceed the registers of two waves and spill),
+                // written after the inputs
+                constexpr int NI = MulNBB<T, 2>::NIN, NO = MulNBB<T, 2>::NOUT;
+                if (p->lastaxis == PD_LASTAXIS_AUTO && p->saf_cap >= NI + NO) {
+                    PD_TRY(launch_xfwd<T>(p, gg, SAp<T>(p), st));
+                    PD_TRY((nbb2_lines_from<T, 0>(p, NI, st)));
                     return launch_xinv<T>(p, ff, SAp<T>(p) + (long)NI * p->geo.saf, st);
                 }
             }

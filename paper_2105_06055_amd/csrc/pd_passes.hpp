@@ -716,6 +716,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 k_lastconv(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps, int nct) {
     static_assert(!M::RT_ODD && NT >= 2 && NT <= 5, "direct pass: compile-time parities, at most 4 neighbours");
     constexpr int NI = M::NIN, NO = M::NOUT;
+    constexpr bool LAZY = sizeof(T) == 8 && NI * NO > 16;
     const int lane = threadIdx.x & 63;
     const int l = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long li = (long)blockIdx.x * (blockDim.x >> 6) + l;
@@ -728,23 +729,30 @@ k_lastconv(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps, int nct) {
     lds_ptr<cx<T>> halo = as_lds(halo_s) + l * NI * 4;
     for (int ch = 0; ch < nch; ++ch) {
         const int z0 = ch * 256 + 4 * lane;
-        // this lane's 4 points of every input field, all loads issued together
-        cx<T> cur[NI][4];
-#pragma unroll
-        for (int f = 0; f < NI; ++f) {
+        // this lane's 4 points of an input field
+        auto load_in = [&](int f, cx<T>(&dst)[4]) {
             const cx<T>* src = S + f * ln.fstride + lic * ln.pitch + z0;
             if (ok && z0 + 3 < len) {
                 // 4 consecutive points; line starts are 16-point aligned
                 const cx2<T> p0 = reinterpret_cast<const cx2<T>*>(src)[0];
                 const cx2<T> p1 = reinterpret_cast<const cx2<T>*>(src)[1];
-                cur[f][0] = p0.a; cur[f][1] = p0.b; cur[f][2] = p1.a; cur[f][3] = p1.b;
+                dst[0] = p0.a; dst[1] = p0.b; dst[2] = p1.a; dst[3] = p1.b;
             } else {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    cur[f][q] = cx<T>{T(0), T(0)};
-                    if (ok && z0 + q < len) cur[f][q] = src[q];
+                    dst[q] = cx<T>{T(0), T(0)};
+                    if (ok && z0 + q < len) dst[q] = src[q];
                 }
             }
+        };
+        // every input's points loaded together, or (FP64 chains with many
+        // inputs and outputs, whose points and outputs would not fit in the
+        // registers of two waves) one input ahead of the arithmetic
+        cx<T> cur[LAZY ? 2 : NI][4];
+        if constexpr (LAZY) load_in(0, cur[0]);
+        else {
+#pragma unroll
+            for (int f = 0; f < NI; ++f) load_in(f, cur[f]);
         }
         const int e0 = z0 + 4;   // lane 63: the next chunk's first points
         const bool edge_lane = ok && lane == 63;
@@ -755,6 +763,9 @@ k_lastconv(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps, int nct) {
             for (int q = 0; q < 4; ++q) out[o][q] = cx<T>{T(0), T(0)};
 #pragma unroll
         for (int J = 0; J < NI; ++J) {
+            if constexpr (LAZY) {
+                if (J + 1 < NI) load_in(J + 1, cur[(J + 1) & 1]);
+            }
             // window of points z0 - 4 .. z0 + 7 of input J; lanes 0 and 63
             // load the points beyond the chunk ends themselves
             cx<T> edge[4];
@@ -770,7 +781,7 @@ k_lastconv(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps, int nct) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) edge[q] = halo[J * 4 + q];
             }
-            const cx<T>(&cj)[4] = cur[J];
+            const cx<T>(&cj)[4] = cur[LAZY ? (J & 1) : J];
             cx<T> w[12];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
