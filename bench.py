@@ -136,11 +136,15 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(pass_name):
-    """HBM bytes per launch of a pass from the committed rocprofv3 counter
-    summary (FETCH_SIZE, WRITE_SIZE, scaled by the 1 GiB copy calibration),
-    or None if there is none for these sources."""
-    p = os.path.join(ROOT, "profiles", "hbm_traffic_lps256_fp32_step.json")
+def measured_traffic(pass_name, path="auto"):
+    """HBM bytes per launch of a pass of the 256^3 FP32 step on a force path
+    ("auto" or "fft") from the committed rocprofv3 counter summary
+    (FETCH_SIZE, WRITE_SIZE, scaled by the 1 GiB copy calibration), or None
+    if there is none for these sources."""
+    name = {"auto": "hbm_traffic_lps256_fp32_step.json", "fft": "hbm_traffic_lps256_fp32_step_allaxes.json"}.get(path)
+    if name is None:
+        return None
+    p = os.path.join(ROOT, "profiles", name)
     try:
         with open(p) as fh:
             t = json.load(fh)
@@ -654,7 +658,7 @@ def main():
                             "fft": "transforms on all three axes"}[args.lastaxis]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom["name"]) if args.lastaxis == "auto" else None,
+                     "traffic": measured_traffic(dom["name"], args.lastaxis),
                      "kernel": dom["name"], "kernel_avg_ms": dom["avg_ms"],
                      "kernel_bytes": dom["bytes_per_launch"]},
         "cpu_baseline": cpu,
@@ -678,7 +682,9 @@ def main():
             "fp32_fft_all_axes": None if r32f is None else {
                 "step_Gnode_s": nodes / r32f["s_per_step"] / 1e9, "ms_per_step": r32f["s_per_step"] * 1e3,
                 "force_Gnode_s": nodes / r32f["s_per_force"] / 1e9, "force_ms": r32f["s_per_force"] * 1e3,
-                "finite": r32f["finite"], "roofline": pass_roofline(r32f["passes"], args.steps),
+                "finite": r32f["finite"],
+                "roofline": dict(pass_roofline(r32f["passes"], args.steps),
+                                 traffic=measured_traffic(pass_roofline(r32f["passes"], args.steps)["kernel"], "fft")),
                 "passes": r32f["passes"]},
             "m_crossover": mcross,
             "min_padding_x": minpad,
