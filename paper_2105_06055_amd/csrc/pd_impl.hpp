@@ -222,10 +222,10 @@ inline bool x_fast(const Geo& g) {
 }
 
 template <class T>
-int rows_per_block(pd_plan p) {
+int rows_per_block(pd_plan p, int want = 0) {
     const Geo& g = p->geo;
     const int Tc = g.Nc / 8;
-    int Lt = g.rad != 1 ? xrows_mixed<T>() : xrows<T>();
+    int Lt = g.rad != 1 ? xrows_mixed<T>() : (want > 0 ? want : xrows<T>());
     while (Lt > 1 && Tc * Lt > 512) Lt >>= 1;
     // few rows (2D plates, small blocks): fewer rows per block, down to two
     // (16-byte runs in the transposed stores), until the grid has a block for
@@ -641,8 +641,9 @@ pd_status launch_ytrans(pd_plan p, int F, int fb, hipStream_t st) {
 template <class T, class F, int LG>
 pd_status launch_xinv_lg(pd_plan p, const F& fin, const cx<T>* SA, hipStream_t st, cx<T>* SAout = nullptr) {
     const Geo& g = p->geo;
-    const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p);
-    if (x_block_fixed<T, LG>() > 0 && Tc * Lt != x_block_fixed<T, LG>()) return PD_EUNSUPPORTED;
+    constexpr int XF = x_block_fixed<T, LG, fin_xrows<F>::value>();
+    const int Tc = g.Nc / 8, Lt = rows_per_block<T>(p, fin_xrows<F>::value);
+    if (XF > 0 && Tc * Lt != XF) return PD_EUNSUPPORTED;
     dim3 grid((g.b2 + Lt - 1) / Lt, g.b3), block(Tc * Lt);
     size_t lds = ((size_t)Lt * row_pitch(g.Nc) + tw_lds_len(g.n1)) * sizeof(cx<T>);
     size_t red_lds = (size_t)((Tc * Lt + 63) / 64) * 8 * sizeof(double);
@@ -1118,7 +1119,8 @@ pd_status plan_alloc(pd_plan p, hipStream_t st, const uint8_t* chiB_h, const uin
     HIP_TRY(hipMalloc(&p->vtmp2, 2 * sizeof(T) * p->nb * D));
     p->bytes += 4 * sizeof(T) * p->nb * D;
     {
-        const int Lt = rows_per_block<T>(p);
+        // (the fewest rows per block any x pass takes: 8 for the Verlet c2r)
+        const int Lt = std::min(rows_per_block<T>(p), rows_per_block<T>(p, 8));
         long nblk = (long)((g.b2 + Lt - 1) / Lt) * g.b3;
         p->partials_cap = std::max(nblk * 8, 4096L);
         HIP_TRY(hipMalloc(&p->partials, sizeof(double) * p->partials_cap));

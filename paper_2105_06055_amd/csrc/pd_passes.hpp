@@ -134,11 +134,18 @@ __host__ __device__ constexpr int x_rn() {
     else if constexpr (LG < -1) return mix_R<LG>() == 3 ? 11 : (mix_R<LG>() == 5 ? 13 : 15);
     else return 16;
 }
-// Threads of an x-pass block: fixed for the compile-time lengths (xrows rows
-// of Nc / 8 threads), else the launch's block size.
-template <class T, int LG>
+// Rows per block an x-pass epilogue asks for on the power-of-two lengths
+// (F::XROWS; 0: xrows).
+template <class F, class = void>
+struct fin_xrows : std::integral_constant<int, 0> {};
+template <class F>
+struct fin_xrows<F, std::void_t<decltype(F::XROWS)>> : std::integral_constant<int, F::XROWS> {};
+
+// Threads of an x-pass block: fixed for the compile-time lengths (R rows, or
+// xrows, of Nc / 8 threads), else the launch's block size.
+template <class T, int LG, int R = 0>
 __host__ __device__ constexpr int x_block_fixed() {
-    if constexpr (LG > 0) return ((1 << LG) / 8) * xrows<T>();
+    if constexpr (LG > 0) return ((1 << LG) / 8) * (R > 0 ? R : xrows<T>());
     else if constexpr (LG < -1) return ((mix_R<LG>() << mix_lgM<LG>()) / 8) * xrows_mixed<T>();
     else return 0;
 }
@@ -352,6 +359,8 @@ template <class T, class M, int NIN, int NOUT>
 __device__ __forceinline__ void spectral_all(const M& mul, const T* __restrict__ B_g, int ntap, uint32_t oddmask,
                                              int j, int Tn, int n_last, const cx<T>* __restrict__ twl_g,
                                              const cx<T> (&vin)[NIN][8], cx<T> (&w)[NOUT][8]) {
+    // (w may be vin: each wavenumber's inputs are copied before its outputs
+    // are written)
     const uint32_t odd = M::RT_ODD ? oddmask : M::ODD;
     lds_ptr<const T> B = as_lds(B_g);
     lds_ptr<const cx<T>> twl = as_lds(twl_g);
@@ -448,19 +457,20 @@ __global__ void __launch_bounds__(256) k_lastmul(Lines ln, M mul, cx<T>* S, cons
 #pragma unroll
     for (int f = 0; f < NI; ++f) fft_line<-1>(vin[f], j, lgN, tw, 0, line);
     const T* Bt = tl + l * (M::NC * ntap);
-    if constexpr (has_all_out<M>::value) {
-        // one symbol evaluation per wavenumber for all outputs
-        cx<T> wa[NO][8];
-        spectral_all<T, M, NI, NO>(mul, Bt, ntap, oddmask, j, Tn, N, tw, vin, wa);
+    if constexpr (has_all_out<M>::value && NI == NO) {
+        // one symbol evaluation per wavenumber for all outputs, written over
+        // the inputs of that wavenumber (a separate output array next to the
+        // inputs spilled in FP64)
+        spectral_all<T, M, NI, NO>(mul, Bt, ntap, oddmask, j, Tn, N, tw, vin, vin);
         OutLoop<0, NO>::run([&](auto Oc) {
             constexpr int O = decltype(Oc)::value;
-            fft_line<1>(wa[O], j, lgN, tw, 0, line);
+            fft_line<1>(vin[O], j, lgN, tw, 0, line);
             if (ok) {
                 cx<T>* dst = S + (ln.out_off + O) * ln.fstride + li * ln.pitch;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const int p = j + Tn * q;
-                    if (p < ln.len) dst[p] = wa[O][q];
+                    if (p < ln.len) dst[p] = vin[O][q];
                 }
             }
         });
@@ -1276,7 +1286,8 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int NO = F::NOUT, NG = node_group<T>();
     const int Nc = x_len<LG>(g), lgNc = x_lg<LG>(g), Tc = Nc >> 3;
-    const int nthr = x_block_fixed<T, LG>() > 0 ? x_block_fixed<T, LG>() : (int)blockDim.x;
+    constexpr int XF = x_block_fixed<T, LG, fin_xrows<F>::value>();
+    const int nthr = XF > 0 ? XF : (int)blockDim.x;
     const int Lt = nthr / Tc;
     const int tid = threadIdx.x, j = tid % Tc, l = tid / Tc;
     const int z = blockIdx.y;
