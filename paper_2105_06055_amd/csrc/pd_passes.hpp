@@ -156,11 +156,9 @@ __host__ __device__ constexpr int x_block_fixed() {
 // in LDS after the Lt row buffers; every LDS use is fenced here.
 template <class T, int NF, int RN, int LG>
 __device__ __forceinline__ void r2c_store(const Geo& g, const T (&gv)[NF][RN], cx<T>* __restrict__ SA, cx<T>* lds,
-                                          int nthr, int nval) {
+                                          int nthr, int nval, int z, int y0) {
     const int Nc = x_len<LG>(g), lgNc = x_lg<LG>(g), Tc = Nc >> 3, Lt = nthr / Tc;
     const int tid = threadIdx.x, j = tid % Tc, l = tid / Tc;
-    const int z = blockIdx.y;
-    const int y0 = blockIdx.x * Lt;
     const bool rowok = y0 + l < g.b2;
     const int pitch = row_pitch(Nc);
     cx<T>* twn1 = lds + Lt * pitch;
@@ -299,7 +297,7 @@ __global__ void __launch_bounds__(512) k_xfwd(Geo g, G gen, cx<T>* __restrict__ 
     else run_gen(std::false_type{});
     // twiddles of length n1 in LDS after the rows; W_Nc^e = W_n1^(2e)
     stage_table(lds + Lt * row_pitch(Nc), twb + g.twn1, g.n1);
-    r2c_store<T, NF, RN, LG>(g, gv, SA, lds, nthr, nval);
+    r2c_store<T, NF, RN, LG>(g, gv, SA, lds, nthr, nval, z, y0);
 }
 
 // Output O of the spectral multiply for the 8 wavenumbers of thread j along
@@ -1290,8 +1288,15 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     const int nthr = XF > 0 ? XF : (int)blockDim.x;
     const int Lt = nthr / Tc;
     const int tid = threadIdx.x, j = tid % Tc, l = tid / Tc;
-    const int z = blockIdx.y;
-    const int y0 = blockIdx.x * Lt;
+    // block -> (row group, plane): consecutive row groups of a plane on one
+    // XCD (the hardware deals consecutive blocks to the 8 XCDs in turn), so
+    // that the two blocks sharing the 128-byte lines of an 8-row transposed
+    // run meet in one L2
+    const long nblk = (long)gridDim.x * gridDim.y, bq = nblk >> 3, br = nblk & 7;
+    const long lin = (long)blockIdx.y * gridDim.x + blockIdx.x, xcd = lin & 7, bk = lin >> 3;
+    const long lg = xcd < br ? xcd * (bq + 1) + bk : br * (bq + 1) + (xcd - br) * bq + bk;
+    const int z = (int)(lg / gridDim.x);
+    const int y0 = (int)(lg % gridDim.x) * Lt;
     const int y = y0 + l;
     const int pitch = row_pitch(Nc);
     cx<T>* row = lds + l * pitch;
@@ -1441,7 +1446,7 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     if constexpr (NCH > 0) {
         // the twiddles are still in LDS after the row buffers
         static_assert(F::NRED == 0, "a chained epilogue has no reductions");
-        r2c_store<T, NCH, RN, LG>(g, chv, SAout, lds, nthr, nval);
+        r2c_store<T, NCH, RN, LG>(g, chv, SAout, lds, nthr, nval, z, y0);
     }
     if constexpr (F::NRED > 0) {
         __syncthreads();
