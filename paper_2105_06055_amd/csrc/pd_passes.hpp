@@ -1288,13 +1288,14 @@ __global__ void __launch_bounds__(512) k_xinv(Geo g, F fin, const cx<T>* __restr
     const int nthr = XF > 0 ? XF : (int)blockDim.x;
     const int Lt = nthr / Tc;
     const int tid = threadIdx.x, j = tid % Tc, l = tid / Tc;
-    // block -> (row group, plane): consecutive row groups of a plane on one
-    // XCD (the hardware deals consecutive blocks to the 8 XCDs in turn), so
-    // that the two blocks sharing the 128-byte lines of an 8-row transposed
-    // run meet in one L2
+    // block -> (row group, plane): when a block's transposed runs are shorter
+    // than a 128-byte line (8 FP32 rows), consecutive row groups of a plane
+    // go to one XCD (the hardware deals consecutive blocks to the 8 XCDs in
+    // turn), so that the two blocks sharing a line meet in one L2
     const long nblk = (long)gridDim.x * gridDim.y, bq = nblk >> 3, br = nblk & 7;
     const long lin = (long)blockIdx.y * gridDim.x + blockIdx.x, xcd = lin & 7, bk = lin >> 3;
-    const long lg = xcd < br ? xcd * (bq + 1) + bk : br * (bq + 1) + (xcd - br) * bq + bk;
+    const bool part_lines = Lt * (int)sizeof(cx<T>) < 128;   // block-uniform
+    const long lg = !part_lines ? lin : (xcd < br ? xcd * (bq + 1) + bk : br * (bq + 1) + (xcd - br) * bq + bk);
     const int z = (int)(lg / gridDim.x);
     const int y0 = (int)(lg % gridDim.x) * Lt;
     const int y = y0 + l;
