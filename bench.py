@@ -473,8 +473,8 @@ def cpu_baseline(wl, budget_s=10.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=256, help="body nodes per edge")
     ap.add_argument("--fft", type=int, default=512, help="FFT grid per edge")
     ap.add_argument("--no-fp64", action="store_true")

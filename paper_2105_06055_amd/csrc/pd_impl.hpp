@@ -1730,12 +1730,19 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, doubl
         fA.theta = reinterpret_cast<T*>(p->theta);
         MulLPSB<T> mB{};
         mB.ka = T(p->ka);
-        FinLin<T, 3, 1, ENRED, true> fB{};
-        fB.c = ctx<T>(p);
-        fB.ka = T(p->ka); fB.u = u; fB.theta = reinterpret_cast<const T*>(p->theta);
-        fB.v = v; fB.F = F; fB.b = b; fB.c1 = c1; fB.rho = rho; fB.nanflag = nanflag;
-        fB.vh_in = vh_in; fB.vh_out = vh_out;
-        return run_lps<T>(p, gA, fA, mB, fB, st);
+        auto finish = [&](auto fB) -> pd_status {
+            fB.c = ctx<T>(p);
+            fB.ka = T(p->ka); fB.u = u; fB.theta = reinterpret_cast<const T*>(p->theta);
+            fB.v = v; fB.F = F; fB.b = b; fB.c1 = c1; fB.rho = rho; fB.nanflag = nanflag;
+            fB.vh_in = vh_in; fB.vh_out = vh_out;
+            return run_lps<T>(p, gA, fA, mB, fB, st);
+        };
+        // the inner steps of a call (no F read or written) with their own
+        // epilogue instance: without registers for F the force-stage c2r pass
+        // ran 10 % faster on the 256^3 FP32 step
+        if constexpr (!ENRED)
+            if (vh_in && vh_out) return finish(FinLin<T, 3, 1, false, true, true>{});
+        return finish(FinLin<T, 3, 1, ENRED, true>{});
     }
     auto go = [&](auto Dc) -> pd_status {
         constexpr int DD = decltype(Dc)::value;

@@ -1030,8 +1030,10 @@ struct FinThetaChain : FinTheta<T> {
 //   L_i = chi (conv_i + k_a theta g_i - G_ij u_j), conv_i including k_a a (*) chi theta.
 // MODE 0: write L;  MODE 1: Verlet finish (as FinBB);  MODE 2: CG operator
 // Ap = -chi_O L with partial sum p.Ap;  MODE 3: FP64 residual
-// r = chi_O (L + b) with partial |r|^2.
-template <class T, int D, int MODE, bool ENRED, bool LPS>
+// r = chi_O (L + b) with partial |r|^2.  INNER (MODE 1): an inner step of a
+// multi-step call, vh_in = vh_out = 1 at compile time, so the epilogue keeps
+// no registers for F and issues no load for it.
+template <class T, int D, int MODE, bool ENRED, bool LPS, bool INNER = false>
 struct FinLin {
     // Shared by bond-based (static G, LPS = false) and LPS for the solver / VV modes.
     static constexpr int NOUT = D;
@@ -1047,13 +1049,16 @@ struct FinLin {
     double* nanflag;   // MODE 1: set to 1 on a non-finite F' or v (null: no check)
     // MODE 1, steps inside a multi-step call: v holds the half-step velocity
     // vh = v + c1 F on entry (vh_in; F is not read) and receives
-    // vh' = v' + c1 F' on exit (vh_out; F is not written)
+    // vh' = v' + c1 F' on exit (vh_out; F is not written); both 1 when INNER
     int vh_in, vh_out;
+    static_assert(!INNER || (MODE == 1 && !ENRED), "INNER is a Verlet step without energy sums");
+    __host__ __device__ bool vhi() const { return INNER || vh_in; }
+    __host__ __device__ bool vho() const { return INNER || vh_out; }
     __host__ double nbytes() const {
         const double t = sizeof(T);
         double r = D * t + 1 + nsym(D) * t * c.edge_frac + (LPS ? t + D * t * c.edge_frac : 0.0);
         if (MODE == 0) r += D * t;
-        else if (MODE == 1) r += D * ((2 + (vh_in ? 0 : 1) + (vh_out ? 0 : 1)) * t + 1) + (b ? D * t : 0.0);
+        else if (MODE == 1) r += D * ((2 + (vhi() ? 0 : 1) + (vho() ? 0 : 1)) * t + 1) + (b ? D * t : 0.0);
         else if (MODE == 2) r += D * (t + 1);
         else r += D * (2 * t + 1);
         return r;
@@ -1061,7 +1066,7 @@ struct FinLin {
     static constexpr bool HAS_O = MODE >= 1;
     struct Ld {
         T u[D], G[nsym(D)], g[LPS ? D : 1], th;
-        T v[MODE == 1 ? D : 1], F[MODE == 1 ? D : 1], b[(MODE == 1 || MODE == 3) ? D : 1];
+        T v[MODE == 1 ? D : 1], F[(MODE == 1 && !INNER) ? D : 1], b[(MODE == 1 || MODE == 3) ? D : 1];
         uint8_t o[HAS_O ? D : 1];
         uint8_t chiB;
     };
@@ -1089,7 +1094,7 @@ struct FinLin {
             if constexpr (HAS_O) Q.o[d] = ldf(c.chiO + k, i);
             if constexpr (MODE == 1) {
                 Q.v[d] = ldf(v + k, i);
-                Q.F[d] = ldf((vh_in ? v : F) + k, i);   // with vh_in: a cache hit, unused
+                if constexpr (!INNER) Q.F[d] = ldf((vh_in ? v : F) + k, i);   // with vh_in: a cache hit, unused
             }
             if constexpr (MODE == 3) Q.b[d] = ldf(b + k, i);
         }
@@ -1116,10 +1121,11 @@ struct FinLin {
             } else if constexpr (MODE == 1) {
                 const T bk = b ? Q.b[a] : T(0);
                 T Fn = La + bk;
-                const T Fo = vh_in ? T(0) : Q.F[a];
+                T Fo = T(0);
+                if constexpr (!INNER) Fo = vh_in ? T(0) : Q.F[a];
                 const T vf = Q.v[a] + c1 * (Fo + Fn);
                 T vn = Q.o[a] ? vf : T(0);
-                if (vh_out) {
+                if (vho()) {
                     stf(v + k, i, Q.o[a] ? vn + c1 * Fn : T(0));
                 } else {
                     stf(v + k, i, vn);
