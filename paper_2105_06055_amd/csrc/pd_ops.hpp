@@ -137,8 +137,10 @@ struct NodeCtx {
 // VV = 1 first applies the embedded-constraint position update (Eq. 83)
 //     u <- chi_O [u + dt v + c2 F] + (1 - chi_O) w   (written back to u)
 // and, for integrity weights with failure on, lambda <- lambda && W <= Wc
-// (Eq. 63, irreversible), written back to lambda.
-template <class T, int D, int WK, bool WPHI, bool ENERGY, bool VV>
+// (Eq. 63, irreversible), written back to lambda.  INNER (VV): an inner step
+// of a multi-step call without prescribed displacements (vhalf = 1, w = null
+// at compile time): no loads or registers for F and w.
+template <class T, int D, int WK, bool WPHI, bool ENERGY, bool VV, bool INNER = false>
 struct GenU {
     static constexpr int NIN = D + (WPHI ? 1 : 0) + (ENERGY ? nsym(D) : 0);
     NodeCtx<T> c;
@@ -152,6 +154,7 @@ struct GenU {
     // VV: v holds the half-step velocity v + dt/(2 rho) F (a step inside a
     // multi-step call), so the position update needs no F
     int vhalf;
+    static_assert(!INNER || VV, "INNER is a Verlet position update");
     // algorithmic bytes moved per body node (reads + writes)
     __host__ double nbytes() const {
         const double t = sizeof(T);
@@ -159,13 +162,13 @@ struct GenU {
         if (WK == WK_LAMBDA) b += 1;
         if (WK == WK_SCALE) b += t;
         if (VV) {
-            b += D * ((vhalf ? 2 : 3) * t + 1) + (w ? D * t : 0.0);
+            b += D * ((INNER || vhalf ? 2 : 3) * t + 1) + (!INNER && w ? D * t : 0.0);
             if (WK == WK_LAMBDA && fail) b += t + 1;
         }
         return b;
     }
     struct Ld {
-        T u[D], v[VV ? D : 1], F[VV ? D : 1], w[VV ? D : 1];
+        T u[D], v[VV ? D : 1], F[(VV && !INNER) ? D : 1], w[(VV && !INNER) ? D : 1];
         uint8_t o[VV ? D : 1];
         uint8_t chiB, lam;
         T s, W;
@@ -181,8 +184,10 @@ struct GenU {
                 // no branch around a load (it would hold back the loads of the
                 // node group): with vhalf the F slot re-reads v (a cache hit)
                 // and is not used
-                L.F[d] = ldf((vhalf ? v : F) + k, i);
-                L.w[d] = ldf((w ? w : u) + k, i);
+                if constexpr (!INNER) {
+                    L.F[d] = ldf((vhalf ? v : F) + k, i);
+                    L.w[d] = ldf((w ? w : u) + k, i);
+                }
                 L.o[d] = ldf(c.chiO + k, i);
             }
         }
@@ -197,7 +202,11 @@ struct GenU {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             T x = L.u[d];
-            if constexpr (VV) {
+            if constexpr (VV && INNER) {
+                const T xn = x + dt * L.v[d];
+                x = L.o[d] ? xn : T(0);
+                stf(u + d * c.nb, i, x);
+            } else if constexpr (VV) {
                 const T Fs = vhalf ? T(0) : L.F[d];
                 const T xn = x + dt * L.v[d] + c2 * Fs;
                 x = L.o[d] ? xn : (w ? L.w[d] : T(0));

@@ -880,7 +880,8 @@ k_lastconv(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps, int nct) {
 // 3D multiplier other than the x one being the y and z parities here.
 //
 // A block takes one x-wavenumber, a tile of YT consecutive rows y (one per
-// thread) and a chunk of planes z, and sweeps the input planes in order.
+// thread) and a chunk of planes z, and sweeps the input planes in order
+// (upwards in even chunks, downwards in odd ones).
 // Each plane goes through LDS with MT halo rows on either side, so a thread
 // forms its y-neighbour sums and differences there; the plane's
 // contributions go into the accumulators of the 2 MT + 1 output planes it
@@ -1006,7 +1007,15 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
     // written once below)
     const bool halo = a.nyt > 1;
     const int z0 = zc * a.zc, z1 = min(a.b3, z0 + a.zc);
-    const T* __restrict__ tk = taps + ((long)kx * a.nct + M::C0) * NU;   // block-uniform
+    // odd chunks sweep their planes downwards, so that both chunks at a
+    // chunk boundary sweep the planes around it at the same time (both at
+    // their start or both at their end) and the halo planes they share are
+    // fetched from HBM once; a downward sweep takes the second taps table,
+    // whose components odd along z are negated (the plane at offset -b then
+    // takes the place of the one at +b)
+    const bool down = (zc & 1) != 0;   // block-uniform
+    const int dz = down ? -1 : 1;
+    const T* __restrict__ tk = taps + (down ? (long)a.h1 * a.nct * NU : 0L) + ((long)kx * a.nct + M::C0) * NU;
     const T ka = mul.ka_value();
     const long zs = (long)a.h1 * a.P2;
     const cx<T>* __restrict__ src = S + (long)a.in_off * a.saf + (long)kx * a.P2;
@@ -1059,15 +1068,15 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
         for (int J = 0; J < 2 * NI; ++J) lds[J * W + ph] = cx<T>{T(0), T(0)};
     }
 
-    const int zb = z0 - MT;               // first input plane of the sweep
-    const int nst = (z1 - z0) + 2 * MT;   // input planes swept
-    OutLoop<0, PF>::run([&](auto kc) { load(kc, zb + decltype(kc)::value); });
+    const int zb = down ? z1 - 1 + MT : z0 - MT;   // first input plane of the sweep
+    const int nst = (z1 - z0) + 2 * MT;            // input planes swept
+    OutLoop<0, PF>::run([&](auto kc) { load(kc, zb + dz * decltype(kc)::value); });
     for (int s0 = 0; s0 < nst; s0 += RR) {
         OutLoop<0, RR>::run([&](auto rc) {
             constexpr int rr = decltype(rc)::value, P = rr & 1, PS = rr % PF;
             const int s = s0 + rr;
             if (s >= nst) return;   // block-uniform
-            const int zi = zb + s;
+            const int zi = zb + dz * s;
             const bool act = zi >= 0 && zi < a.b3;   // block-uniform
             lds_ptr<cx<T>> row = lds + P * (NI * W);
             if (act) {
@@ -1083,7 +1092,7 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
             }
             // the set just stored takes plane zi + PF (PF planes of arithmetic
             // to arrive)
-            load(std::integral_constant<int, PS>{}, zi + PF);
+            load(std::integral_constant<int, PS>{}, zi + dz * PF);
             if (act) {
                 // per output and z-offset b, the terms of inputs J0 .. J1-1
                 // even (G = 0) and odd (G = 1) along z: q0 and q1 reach output
@@ -1168,8 +1177,8 @@ __global__ void __launch_bounds__(YT) k_yzconv(YZArgs a, M mul, cx<T>* S, const 
             }
             // output plane zi - MT has all its inputs
             constexpr int sd = (rr - MT + RR) % RR;
-            const int zo = zi - MT;
-            if (zo >= z0 && yin) {
+            const int zo = zi - dz * MT;
+            if (zo >= z0 && zo < z1 && yin) {
 #pragma unroll
                 for (int o = 0; o < NO; ++o) dst[o * a.saf + zo * zs] = acc[sd][o];
             }
