@@ -129,12 +129,15 @@ __global__ void k_taps_yz(int n1, int h1, int MT, int nu, int ns, const int* __r
 // (the paper allows P = C (*) 1 either by quadrature or by FFT, Sec. 3.1):
 //   stat_c(x) = sum_{o in S} chi_B(x + o) K_c(o)   on the body box,
 // stored node-major (stat[i * ncs + c]).
-// Also flags[i] = chiB[i] | 2 when the node's whole horizon lies in the body
-// (then stat equals the interior sums: every bond counted, same order).
+// Also the node flags: flags[i] = chiB[i] | 2 when the node's whole horizon
+// lies in the body (then stat equals the interior sums: every bond counted,
+// same order), and bit 2 + d = chi_Omega of component d (zero outside the
+// body), so that the passes read no separate chi_Omega bytes.
 template <class T>
 __global__ void k_static(int b1, int b2, int b3, int ns, const int* __restrict__ offs,
                          const double* __restrict__ kval, int ncs, const uint8_t* __restrict__ chiB,
-                         T* __restrict__ stat, uint8_t* __restrict__ flags, long nb) {
+                         const uint8_t* __restrict__ chiO, int D, T* __restrict__ stat,
+                         uint8_t* __restrict__ flags, long nb) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb) return;
     const int x = (int)(i % b1), y = (int)((i / b1) % b2), z = (int)(i / ((long)b1 * b2));
@@ -149,7 +152,9 @@ __global__ void k_static(int b1, int b2, int b3, int ns, const int* __restrict__
         for (int c = 0; c < ncs; ++c) acc[c] += kval[(long)s * ncs + c];
     }
     for (int c = 0; c < ncs; ++c) stat[i * ncs + c] = T(acc[c]);
-    flags[i] = (uint8_t)(chiB[i] ? (inside == ns ? 3 : 1) : 0);
+    int f = chiB[i] ? (inside == ns ? 3 : 1) : 0;
+    for (int d = 0; d < D; ++d) f |= (chiB[i] && chiO[d * nb + i]) ? (4 << d) : 0;
+    flags[i] = (uint8_t)f;
 }
 
 template <class T>
@@ -211,7 +216,6 @@ NodeCtx<T> ctx(pd_plan p) {
     NodeCtx<T> c;
     c.nb = p->nb;
     c.chiB = p->chiB;
-    c.chiO = p->chiO;
     c.stat = reinterpret_cast<const T*>(p->stat);
     c.ncs = p->ncs;
     c.stat_int = reinterpret_cast<const T*>(p->stat_int);
@@ -1005,13 +1009,14 @@ pd_status build_device_tables(pd_plan p, const std::vector<Bond>& S, hipStream_t
     uint8_t* flags = nullptr;
     HIP_TRY(hipMalloc(&flags, p->nb));
     hipLaunchKernelGGL((k_static<T>), dim3((unsigned)((p->nb + 255) / 256)), dim3(256), 0, st, g.b1, g.b2, g.b3, ns,
-                       p->offs_dev, p->kval_dev, ncs, p->chiB, reinterpret_cast<T*>(p->stat), flags, p->nb);
+                       p->offs_dev, p->kval_dev, ncs, p->chiB, p->chiO, D, reinterpret_cast<T*>(p->stat), flags,
+                       p->nb);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
         (void)hipFree(flags);
         return PD_EDEVICE;
     }
     (void)hipFree(p->chiB);
-    p->chiB = flags;   // body | interior << 1
+    p->chiB = flags;   // body | interior << 1 | chi_Omega[d] << (2 + d)
     {
         // nodes that read per-node static fields (everything not interior),
         // for the byte accounting of the passes

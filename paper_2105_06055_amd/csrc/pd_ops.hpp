@@ -39,9 +39,11 @@ enum { WK_NONE = 0, WK_LAMBDA = 1, WK_SCALE = 2 };
 // chiB[i] bit 0: the node is in the body; bit 1 (set only with bit 0): the
 // node's whole horizon lies in the body ("interior"), so its static fields
 // equal the constants stat_int (the same sums, in the same order) and are
-// read from that small cached table instead of the per-node arrays.  The
+// read from that small cached table instead of the per-node arrays; bit
+// 2 + d: component d is an unknown (chi_Omega, only on the body).  The
 // passes load chiB[i] ahead of the node's other loads and hand it to the
-// generators' and epilogues' load steps.
+// generators' and epilogues' load steps, which take chi_Omega from it.
+__device__ __forceinline__ uint8_t omega_bit(uint8_t cb, int d) { return (cb >> (2 + d)) & 1; }
 // Node index of the x passes, split into a block-uniform part (the start of
 // the block's run of body nodes) and a small per-thread part, so that every
 // field access is a uniform base plus a 32-bit offset: the addressing mode
@@ -94,8 +96,7 @@ __device__ __forceinline__ const T* adf(const T* p, Nd n) {
 template <class T>
 struct NodeCtx {
     long nb;                   // body nodes
-    const uint8_t* chiB;       // [nb] body | interior << 1
-    const uint8_t* chiO;       // [D][nb]
+    const uint8_t* chiB;       // [nb] body | interior << 1 | chi_Omega[d] << (2 + d)
     const T* stat;             // static fields [nb][ncs] (a node's fields together)
     int ncs;                   // static fields per node
     const T* stat_int;         // [ncs] values at interior nodes (device copy)
@@ -162,7 +163,7 @@ struct GenU {
         if (WK == WK_LAMBDA) b += 1;
         if (WK == WK_SCALE) b += t;
         if (VV) {
-            b += D * ((INNER || vhalf ? 2 : 3) * t + 1) + (!INNER && w ? D * t : 0.0);
+            b += D * ((INNER || vhalf ? 2 : 3) * t) + (!INNER && w ? D * t : 0.0);
             if (WK == WK_LAMBDA && fail) b += t + 1;
         }
         return b;
@@ -188,7 +189,7 @@ struct GenU {
                     L.F[d] = ldf((vhalf ? v : F) + k, i);
                     L.w[d] = ldf((w ? w : u) + k, i);
                 }
-                L.o[d] = ldf(c.chiO + k, i);
+                L.o[d] = omega_bit(cb, d);
             }
         }
         L.chiB = cb;
@@ -833,14 +834,14 @@ struct GenMasked {
     static constexpr int NIN = D;
     NodeCtx<T> c;
     const TR* r;
-    __host__ double nbytes() const { return D * (sizeof(TR) + 1.0); }
+    __host__ double nbytes() const { return D * double(sizeof(TR)) + 1.0; }
     struct Ld { TR r[D]; uint8_t o[D]; };
     __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const {
         Ld L;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             L.r[d] = ldf(r + d * c.nb, i);
-            L.o[d] = ldf(c.chiO + d * c.nb, i);
+            L.o[d] = omega_bit(cb, d);
         }
         return L;
     }
@@ -899,7 +900,7 @@ struct FinBB {
         double r = D * t + 1 + (WK == WK_LAMBDA ? 1.0 : 0.0) + (WK == WK_SCALE ? t : 0.0);
         if (!WPHI) r += nsym(D) * t * c.edge_frac;
         if (ENERGY) r += t;
-        if (VV) r += D * ((2 + (vh_in ? 0 : 1) + (vh_out ? 0 : 1)) * t + 1) + (b ? D * t : 0.0);
+        if (VV) r += D * ((2 + (vh_in ? 0 : 1) + (vh_out ? 0 : 1)) * t) + (b ? D * t : 0.0);
         else r += D * t;
         return r;
     }
@@ -921,7 +922,7 @@ struct FinBB {
                 const long k = d * c.nb;
                 Q.v[d] = ldf(v + k, i);
                 Q.F[d] = ldf((vh_in ? v : F) + k, i);   // with vh_in: a cache hit, unused
-                Q.o[d] = ldf(c.chiO + k, i);
+                Q.o[d] = omega_bit(cb, d);
             }
             if (b) {   // kernel-uniform
 #pragma unroll
@@ -1067,9 +1068,9 @@ struct FinLin {
         const double t = sizeof(T);
         double r = D * t + 1 + nsym(D) * t * c.edge_frac + (LPS ? t + D * t * c.edge_frac : 0.0);
         if (MODE == 0) r += D * t;
-        else if (MODE == 1) r += D * ((2 + (vhi() ? 0 : 1) + (vho() ? 0 : 1)) * t + 1) + (b ? D * t : 0.0);
-        else if (MODE == 2) r += D * (t + 1);
-        else r += D * (2 * t + 1);
+        else if (MODE == 1) r += D * ((2 + (vhi() ? 0 : 1) + (vho() ? 0 : 1)) * t) + (b ? D * t : 0.0);
+        else if (MODE == 2) r += D * t;
+        else r += D * (2 * t);
         return r;
     }
     static constexpr bool HAS_O = MODE >= 1;
@@ -1100,7 +1101,7 @@ struct FinLin {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             const long k = d * c.nb;
-            if constexpr (HAS_O) Q.o[d] = ldf(c.chiO + k, i);
+            if constexpr (HAS_O) Q.o[d] = omega_bit(cb, d);
             if constexpr (MODE == 1) {
                 Q.v[d] = ldf(v + k, i);
                 if constexpr (!INNER) Q.F[d] = ldf((vh_in ? v : F) + k, i);   // with vh_in: a cache hit, unused
@@ -1295,14 +1296,14 @@ struct FinPre {
     NodeCtx<T> c;
     const TR* r;
     TZ* z;
-    __host__ double nbytes() const { return D * (sizeof(TR) + sizeof(TZ) + 1.0); }
+    __host__ double nbytes() const { return D * double(sizeof(TR) + sizeof(TZ)) + 1.0; }
     struct Ld { TR r[D]; uint8_t o[D]; };
     __device__ __forceinline__ Ld load(Nd i, uint8_t cb) const {
         Ld Q;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             Q.r[d] = ldf(r + d * c.nb, i);
-            Q.o[d] = ldf(c.chiO + d * c.nb, i);
+            Q.o[d] = omega_bit(cb, d);
         }
         return Q;
     }
