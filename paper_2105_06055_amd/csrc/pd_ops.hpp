@@ -1042,7 +1042,10 @@ struct FinThetaChain : FinTheta<T> {
 // Ap = -chi_O L with partial sum p.Ap;  MODE 3: FP64 residual
 // r = chi_O (L + b) with partial |r|^2.  INNER (MODE 1): an inner step of a
 // multi-step call, vh_in = vh_out = 1 at compile time, so the epilogue keeps
-// no registers for F and issues no load for it.
+// no registers for F and issues no load for it; it also makes the next
+// step's position update u <- chi_O (u + dt vh') (the caller has no
+// prescribed displacement w), with u and vh' already in registers, so that
+// the next step's first pass only reads u.
 template <class T, int D, int MODE, bool ENRED, bool LPS, bool INNER = false>
 struct FinLin {
     // Shared by bond-based (static G, LPS = false) and LPS for the solver / VV modes.
@@ -1056,6 +1059,7 @@ struct FinLin {
     const T* u; const T* theta;
     T* L; T* v; T* F; const T* b;
     T c1, rho;
+    T* u_next; T dt;   // INNER: the position update of the next step (u_next = u)
     double* nanflag;   // MODE 1: set to 1 on a non-finite F' or v (null: no check)
     // MODE 1, steps inside a multi-step call: v holds the half-step velocity
     // vh = v + c1 F on entry (vh_in; F is not read) and receives
@@ -1068,7 +1072,7 @@ struct FinLin {
         const double t = sizeof(T);
         double r = D * t + 1 + nsym(D) * t * c.edge_frac + (LPS ? t + D * t * c.edge_frac : 0.0);
         if (MODE == 0) r += D * t;
-        else if (MODE == 1) r += D * ((2 + (vhi() ? 0 : 1) + (vho() ? 0 : 1)) * t) + (b ? D * t : 0.0);
+        else if (MODE == 1) r += D * ((2 + (vhi() ? 0 : 1) + (vho() ? 0 : 1) + (INNER ? 1 : 0)) * t) + (b ? D * t : 0.0);
         else if (MODE == 2) r += D * t;
         else r += D * (2 * t);
         return r;
@@ -1136,7 +1140,10 @@ struct FinLin {
                 const T vf = Q.v[a] + c1 * (Fo + Fn);
                 T vn = Q.o[a] ? vf : T(0);
                 if (vho()) {
-                    stf(v + k, i, Q.o[a] ? vn + c1 * Fn : T(0));
+                    const T vh2 = Q.o[a] ? vn + c1 * Fn : T(0);
+                    stf(v + k, i, vh2);
+                    // the same expression as the position update of GenU
+                    if constexpr (INNER) stf(u_next + k, i, Q.o[a] ? Q.u[a] + dt * vh2 : T(0));
                 } else {
                     stf(v + k, i, vn);
                     stf(F + k, i, Fn);
