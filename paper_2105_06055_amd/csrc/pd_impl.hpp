@@ -1352,21 +1352,31 @@ pd_status launch_energy(pd_plan p, const T* u, const uint8_t* lam, const T* s, T
 // pass (FinThetaChain): x transform of chi u -> SA 0..2, (y, z) dilatation
 // -> SA 4, c2r + theta + r2c -> SA 3, (y, z) force stage SA 0..3 -> SA
 // 4..6, c2r + epilogue.
+// have_spectra: slots 0 .. 2 already hold the chi u spectra (made by the
+// previous step's chained epilogue), so the first pass is skipped.  A
+// chained force-stage epilogue (FB::NCHAIN > 0) transforms its outputs into
+// slots 0 .. 2, which the force stage's (y, z) pass has finished reading.
+template <class T>
+bool lps_yz(pd_plan p) {
+    return use_yz<T, MulLPSA<T>>(p) && use_yz<T, MulLPSB<T>>(p);
+}
 template <class T, class GA, class FB>
 pd_status run_lps(pd_plan p, const GA& gA, const FinTheta<T>& fA, const MulLPSB<T>& mB, const FB& fB,
-                  hipStream_t st) {
-    if (use_yz<T, MulLPSA<T>>(p) && use_yz<T, MulLPSB<T>>(p)) {
+                  hipStream_t st, bool have_spectra = false) {
+    constexpr bool CHAIN = fin_chain_n<FB>::value > 0;
+    if (lps_yz<T>(p)) {
         const Geo& g = p->geo;
         cx<T>* SA = SAp<T>(p);
         if (p->saf_cap < 7) return PD_EINVAL;
-        PD_TRY(launch_xfwd<T>(p, gA, SA, st));
+        if (!have_spectra) PD_TRY(launch_xfwd<T>(p, gA, SA, st));
         PD_TRY((launch_yzconv<T, MulLPSA<T>>(p, MulLPSA<T>{}, 0, 4, st)));
         FinThetaChain<T> fc{};
         static_cast<FinTheta<T>&>(fc) = fA;
         PD_TRY(launch_xinv<T>(p, fc, SA + 4 * g.saf, st, SA + 3 * g.saf));
         PD_TRY((launch_yzconv<T, MulLPSB<T>>(p, mB, 0, 4, st)));
-        return launch_xinv<T>(p, fB, SA + 4 * g.saf, st);
+        return launch_xinv<T>(p, fB, SA + 4 * g.saf, st, CHAIN ? SA : nullptr);
     }
+    if (have_spectra || CHAIN) return PD_EINVAL;   // only the (y, z) path chains the steps
     PD_TRY(run_chain<T>(p, gA, MulLPSA<T>{}, fA, st, 0, 3));
     GenTheta<T> gB{};
     gB.c = ctx<T>(p);
@@ -1745,6 +1755,8 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, doubl
         fA.theta = reinterpret_cast<T*>(p->theta);
         MulLPSB<T> mB{};
         mB.ka = T(p->ka);
+        // whether the inner epilogue also transforms the next chi u (FP64)
+        constexpr bool CH = fin_chain_n<FinLin<T, 3, 1, false, true, true>>::value > 0;
         auto go = [&](auto gA, auto fB) -> pd_status {
             gA.c = ctx<T>(p);
             gA.u = u; gA.v = v; gA.F = F; gA.w = w; gA.dt = dt; gA.c2 = c2; gA.vhalf = vh_in;
@@ -1753,28 +1765,30 @@ pd_status verlet_one(pd_plan p, pd_state* S, const T* b, const T* w, T dt, doubl
             fB.v = v; fB.F = F; fB.b = b; fB.c1 = c1; fB.rho = rho; fB.nanflag = nanflag;
             fB.vh_in = vh_in; fB.vh_out = vh_out;
             fB.u_next = u; fB.dt = dt;
-            return run_lps<T>(p, gA, fA, mB, fB, st);
+            // after a chained step the chi u spectra of this step are in place
+            return run_lps<T>(p, gA, fA, mB, fB, st, CH && drifted != 0);
         };
         // The inner steps of a call (no F read or written; no prescribed
         // displacement) run generator and epilogue instances of their own,
         // with the half-step flags fixed at compile time and no registers or
-        // loads for F and w; the inner epilogue also makes the next step's
-        // position update, after which that step's first pass is the plain
-        // chi u transform (GenP).  On the 256^3 FP32 step the c2r pass of the
-        // force stage ran 10 % and the first x pass 6 % faster with the
-        // instances, and the moved update saves 12 B per node and step.
+        // loads for F and w.  The inner epilogue also makes the next step's
+        // position update (12 B per node and step less), after which that
+        // step's first pass is the plain chi u transform (GenP); in FP64, on
+        // the (y, z) path, the epilogue also transforms chi u, and the next
+        // step starts at its first (y, z) pass.  (256^3 FP32: the instances
+        // ran the force-stage c2r pass 10 % and the first x pass 6 % faster.)
         using GenG = GenU<T, 3, WK_NONE, false, false, true>;
         using FinG = FinLin<T, 3, 1, ENRED, true>;
         if constexpr (!ENRED) {
             using GenI = GenU<T, 3, WK_NONE, false, false, true, true>;
             using GenP = GenU<T, 3, WK_NONE, false, false, false>;
             using FinI = FinLin<T, 3, 1, false, true, true>;
-            const bool fi = vh_in && vh_out && !w;
+            const bool fi = vh_in && vh_out && !w && (!CH || lps_yz<T>(p));
             *drift_out = fi ? 1 : 0;
             if (drifted) return fi ? go(GenP{}, FinI{}) : go(GenP{}, FinG{});
             if (vh_in && !w) return fi ? go(GenI{}, FinI{}) : go(GenI{}, FinG{});
         }
-        if (drifted) return PD_EINVAL;   // not reached: only the inner epilogue drifts
+        if (drifted) return PD_EINVAL;   // not reached: only the inner epilogue chains
         return go(GenG{}, FinG{});
     }
     auto go = [&](auto Dc) -> pd_status {

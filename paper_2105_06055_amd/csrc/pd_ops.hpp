@@ -1044,8 +1044,12 @@ struct FinThetaChain : FinTheta<T> {
 // multi-step call, vh_in = vh_out = 1 at compile time, so the epilogue keeps
 // no registers for F and issues no load for it; it also makes the next
 // step's position update u <- chi_O (u + dt vh') (the caller has no
-// prescribed displacement w), with u and vh' already in registers, so that
-// the next step's first pass only reads u.
+// prescribed displacement w), with u and vh' already in registers; in FP64
+// it also hands chi u of the new positions to the pass's forward transform
+// (NCHAIN = D: the next step's first stage starts from those spectra).  In
+// FP32 the chained pass ran slower than the two passes it replaces (0.440
+// against 0.277 + 0.15 ms at 256^3), so there the next step's first pass is
+// the plain chi u transform.
 template <class T, int D, int MODE, bool ENRED, bool LPS, bool INNER = false>
 struct FinLin {
     // Shared by bond-based (static G, LPS = false) and LPS for the solver / VV modes.
@@ -1066,6 +1070,7 @@ struct FinLin {
     // vh' = v' + c1 F' on exit (vh_out; F is not written); both 1 when INNER
     int vh_in, vh_out;
     static_assert(!INNER || (MODE == 1 && !ENRED), "INNER is a Verlet step without energy sums");
+    static constexpr int NCHAIN = (INNER && sizeof(T) == 8) ? D : 0;
     __host__ __device__ bool vhi() const { return INNER || vh_in; }
     __host__ __device__ bool vho() const { return INNER || vh_out; }
     __host__ double nbytes() const {
@@ -1121,6 +1126,15 @@ struct FinLin {
         return Q;
     }
     __device__ __forceinline__ void fin(Nd i, const Ld& Q, const T (&val)[D], double* red) const {
+        T next[D];
+        apply<false>(i, Q, val, red, next);
+    }
+    __device__ __forceinline__ void fin_chain(Nd i, const Ld& Q, const T (&val)[D], double* red,
+                                              T (&next)[D]) const {
+        apply<true>(i, Q, val, red, next);
+    }
+    template <bool CH>
+    __device__ __forceinline__ void apply(Nd i, const Ld& Q, const T (&val)[D], double* red, T (&next)[D]) const {
         const T chi = Q.chiB ? T(1) : T(0);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -1142,8 +1156,13 @@ struct FinLin {
                 if (vho()) {
                     const T vh2 = Q.o[a] ? vn + c1 * Fn : T(0);
                     stf(v + k, i, vh2);
-                    // the same expression as the position update of GenU
-                    if constexpr (INNER) stf(u_next + k, i, Q.o[a] ? Q.u[a] + dt * vh2 : T(0));
+                    // the same expressions as the position update and the
+                    // chi u input of GenU
+                    if constexpr (INNER) {
+                        const T un = Q.o[a] ? Q.u[a] + dt * vh2 : T(0);
+                        stf(u_next + k, i, un);
+                        if constexpr (CH) next[a] = chi * un;
+                    }
                 } else {
                     stf(v + k, i, vn);
                     stf(F + k, i, Fn);
