@@ -118,6 +118,44 @@ def test_clamped_layer_and_body_force(orc):
     plan.close()
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("prescribed", [False, True])
+def test_lps_clamped_layer_body_force_multistep(orc, dtype, prescribed):
+    """3D LPS with a clamped layer (chi_Omega = 0 on the planes z < 3), a body
+    force and, optionally, a prescribed displacement on that layer, 40 steps
+    in one call, against the oracle.  Without w the inner steps make the next
+    step's position update in their velocity update (in FP64 also the next
+    chi u transform); with w every step takes the general instances."""
+    from paper_2105_06055_amd import binding
+    w = wl.block_voids_dynamics(nb=24, nfft=32, nvoids=3, steps=40, nu=0.3)
+    chiO = np.stack([w.chiB] * 3).astype(np.uint8)
+    chiO[:, :3] = 0
+    rng = np.random.default_rng(29)
+    b = rng.normal(0.0, 1e8, size=(3,) + w.body) * w.chiB
+    wv = None
+    if prescribed:
+        wv = np.zeros((3,) + w.body)
+        wv[:, :3] = rng.normal(0.0, 1e-7, size=(3, 3) + w.body[1:]) * w.chiB[:3]
+    plan = binding.Plan(w.fft, w.body, w.dx, w.delta, model="lps", E=w.E, nu=w.nu, rho=w.rho, chiB=w.chiB,
+                        chiO=chiO, dtype=dtype)
+    st = _state(w, dtype)
+    plan.verlet(st, w.dt, w.steps, b=_dev(b, dtype), w=None if wv is None else _dev(wv, dtype))
+    g = orc.geom(w.body, w.dx, w.delta)
+    mdl = orc.model("lps", E=w.E, nu=w.nu, rho=w.rho)
+    o = orc.verlet(g, mdl, w.chiB, chiO, w.u0, w.v0, w.dt, w.steps, b=b, w=wv)
+    tol = 1e-11 if dtype == torch.float64 else 1e-4
+    us, vs, Fs = (st[k].cpu().numpy() for k in ("u", "v", "F"))
+    eu, ev, eF = _rel(us, o["u"]), _rel(vs, o["v"]), _rel(Fs, o["F"])
+    print(f"LPS clamped, w={prescribed}, {dtype}: u {eu:.2e} v {ev:.2e} F {eF:.2e}")
+    assert eu <= tol and ev <= tol and eF <= tol, (eu, ev, eF)
+    assert np.array_equal(vs[:, :3], np.zeros_like(vs[:, :3]))
+    if prescribed:
+        assert np.array_equal(us[:, :3], wv[:, :3].astype(us.dtype))
+    else:
+        assert np.array_equal(us[:, :3], np.zeros_like(us[:, :3]))
+    plan.close()
+
+
 def test_fracture_subcase_damage_bit_exact(orc):
     """The 100x40 notched plate (FP64), the full 10,000 steps of the
     fracture configuration: integrity map and damage index bit-exact against
