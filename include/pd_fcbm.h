@@ -152,8 +152,9 @@ void pd_plan_destroy(pd_plan plan);
 pd_status pd_plan_query(pd_plan plan, pd_plan_info* info);
 
 /* Internal force density L (Eq. 57/58 for bond-based; Eq. 95-97 for LPS,
- * with the sign reading of the design doc; Eq. 101 with weights; Eq. 21-26 for
- * the nonlinear bond-based model).
+ * read with minus signs on the (C*chi) u, P u and (a*chi) u terms, which the
+ * derivations imply and which make an affine field's interior force vanish;
+ * Eq. 101 with weights; Eq. 21-26 for the nonlinear bond-based model).
  *   u      [dim][body]  displacement
  *   weight NULL for PD_WEIGHT_NONE; uint8 lambda [body] for INTEGRITY;
  *          dtype s [body] for SCALE

@@ -12,7 +12,7 @@
  * No FFT, no blocking, no fusion: every function is a loop over nodes and,
  * inside, a loop over the bonds of that node.
  *
- * Conventions (readings of the paper, each one documented in the design doc):
+ * Conventions (readings of the paper where it is silent or ambiguous):
  *  - grid box nb[0] x nb[1] x nb[2] (x fastest, nb[2] = 1 in 2D); fields are
  *    stored component-major: f[c*N + (z*ny + y)*nx + x], N = nx*ny*nz;
  *  - node spacing dx[d]; cell volume dV = prod dx[d] (unit thickness in 2D);
