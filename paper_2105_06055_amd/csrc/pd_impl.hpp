@@ -396,7 +396,8 @@ pd_status launch_lastmul(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, con
             path = 0;
     }
     if constexpr (!M::RT_ODD) {
-        if (path != 0 && p->lastaxis != PD_LASTAXIS_FFT_GENERIC && ln.N == 512 && ntap == 4) path = 1;
+        if (path != 0 && p->lastaxis != PD_LASTAXIS_FFT_GENERIC && (ln.N == 512 || ln.N == 256) && ntap == 4)
+            path = 1;
     }
     if (path == 0) {
         if constexpr (direct_ok) {
@@ -411,13 +412,20 @@ pd_status launch_lastmul(pd_plan p, const Lines& ln, const M& mul, cx<T>* S, con
         }
     } else if (path == 1) {
         if constexpr (!M::RT_ODD) {
-            constexpr int LG = 9, NT = 4;
-            const int Lw = 4;
-            const size_t lds = ((size_t)Lw * line_pitch(1 << LG) + tw_lds_len(1 << LG)) * sizeof(cx<T>);
-            if (lds > (size_t)p->max_lds) return PD_EUNSUPPORTED;
-            dim3 grid((unsigned)((ln.nlines + Lw - 1) / Lw)), block(Lw * ((1 << LG) / 8));
-            allow_lds(k_lastmul_f<T, M, LG, NT>, lds);
-            hipLaunchKernelGGL((k_lastmul_f<T, M, LG, NT>), grid, block, lds, st, ln, mul, S, taps, nct, TWp<T>(p));
+            // 512-point lines: 4 per block; 256-point lines (the 128^3 cube's
+            // preconditioner): 8 per block, two per wave
+            auto go = [&](auto lgc) -> pd_status {
+                constexpr int LG = decltype(lgc)::value, NT = 4;
+                const int Lw = 2048 >> LG;   // 256 threads
+                const size_t lds = ((size_t)Lw * line_pitch(1 << LG) + tw_lds_len(1 << LG)) * sizeof(cx<T>);
+                if (lds > (size_t)p->max_lds) return PD_EUNSUPPORTED;
+                dim3 grid((unsigned)((ln.nlines + Lw - 1) / Lw)), block(Lw * ((1 << LG) / 8));
+                allow_lds(k_lastmul_f<T, M, LG, NT>, lds);
+                hipLaunchKernelGGL((k_lastmul_f<T, M, LG, NT>), grid, block, lds, st, ln, mul, S, taps, nct,
+                                   TWp<T>(p));
+                return PD_OK;
+            };
+            PD_TRY(ln.N == 512 ? go(std::integral_constant<int, 9>{}) : go(std::integral_constant<int, 8>{}));
         }
     } else {
         int Lw = std::max(1, 256 / Tn);

@@ -563,16 +563,19 @@ struct QLoop<NQ, NQ> {
     __device__ __forceinline__ static void run(F&&) {}
 };
 
-// block Lw*(N/8) (Lw lines), LDS Lw*line_pitch(N) + N complex.
+// block Lw*(N/8) (Lw lines), LDS Lw*line_pitch(N) + N complex.  From 512
+// points on a line fills whole waves and its taps are wave-uniform (scalar
+// loads); a 256-point line is half a wave, and the taps are per-lane loads.
 template <class T, class M, int LG, int NT>
 __global__ void __launch_bounds__(256) k_lastmul_f(Lines ln, M mul, cx<T>* S, const T* __restrict__ taps, int nct,
                                                    const cx<T>* __restrict__ twb) {
-    static_assert(LG >= 9 && NT >= 1 && !M::RT_ODD, "specialised pass needs N >= 512");
+    static_assert(LG >= 8 && NT >= 1 && !M::RT_ODD, "specialised pass needs N >= 256");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int NI = M::NIN, NO = M::NOUT, N = 1 << LG, Tn = N >> 3;
     const int tid = threadIdx.x, j = tid & (Tn - 1);
-    const int l = __builtin_amdgcn_readfirstlane(tid >> (LG - 3));   // wave-uniform line slot
+    // line slot: wave-uniform from 512 points on
+    const int l = LG >= 9 ? __builtin_amdgcn_readfirstlane(tid >> (LG - 3)) : (tid >> (LG - 3));
     const int Lw = blockDim.x >> (LG - 3);
     const long li = (long)blockIdx.x * Lw + l;
     const bool ok = li < ln.nlines;
