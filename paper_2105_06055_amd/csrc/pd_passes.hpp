@@ -635,10 +635,19 @@ __global__ void __launch_bounds__(256) k_lastmul_f(Lines ln, M mul, cx<T>* S, co
             cx<T> a[NI];
 #pragma unroll
             for (int f = 0; f < NI; ++f) a[f] = vin[f][Q];
-            OutLoop<0, NO>::run([&](auto Oc) {
-                constexpr int O = decltype(Oc)::value;
-                w[O][Q] = mul.template one<O>(K, a);
-            });
+            if constexpr (has_all_out<M>::value) {
+                // all outputs from one evaluation (the preconditioner's 3x3
+                // inverse once per wavenumber)
+                cx<T> o[NO];
+                mul.all(K, a, o);
+#pragma unroll
+                for (int O = 0; O < NO; ++O) w[O][Q] = o[O];
+            } else {
+                OutLoop<0, NO>::run([&](auto Oc) {
+                    constexpr int O = decltype(Oc)::value;
+                    w[O][Q] = mul.template one<O>(K, a);
+                });
+            }
         });
 #pragma unroll
         for (int O = 0; O < NO; ++O) {
